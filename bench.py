@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Benchmark of the CS-WGS hologram hot path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--form fp32] [--no-cpu-baseline]
+
+One step is one complete hologram: RS start, 30 CS-WGS iterations (forward
+projection on a 1/16 random pixel subset for iterations 1..29, on all pixels
+for iteration 30, weight update, back-propagation) and the final full-grid
+phase, for a 1152 x 1152 SLM and 100 spots.  Spot clouds are synthetic
+(seeded uniform clouds, workload/spots.py) and already resident in HBM when
+the timed region starts; each step uses a different cloud and seed.
+
+Printed: one JSON line with holograms/s, the roofline of the dominant kernel
+measured live with HIP events on its stream, the accuracy of the seed-0
+hologram against the stored FP64 oracle result, and the FP64 oracle timed
+on the host cores on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "holograms/s at M=1152^2,N=100 CS-WGS (e,u vs FP64 oracle); % FP32 roofline"
+WORKLOAD = "cswgs_1152x1152_n100_i30_c16"
+W = H = 1152
+N = 100
+ITER = 30
+COMP = 1.0 / 16
+CLOUDS = 10
+
+# Algorithmic work of one (pixel, spot) term, FP32 flops (sincos counted
+# separately): back-propagation 3 FMA for the phase + 2 FMA for the
+# amplitude-weighted sum = 10; forward 3 FMA-equivalents for the phase +
+# 4 FMA for the complex accumulate = 14.  The fused kernel does one of each
+# per (pixel, spot) pair.
+FLOPS_BACK = 10
+FLOPS_FWD = 14
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (256 CU, 2.4 GHz, packed FMA)
+
+
+def cpu_baseline(grid, optics, spots, seed):
+    """Times the FP64 oracle (single thread) on a bounded sample of one
+    hologram: one full-grid back-propagation, one full-grid forward
+    projection and two compressed iterations; scales to a whole hologram
+    (2 full back-propagations + 1 full forward + 29 compressed iterations)."""
+    import numpy as np
+    import oracle
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        limiter = None
+    w = np.ones(spots.n)
+    th = oracle.theta0(seed, spots.n)
+    t0 = time.perf_counter()
+    Phi = oracle.backward(grid, optics, spots, w, th)
+    t_fb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    V = oracle.forward(grid, optics, spots, Phi)
+    t_ff = time.perf_counter() - t0
+    t_sub = []
+    for j in (1, 2):
+        t0 = time.perf_counter()
+        p = oracle.sampler.subset(grid.M, seed, j, COMP)
+        Phi_p = oracle.backward(grid, optics, spots, w, th, p)
+        V = oracle.forward(grid, optics, spots, Phi_p, p)
+        w, th = oracle.update(w, V)
+        t_sub.append(time.perf_counter() - t0)
+    if limiter is not None:
+        limiter.unregister()
+    per_holo = 2 * t_fb + t_ff + (ITER - 1) * (sum(t_sub) / len(t_sub))
+    return {
+        "value": 1.0 / per_holo, "unit": "holograms/s", "cores": 1, "kind": "oracle",
+        "sample": (f"1 full back-propagation ({t_fb:.1f} s), 1 full forward ({t_ff:.1f} s) and "
+                   f"2 compressed iterations ({sum(t_sub):.1f} s) of the seed-{seed} hologram, "
+                   f"scaled to 2 full back + 1 full forward + {ITER - 1} compressed iterations "
+                   f"= {per_holo:.1f} s per hologram"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--form", default="fp32", choices=["fp32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the hologram "
+              "path has no multi-GPU form in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2003_05293_amd as hg
+    from workload import Grid, OPTICS, spot_cloud
+
+    grid = Grid(W, H)
+    clouds = [spot_cloud(s, N, grid) for s in range(CLOUDS)]
+    spots_dev = [torch.tensor(np.stack([c.x_mm, c.y_mm, c.z_mm, c.amp]), dtype=torch.float64,
+                              device="cuda") for c in clouds]
+    phis = [torch.empty(W * H, dtype=torch.float32, device="cuda") for _ in range(CLOUDS)]
+    stream = torch.cuda.current_stream()
+
+    def step(k):
+        s = k % CLOUDS
+        hg.cswgs_device(grid, OPTICS, spots_dev[s], ITER, COMP, s, phi=phis[s], stream=stream,
+                        precision=args.form)
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done ({args.warmup} holograms)", file=sys.stderr, flush=True)
+
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    start.record(stream)
+    for k in range(args.steps):
+        step(k)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_per_step = start.elapsed_time(stop) / args.steps
+    value = 1000.0 / ms_per_step
+    print(f"[bench] timed {args.steps} holograms: {ms_per_step:.4f} ms each", file=sys.stderr,
+          flush=True)
+
+    # Dominant kernel, timed live with HIP events on the stream it runs on.
+    hg.timing_reset()
+    hg.timing_enable(True)
+    for k in range(args.steps):
+        step(k)
+    torch.cuda.synchronize()
+    hg.timing_enable(False)
+    kern = {}
+    for name in ("k_iter_subset", "k_iter_full", "k_update", "k_backprop_phi"):
+        ms, cnt = hg.timing_read(name)
+        kern[name] = {"total_ms": ms, "launches": cnt, "avg_us": 1000.0 * ms / max(cnt, 1)}
+    dominant = max(kern, key=lambda k: kern[k]["total_ms"])
+    m = math.ceil(COMP * W * H)
+    pixels = {"k_iter_subset": m, "k_iter_full": W * H}
+    if dominant in pixels:
+        flops = pixels[dominant] * N * (FLOPS_BACK + FLOPS_FWD)
+    else:
+        flops = W * H * N * FLOPS_BACK
+    achieved = flops / (kern[dominant]["avg_us"] * 1e-6) / 1e12
+    roofline = {
+        "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+        "kernel": dominant, "avg_launch_us": round(kern[dominant]["avg_us"], 3),
+        "flops_per_launch": flops,
+        "kernels": {k: {"avg_us": round(v["avg_us"], 3),
+                        "launches_per_hologram": v["launches"] / args.steps}
+                    for k, v in kern.items()},
+    }
+
+    # Accuracy of the seed-0 hologram against the stored FP64 oracle run.
+    accuracy = None
+    gold = os.path.join(ROOT, "tests", "golden", "cswgs_1152x1152_n100_i30_c16_seed0.json")
+    step(0)
+    e, u, _ = hg.metrics(grid, OPTICS, clouds[0], phis[0])
+    accuracy = {"e": e, "u": u}
+    if os.path.exists(gold):
+        with open(gold) as f:
+            gd = json.load(f)
+        accuracy.update({"e_oracle": gd["e"], "u_oracle": gd["u"],
+                         "e_abs_err": abs(e - gd["e"]), "u_abs_err": abs(u - gd["u"])})
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the FP64 oracle on a sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(grid, OPTICS, clouds[0], 0)
+
+    line = {
+        "metric": METRIC, "value": round(value, 3), "unit": "holograms/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic", "wall_s": round(wall, 4),
+        "config": {"workload": WORKLOAD, "W": W, "H": H, "N": N, "iterations": ITER,
+                   "compression": COMP, "form": args.form, "clouds": CLOUDS,
+                   "spots": "resident in HBM"},
+        "roofline": roofline, "accuracy": accuracy, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,226 @@
+/*
+ * hg.h - C ABI of libhg: phase-only holograms of 3-D spot clouds on AMD
+ * MI355X (gfx950) by random superposition (RS), weighted Gerchberg-Saxton
+ * (WGS) and compressed-sensing WGS (CS-WGS).
+ *
+ * Method: Pozzi & Mapelli, "Real time computer generation of
+ * three-dimensional point cloud holograms through GPU implementation of
+ * compressed sensing Gerchberg-Saxton algorithm" (arXiv 2003.05293),
+ * section 2, eqs. (1)-(7).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Pixel grid (paper, GPU implementation section, fixed SLM parameters):
+ *   W columns, H rows, square pixels of pitch `pitch_mm`; pixel (i, j) sits at
+ *   x'_i = (i - (W-1)/2) * pitch, y'_j = (j - (H-1)/2) * pitch and has flat
+ *   index p = j*W + i.  Every full-grid phase buffer is float32 [H][W]
+ *   row-major, radians in (-pi, pi].
+ * Spot phase phi_n (eq. 2), back-propagation (eq. 1), forward projection
+ *   (eq. 3, read with the + sign and as a mean over the pixel set with
+ *   uniform illumination), weight update (eqs. 4-6) and metrics (eq. 7)
+ *   are as in the paper.
+ * Random draws: theta_n^0 and the pixel subsets of the compressed
+ *   iterations come from the 64-bit `seed` through Philox4x64-10 and a keyed
+ *   six-round Feistel permutation of [0, W*H) (one random pixel order at
+ *   start-up, as in the paper's compressed-sensing subsection; iteration j
+ *   uses the window of m = ceil(c*W*H) consecutive entries starting at
+ *   (j-1)*m, wrapping at W*H).
+ *
+ * Ownership: the caller owns every buffer.  Host arrays are read during the
+ *   call only.  Device buffers (`*_dev`) are caller allocations on the
+ *   current HIP device (for example torch tensors' data_ptr()).  `stream`
+ *   is a hipStream_t (NULL = the default stream); work is enqueued on it in
+ *   order.  The library keeps per-stream scratch memory that it allocates
+ *   on first use and reuses; hg_release() frees it.  Two calls that overlap
+ *   on different streams use different scratch and do not race.
+ *
+ * Errors: every call validates all arguments before launching anything.
+ *   On failure it returns a non-zero hg_status, writes no output, and sets a
+ *   thread-local message readable with hg_last_error().  No C++ exception
+ *   crosses this interface.
+ *
+ * Limits: 1 <= W, H <= 8192; 1 <= N <= HG_MAX_SPOTS; 0 <= iterations <=
+ *   HG_MAX_ITERATIONS; 0 < compression <= 1; pitch, wavelength, focal length
+ *   positive and finite; coordinates finite; amplitudes positive and finite.
+ */
+#ifndef HG_H
+#define HG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HG_MAX_SPOTS 4096
+#define HG_MAX_ITERATIONS 100000
+
+typedef enum hg_status {
+  HG_OK = 0,
+  HG_EINVAL = 1,   /* an argument is out of range, NULL or not finite        */
+  HG_ENOMEM = 2,   /* device or pinned host allocation failed                */
+  HG_EBUSY = 3,    /* engine: no slot or memory free for the request now     */
+  HG_ENUMERIC = 4, /* a spot field came out zero or not finite               */
+  HG_EDEVICE = 5   /* a HIP runtime call or kernel launch failed             */
+} hg_status;
+
+/* SLM pixel grid (paper: pixel coordinates x', y' uploaded once). */
+typedef struct hg_grid {
+  int32_t W;        /* columns (x')                                        */
+  int32_t H;        /* rows (y')                                           */
+  double pitch_mm;  /* pixel pitch                                         */
+} hg_grid;
+
+/* Optics of eq. (2): wavelength lambda and focal length f, in mm. */
+typedef struct hg_optics {
+  double lambda_mm;
+  double focal_mm;
+} hg_optics;
+
+/* N target spots X_n = (x_n, y_n, z_n) in mm and target amplitudes a_n^0
+ * (relative intensities |a_n^0|^2), section 2.  Four host arrays of n
+ * doubles each. */
+typedef struct hg_spots {
+  int32_t n;
+  const double *x_mm;
+  const double *y_mm;
+  const double *z_mm;
+  const double *amp;
+} hg_spots;
+
+/* Arithmetic of the iteration kernels (low bits of hg_params.flags and of
+ * the flags argument of the single-step calls). */
+#define HG_PREC_FP32 0u   /* FP32 phases, sincos and sums                  */
+#define HG_PREC_MIXED 1u  /* FP16-packed complex back-prop terms with FP32
+                             accumulation, compensated FP32 forward sums   */
+#define HG_PREC_MASK 0xffu
+/* hg_params.flags: the four hg_spots arrays are device pointers (already
+ * in HBM) instead of host pointers.  Their values are then checked on the
+ * device; a non-finite coordinate or a non-positive amplitude is reported
+ * as HG_EINVAL by the next blocking call on the stream. */
+#define HG_SPOTS_ON_DEVICE 0x100u
+
+/* Extended parameters of hg_cswgs_ex. */
+typedef struct hg_params {
+  int32_t iterations;    /* I >= 0                                          */
+  double compression;    /* c in (0, 1]; 1 gives WGS                        */
+  uint64_t seed;         /* theta^0 and subsets                             */
+  uint32_t flags;        /* HG_PREC_*                                       */
+  double *trace_V;       /* NULL, or host [iterations][N][2] doubles: the
+                            spot field V^j (re, im) of every iteration j    */
+} hg_params;
+
+/* ---------------------------------------------------------------------- */
+/* Algorithms                                                             */
+/* ---------------------------------------------------------------------- */
+
+/* RS (section 2, eq. 1 with random theta_n^0 and w_n = 1).  Writes the
+ * hologram Phi^0 to phi_dev (float32 [H][W], radians).  Asynchronous. */
+hg_status hg_rs(const hg_grid *grid, const hg_optics *optics,
+                const hg_spots *spots, uint64_t seed, float *phi_dev,
+                void *stream);
+
+/* WGS (section 2, eqs. 1-6): RS, then `iterations` iterations of forward
+ * projection over all pixels, weight update and back-propagation.
+ * iterations = 0 gives RS.  Writes Phi^I to phi_dev.  Asynchronous. */
+hg_status hg_wgs(const hg_grid *grid, const hg_optics *optics,
+                 const hg_spots *spots, int32_t iterations, uint64_t seed,
+                 float *phi_dev, void *stream);
+
+/* CS-WGS (section 2, compressed variant; GPU section, compressed sensing):
+ * as WGS, but the forward sum of iteration j < I runs over the random subset
+ * Omega^j of m = ceil(c*W*H) pixels, and the phase is computed only where
+ * the next forward step reads it; iteration I and the output Phi^I use all
+ * pixels.  compression = 1 gives WGS (same sets, other summation order).
+ * Asynchronous. */
+hg_status hg_cswgs(const hg_grid *grid, const hg_optics *optics,
+                   const hg_spots *spots, int32_t iterations,
+                   double compression, uint64_t seed, float *phi_dev,
+                   void *stream);
+
+/* CS-WGS with the precision flag and an optional per-iteration trace of the
+ * spot fields.  With trace_V != NULL the call blocks until the trace is on
+ * the host; otherwise it is asynchronous. */
+hg_status hg_cswgs_ex(const hg_grid *grid, const hg_optics *optics,
+                      const hg_spots *spots, const hg_params *params,
+                      float *phi_dev, void *stream);
+
+/* Efficiency and uniformity of a hologram (section 2, last paragraph, and
+ * eq. 7), in FP64: V*_n = mean over all pixels of e^{i(Phi - phi_n)},
+ * I_n = |V*_n|^2, e = sum_n I_n, u = 1 - (max I - min I)/(max I + min I).
+ * phi_dev: float32 [H][W].  intensities: NULL or host array of N doubles.
+ * Blocks until the results are on the host. */
+hg_status hg_metrics(const hg_grid *grid, const hg_optics *optics,
+                     const hg_spots *spots, const float *phi_dev, double *e,
+                     double *u, double *intensities, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Single steps, for testing each kernel against the oracle               */
+/* ---------------------------------------------------------------------- */
+
+/* theta_n^0 (radians, FP64) for n < count, computed on the device.  Blocks. */
+hg_status hg_theta0(uint64_t seed, int32_t count, double *out_host);
+
+/* Pixel indices of Omega^j (j >= 1) for compression c: writes m = ceil(c*W*H)
+ * int32 indices, in order, to idx_dev (capacity >= m) and m to *m_out.
+ * Blocks until *m_out is set. */
+hg_status hg_subset(const hg_grid *grid, uint64_t seed, int32_t j,
+                    double compression, int32_t *idx_dev, int32_t *m_out,
+                    void *stream);
+
+/* Forward projection (eq. 3) of a given hologram: V_n = mean over the pixel
+ * set of e^{i(Phi(p) - phi_n(p))}.  phi_dev: float32 [H][W].  idx_dev: NULL
+ * for all pixels, else m device int32 pixel indices.  V_out: host, 2N
+ * doubles (re, im).  flags: HG_PREC_*.  Blocks. */
+hg_status hg_forward(const hg_grid *grid, const hg_optics *optics,
+                     const hg_spots *spots, const float *phi_dev,
+                     const int32_t *idx_dev, int32_t m, uint32_t flags,
+                     double *V_out, void *stream);
+
+/* Back-propagation (eq. 1) with given weights w_n and phases theta_n (host,
+ * N doubles each; a_n = w_n a_n^0): writes Phi at the pixel set to phi_dev,
+ * compact: phi_dev[q] = Phi(idx[q]) for q < m, or phi_dev[p] for all p when
+ * idx_dev is NULL.  flags: HG_PREC_*.  Asynchronous. */
+hg_status hg_backward(const hg_grid *grid, const hg_optics *optics,
+                      const hg_spots *spots, const double *w,
+                      const double *theta, const int32_t *idx_dev, int32_t m,
+                      uint32_t flags, float *phi_dev, void *stream);
+
+/* One fused iteration body: back-propagation with (w, theta) on the pixel
+ * set immediately followed by the forward projection over the same set
+ * (eqs. 1 and 3), returning V (host, 2N doubles).  This is the kernel the
+ * iteration loop runs.  Blocks. */
+hg_status hg_step(const hg_grid *grid, const hg_optics *optics,
+                  const hg_spots *spots, const double *w, const double *theta,
+                  const int32_t *idx_dev, int32_t m, uint32_t flags,
+                  double *V_out, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Library state                                                          */
+/* ---------------------------------------------------------------------- */
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *hg_last_error(void);
+
+/* Frees all scratch memory after synchronising the streams that used it. */
+hg_status hg_release(void);
+
+/* Kernel timing for benchmarks.  While enabled, every launch of the
+ * iteration kernels is bracketed by two HIP events recorded on the stream it
+ * runs on.  hg_timing_read synchronises those events and returns, for the
+ * kernel family `name` ("k_iter_subset", "k_iter_full", "k_update",
+ * "k_backprop_phi"), the summed
+ * duration in ms and the number of launches since the last reset. */
+hg_status hg_timing_enable(int on);
+hg_status hg_timing_reset(void);
+hg_status hg_timing_read(const char *name, double *total_ms, int64_t *launches);
+
+/* Library version string. */
+const char *hg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HG_H */

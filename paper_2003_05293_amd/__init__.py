@@ -1,0 +1,362 @@
+"""Python binding of libhg (include/hg.h): RS, WGS and CS-WGS holograms of
+3-D spot clouds on AMD MI355X.
+
+This module only marshals arguments: it converts grid/optics/spot objects
+to the C structs, passes device pointers of torch tensors and the current
+HIP stream, and turns non-zero status codes into HGError.  Every step of
+the computation runs in the library's HIP kernels.  If libhg.so has not been
+built, every call raises: there is no fallback path.
+
+Grid, optics and spot arguments are duck-typed: any object with
+  grid:   W, H, pitch_mm
+  optics: lambda_mm, focal_mm
+  spots:  x_mm, y_mm, z_mm, amp  (array-likes of equal length)
+works (for example the classes of the workload package).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+__all__ = [
+    "HGError", "lib_path", "load", "version", "last_error", "release",
+    "rs", "wgs", "cswgs", "metrics", "theta0", "subset", "forward", "backward", "step",
+    "PREC_FP32", "PREC_MIXED", "cswgs_device", "timing_enable", "timing_reset", "timing_read",
+]
+
+PREC_FP32 = 0
+PREC_MIXED = 1
+SPOTS_ON_DEVICE = 0x100
+_PREC = {"fp32": PREC_FP32, "mixed": PREC_MIXED}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libhg.so")
+_lib = None
+
+STATUS = {0: "HG_OK", 1: "HG_EINVAL", 2: "HG_ENOMEM", 3: "HG_EBUSY", 4: "HG_ENUMERIC",
+          5: "HG_EDEVICE"}
+
+
+class HGError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("W", ctypes.c_int32), ("H", ctypes.c_int32), ("pitch_mm", ctypes.c_double)]
+
+
+class _Optics(ctypes.Structure):
+    _fields_ = [("lambda_mm", ctypes.c_double), ("focal_mm", ctypes.c_double)]
+
+
+_DP = ctypes.POINTER(ctypes.c_double)
+
+
+class _Spots(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("x_mm", _DP), ("y_mm", _DP), ("z_mm", _DP), ("amp", _DP)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("compression", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("trace_V", _DP)]
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Loads libhg.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"libhg.so not found at {_LIB_PATH}; build it with "
+                           "`python -m paper_2003_05293_amd.build`")
+    lib = ctypes.CDLL(_LIB_PATH)
+    c = ctypes
+    vp, i32, u32, u64, dbl = c.c_void_p, c.c_int32, c.c_uint32, c.c_uint64, c.c_double
+    G, O, S = c.POINTER(_Grid), c.POINTER(_Optics), c.POINTER(_Spots)
+    sig = {
+        "hg_rs": [G, O, S, u64, vp, vp],
+        "hg_wgs": [G, O, S, i32, u64, vp, vp],
+        "hg_cswgs": [G, O, S, i32, dbl, u64, vp, vp],
+        "hg_cswgs_ex": [G, O, S, c.POINTER(_Params), vp, vp],
+        "hg_metrics": [G, O, S, vp, _DP, _DP, _DP, vp],
+        "hg_theta0": [u64, i32, _DP],
+        "hg_subset": [G, u64, i32, dbl, vp, c.POINTER(i32), vp],
+        "hg_forward": [G, O, S, vp, vp, i32, u32, _DP, vp],
+        "hg_backward": [G, O, S, _DP, _DP, vp, i32, u32, vp, vp],
+        "hg_step": [G, O, S, _DP, _DP, vp, i32, u32, _DP, vp],
+        "hg_release": [],
+        "hg_timing_enable": [c.c_int],
+        "hg_timing_reset": [],
+        "hg_timing_read": [c.c_char_p, _DP, c.POINTER(c.c_int64)],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = c.c_int
+    lib.hg_last_error.restype = c.c_char_p
+    lib.hg_last_error.argtypes = []
+    lib.hg_version.restype = c.c_char_p
+    lib.hg_version.argtypes = []
+    _lib = lib
+    return lib
+
+
+def version() -> str:
+    return load().hg_version().decode()
+
+
+def last_error() -> str:
+    return load().hg_last_error().decode()
+
+
+def _check(status: int):
+    if status != 0:
+        raise HGError(status, last_error())
+
+
+def release():
+    _check(load().hg_release())
+
+
+# ----------------------------------------------------------- marshalling ---
+
+def _grid(g) -> _Grid:
+    return _Grid(int(g.W), int(g.H), float(g.pitch_mm))
+
+
+def _optics(o) -> _Optics:
+    return _Optics(float(o.lambda_mm), float(o.focal_mm))
+
+
+class _SpotArgs:
+    """Keeps contiguous float64 copies alive for the duration of a call."""
+
+    def __init__(self, s):
+        self.arrays = [np.ascontiguousarray(getattr(s, k), dtype=np.float64)
+                       for k in ("x_mm", "y_mm", "z_mm", "amp")]
+        n = self.arrays[0].shape[0]
+        for a in self.arrays:
+            if a.ndim != 1 or a.shape[0] != n:
+                raise ValueError("spot arrays must be 1-D and of equal length")
+        self.n = n
+        self.struct = _Spots(n, *[a.ctypes.data_as(_DP) for a in self.arrays])
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_f32(t, numel: int, name: str):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float32 torch tensor on the GPU")
+    if not t.is_contiguous() or t.numel() < numel:
+        raise ValueError(f"{name} must be contiguous with at least {numel} elements")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_i32(t, name: str):
+    import torch
+    if t is None:
+        return None, 0
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.int32 or not t.is_cuda:
+        raise TypeError(f"{name} must be an int32 torch tensor on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr()), int(t.numel())
+
+
+def _new_phi(grid, numel=None):
+    import torch
+    return torch.empty(int(numel if numel is not None else grid.W * grid.H),
+                       dtype=torch.float32, device="cuda")
+
+
+def _flags(precision: str) -> int:
+    try:
+        return _PREC[precision]
+    except KeyError:
+        raise ValueError(f"precision must be one of {sorted(_PREC)}") from None
+
+
+def _f64(a, n: int, name: str):
+    arr = np.ascontiguousarray(a, dtype=np.float64)
+    if arr.shape != (n,):
+        raise ValueError(f"{name} must have shape ({n},)")
+    return arr
+
+
+# ------------------------------------------------------------------ calls ---
+
+def rs(grid, optics, spots, seed: int, phi=None, stream=None):
+    """Random superposition hologram (eq. 1).  Returns phi (float32 [H*W])."""
+    lib = load()
+    phi = _new_phi(grid) if phi is None else phi
+    sa = _SpotArgs(spots)
+    _check(lib.hg_rs(_grid(grid), _optics(optics), sa.struct, int(seed),
+                     _dev_f32(phi, grid.W * grid.H, "phi"), _stream(stream)))
+    return phi
+
+
+def wgs(grid, optics, spots, iterations: int, seed: int, phi=None, stream=None):
+    """Weighted Gerchberg-Saxton hologram after `iterations` iterations."""
+    lib = load()
+    phi = _new_phi(grid) if phi is None else phi
+    sa = _SpotArgs(spots)
+    _check(lib.hg_wgs(_grid(grid), _optics(optics), sa.struct, int(iterations), int(seed),
+                      _dev_f32(phi, grid.W * grid.H, "phi"), _stream(stream)))
+    return phi
+
+
+def cswgs(grid, optics, spots, iterations: int, compression: float, seed: int, phi=None,
+          stream=None, precision: str = "fp32", trace: bool = False):
+    """Compressed-sensing WGS hologram.  With trace=True returns (phi, V)
+    where V[j-1] is the complex spot field of iteration j."""
+    lib = load()
+    phi = _new_phi(grid) if phi is None else phi
+    sa = _SpotArgs(spots)
+    flags = _flags(precision)
+    if precision == "fp32" and not trace:
+        _check(lib.hg_cswgs(_grid(grid), _optics(optics), sa.struct, int(iterations),
+                            float(compression), int(seed),
+                            _dev_f32(phi, grid.W * grid.H, "phi"), _stream(stream)))
+        return phi
+    tr = np.zeros((max(int(iterations), 1), sa.n, 2)) if trace else None
+    params = _Params(int(iterations), float(compression), int(seed), flags,
+                     tr.ctypes.data_as(_DP) if trace else None)
+    _check(lib.hg_cswgs_ex(_grid(grid), _optics(optics), sa.struct, ctypes.byref(params),
+                           _dev_f32(phi, grid.W * grid.H, "phi"), _stream(stream)))
+    if trace:
+        return phi, (tr[..., 0] + 1j * tr[..., 1])[:int(iterations)]
+    return phi
+
+
+def metrics(grid, optics, spots, phi, stream=None) -> Tuple[float, float, np.ndarray]:
+    """FP64 efficiency e, uniformity u and spot intensities of a hologram."""
+    lib = load()
+    sa = _SpotArgs(spots)
+    e, u = ctypes.c_double(), ctypes.c_double()
+    inten = np.zeros(sa.n)
+    _check(lib.hg_metrics(_grid(grid), _optics(optics), sa.struct,
+                          _dev_f32(phi, grid.W * grid.H, "phi"), ctypes.byref(e),
+                          ctypes.byref(u), inten.ctypes.data_as(_DP), _stream(stream)))
+    return e.value, u.value, inten
+
+
+def theta0(seed: int, n: int) -> np.ndarray:
+    """Initial phases theta_n^0 (radians) computed on the GPU."""
+    lib = load()
+    out = np.zeros(int(n))
+    _check(lib.hg_theta0(int(seed), int(n), out.ctypes.data_as(_DP)))
+    return out
+
+
+def subset(grid, seed: int, j: int, compression: float, stream=None):
+    """Pixel indices of Omega^j as an int32 GPU tensor."""
+    import torch
+    lib = load()
+    m_cap = int(np.ceil(float(compression) * grid.W * grid.H))
+    idx = torch.empty(max(m_cap, 1), dtype=torch.int32, device="cuda")
+    m = ctypes.c_int32()
+    _check(lib.hg_subset(_grid(grid), int(seed), int(j), float(compression),
+                         ctypes.c_void_p(idx.data_ptr()), ctypes.byref(m), _stream(stream)))
+    return idx[:m.value]
+
+
+def forward(grid, optics, spots, phi, idx=None, precision: str = "fp32",
+            stream=None) -> np.ndarray:
+    """Spot fields V_n (eq. 3) of the hologram phi over idx (default all)."""
+    lib = load()
+    sa = _SpotArgs(spots)
+    ip, m = _dev_i32(idx, "idx")
+    V = np.zeros(2 * sa.n)
+    _check(lib.hg_forward(_grid(grid), _optics(optics), sa.struct,
+                          _dev_f32(phi, grid.W * grid.H, "phi"), ip, m, _flags(precision),
+                          V.ctypes.data_as(_DP), _stream(stream)))
+    return V[0::2] + 1j * V[1::2]
+
+
+def backward(grid, optics, spots, w, theta, idx=None, out=None, precision: str = "fp32",
+             stream=None):
+    """Phi (eq. 1) with weights w and phases theta at idx (compact) or at
+    all pixels."""
+    lib = load()
+    sa = _SpotArgs(spots)
+    w = _f64(w, sa.n, "w")
+    th = _f64(theta, sa.n, "theta")
+    ip, m = _dev_i32(idx, "idx")
+    count = m if idx is not None else grid.W * grid.H
+    out = _new_phi(grid, count) if out is None else out
+    _check(lib.hg_backward(_grid(grid), _optics(optics), sa.struct, w.ctypes.data_as(_DP),
+                           th.ctypes.data_as(_DP), ip, m, _flags(precision),
+                           _dev_f32(out, count, "out"), _stream(stream)))
+    return out
+
+
+def step(grid, optics, spots, w, theta, idx=None, precision: str = "fp32",
+         stream=None) -> np.ndarray:
+    """One fused iteration body: back-propagate (w, theta) on the pixel set
+    and return the forward spot fields over the same set."""
+    lib = load()
+    sa = _SpotArgs(spots)
+    w = _f64(w, sa.n, "w")
+    th = _f64(theta, sa.n, "theta")
+    ip, m = _dev_i32(idx, "idx")
+    V = np.zeros(2 * sa.n)
+    _check(lib.hg_step(_grid(grid), _optics(optics), sa.struct, w.ctypes.data_as(_DP),
+                       th.ctypes.data_as(_DP), ip, m, _flags(precision),
+                       V.ctypes.data_as(_DP), _stream(stream)))
+    return V[0::2] + 1j * V[1::2]
+
+
+def cswgs_device(grid, optics, spots_dev, iterations: int, compression: float, seed: int,
+                 phi=None, stream=None, precision: str = "fp32"):
+    """CS-WGS with the spot arrays already on the GPU: spots_dev is a float64
+    GPU tensor of shape (4, N) holding x_mm, y_mm, z_mm, amp."""
+    import torch
+    lib = load()
+    if (not isinstance(spots_dev, torch.Tensor) or spots_dev.dtype != torch.float64
+            or not spots_dev.is_cuda or spots_dev.dim() != 2 or spots_dev.shape[0] != 4
+            or not spots_dev.is_contiguous()):
+        raise TypeError("spots_dev must be a contiguous float64 GPU tensor of shape (4, N)")
+    n = int(spots_dev.shape[1])
+    base = spots_dev.data_ptr()
+    ptrs = [ctypes.cast(ctypes.c_void_p(base + 8 * n * k), _DP) for k in range(4)]
+    sp = _Spots(n, *ptrs)
+    phi = _new_phi(grid) if phi is None else phi
+    params = _Params(int(iterations), float(compression), int(seed),
+                     _flags(precision) | SPOTS_ON_DEVICE, None)
+    _check(lib.hg_cswgs_ex(_grid(grid), _optics(optics), sp, ctypes.byref(params),
+                           _dev_f32(phi, grid.W * grid.H, "phi"), _stream(stream)))
+    return phi
+
+
+def timing_enable(on: bool = True):
+    """Bracket every iteration-kernel launch with HIP events (benchmarks)."""
+    _check(load().hg_timing_enable(1 if on else 0))
+
+
+def timing_reset():
+    _check(load().hg_timing_reset())
+
+
+def timing_read(name: str):
+    """(total ms, launches) of a kernel family since the last reset."""
+    ms = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    _check(load().hg_timing_read(name.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value

@@ -1,0 +1,350 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Bars:
+* theta^0 and the subset pixel indices: bit-exact.
+* Forward projection with Phi held fixed (the oracle evaluates eq. 3 on
+  float64 of the GPU's float32 Phi): per-spot |V_n| relative error <= 1e-5.
+* One fused iteration body with (w, theta) held fixed: |V_n| relative
+  error <= 1e-5.
+* Final efficiency and uniformity of RS / WGS / CS-WGS: within 1e-3 of the
+  oracle's; the wrapped Phi error is reported as RMS / 99.9th pct / max.
+* FP64 metrics of one hologram: within 1e-9 of the oracle's on the same Phi.
+Each case prints its name before touching the GPU.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2003_05293_amd as hg
+from workload import Grid, OPTICS, Spots, spot_cloud
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+REL_V = 1e-5
+EU_TOL = 1e-3
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    hg.load()
+    yield
+    torch.cuda.synchronize()
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def to_np(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def to_dev(a, dtype="float32"):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a).astype(dtype), device="cuda")
+
+
+def wrapped(a, b):
+    return np.abs(np.angle(np.exp(1j * (np.asarray(a) - np.asarray(b)))))
+
+
+def err_stats(d):
+    d = np.asarray(d)
+    return dict(rms=float(np.sqrt((d ** 2).mean())), p999=float(np.quantile(d, 0.999)),
+                max=float(d.max()))
+
+
+def rel_mag_err(Vg, Vo):
+    return float(np.max(np.abs(np.abs(Vg) - np.abs(Vo)) / np.abs(Vo)))
+
+
+# ------------------------------------------------------------- draws ---
+
+@pytest.mark.parametrize("seed", [0, 1, 12345, 2**63 + 5, 2**64 - 1])
+def test_theta0_bit_exact(seed):
+    say("theta0", seed)
+    got = hg.theta0(seed, 4096)
+    assert np.array_equal(got, oracle.theta0(seed, 4096))
+
+
+SUBSET_CASES = [
+    (256, 256, 0, 1, 1 / 16), (256, 256, 0, 17, 1 / 16), (1152, 1152, 7, 1, 1 / 16),
+    (1152, 1152, 7, 29, 1 / 16), (1920, 1152, 3, 5, 1 / 16), (512, 512, 9, 2, 1 / 2),
+    (300, 170, 4, 4, 0.3), (7, 5, 1, 3, 0.5), (1, 1, 2, 1, 1.0), (33, 1, 5, 2, 0.9),
+    (1024, 1024, 11, 30, 1 / 256),
+]
+
+
+@pytest.mark.parametrize("W,H,seed,j,c", SUBSET_CASES)
+def test_subset_bit_exact(W, H, seed, j, c):
+    say("subset", W, H, seed, j, c)
+    idx = hg.subset(Grid(W, H), seed, j, c)
+    got = to_np(idx).astype(np.int64)
+    want = oracle.subset(W * H, seed, j, c)
+    assert got.shape == want.shape
+    assert np.array_equal(got, want)
+
+
+# ----------------------------------------------------- back-propagation ---
+
+def test_backward_one_spot_closed_form():
+    g = Grid(1152, 1152)
+    s = spot_cloud(5, 1, g)
+    say("backward one spot 1152x1152")
+    th = np.array([2.5])
+    phi = to_np(hg.backward(g, OPTICS, s, [1.0], th))
+    want = oracle.spot_phase(g, OPTICS, s, np.arange(g.M))[:, 0] + th[0]
+    st = err_stats(wrapped(phi, want))
+    print("N=1 wrapped Phi error", st)
+    # |t| <= 250 turns: three FP32 roundings and the FP32 coefficients stay
+    # within 5e-5 turns = 3.2e-4 rad.
+    assert st["max"] < 3.2e-4 and st["rms"] < 5e-5
+
+
+@pytest.mark.parametrize("W,H,N,seed", [(256, 256, 16, 0), (300, 170, 37, 1),
+                                        (1152, 1152, 100, 2), (1920, 1152, 150, 3)])
+def test_backward_vs_oracle(W, H, N, seed):
+    g = Grid(W, H)
+    s = spot_cloud(seed, N, g, z_half_mm=0.1)
+    rng = np.random.default_rng(seed)
+    w = rng.uniform(0.5, 1.5, N)
+    th = rng.uniform(-math.pi, math.pi, N)
+    idx = np.sort(rng.choice(g.M, min(g.M, 50000), replace=False)).astype(np.int32)
+    say("backward", W, H, N)
+    phi = to_np(hg.backward(g, OPTICS, s, w, th, idx=to_dev(idx, "int32")))
+    want = oracle.backward(g, OPTICS, s, w, th, idx)
+    st = err_stats(wrapped(phi, want))
+    print("backward wrapped Phi error", W, H, N, st)
+    assert st["rms"] < 1e-4 and st["p999"] < 2e-3
+
+
+def test_backward_all_pixels_layout():
+    g = Grid(97, 61)
+    s = spot_cloud(8, 9, g)
+    w = np.linspace(0.7, 1.3, 9)
+    th = np.linspace(0, 6, 9)
+    say("backward all pixels 97x61")
+    phi = to_np(hg.backward(g, OPTICS, s, w, th))
+    want = oracle.backward(g, OPTICS, s, w, th)
+    assert err_stats(wrapped(phi, want))["max"] < 1e-3
+
+
+# ------------------------------------------------------------ forward ---
+
+@pytest.mark.parametrize("W,H,N,seed,sub", [(256, 256, 16, 0, None), (1152, 1152, 100, 1, None),
+                                            (1152, 1152, 100, 1, 1 / 16),
+                                            (300, 170, 70, 4, 0.3), (1920, 1152, 129, 6, 1 / 16)])
+def test_forward_phi_held_fixed(W, H, N, seed, sub):
+    g = Grid(W, H)
+    s = spot_cloud(seed, N, g)
+    th0 = oracle.theta0(seed, N)
+    idx = None if sub is None else oracle.subset(g.M, seed, 1, sub)
+    # a realistic hologram: RS phase, rounded to float32 on the oracle side
+    phi32 = oracle.backward(g, OPTICS, s, np.ones(N), th0).astype(np.float32)
+    say("forward", W, H, N, sub)
+    Vg = hg.forward(g, OPTICS, s, to_dev(phi32),
+                    idx=None if idx is None else to_dev(idx, "int32"))
+    p = np.arange(g.M) if idx is None else idx
+    Vo = oracle.forward(g, OPTICS, s, phi32.astype(np.float64)[p], p)
+    e = rel_mag_err(Vg, Vo)
+    print("forward |V| rel err", W, H, N, sub, e)
+    assert e <= REL_V
+    assert np.max(np.abs(Vg - Vo)) <= REL_V * np.abs(Vo).mean() * 3
+
+
+@pytest.mark.parametrize("W,H,N,seed,sub", [(256, 256, 16, 0, None), (1152, 1152, 100, 3, 1 / 16),
+                                            (333, 129, 65, 9, 0.25), (64, 64, 1, 2, None)])
+def test_step_state_held_fixed(W, H, N, seed, sub):
+    g = Grid(W, H)
+    s = spot_cloud(seed, N, g)
+    rng = np.random.default_rng(seed + 100)
+    w = rng.uniform(0.6, 1.4, N)
+    th = rng.uniform(0, 2 * math.pi, N)
+    idx = None if sub is None else oracle.subset(g.M, seed, 2, sub)
+    say("step", W, H, N, sub)
+    Vg = hg.step(g, OPTICS, s, w, th, idx=None if idx is None else to_dev(idx, "int32"))
+    p = np.arange(g.M) if idx is None else idx
+    Vo = oracle.forward(g, OPTICS, s, oracle.backward(g, OPTICS, s, w, th, p), p)
+    e = rel_mag_err(Vg, Vo)
+    print("step |V| rel err", W, H, N, sub, e)
+    assert e <= REL_V
+
+
+# ----------------------------------------------------------- metrics ---
+
+@pytest.mark.parametrize("W,H,N,seed", [(256, 256, 16, 0), (1152, 1152, 100, 1), (130, 77, 5, 2)])
+def test_metrics_fp64(W, H, N, seed):
+    g = Grid(W, H)
+    s = spot_cloud(seed, N, g)
+    say("metrics", W, H, N)
+    phi = hg.rs(g, OPTICS, s, seed)
+    e, u, inten = hg.metrics(g, OPTICS, s, phi)
+    eo, uo, io = oracle.metrics(g, OPTICS, s, to_np(phi))
+    print("metrics", W, H, N, e, eo, u, uo)
+    assert abs(e - eo) < 1e-9 and abs(u - uo) < 1e-9
+    assert np.max(np.abs(inten - io)) < 1e-10
+
+
+# ------------------------------------------------------- algorithms ---
+
+def test_rs_vs_oracle():
+    g = Grid(256, 256)
+    s = spot_cloud(0, 16, g)
+    say("rs 256x256 N=16")
+    phi = to_np(hg.rs(g, OPTICS, s, 0))
+    want = oracle.rs(g, OPTICS, s, 0)
+    st = err_stats(wrapped(phi, want))
+    print("RS wrapped Phi error", st)
+    assert st["rms"] < 1e-4
+    e, u, _ = oracle.metrics(g, OPTICS, s, phi)
+    eo, uo, _ = oracle.metrics(g, OPTICS, s, want)
+    assert abs(e - eo) < EU_TOL and abs(u - uo) < EU_TOL
+
+
+@pytest.mark.parametrize("W,H,N", [(1, 1, 1), (1, 1, 3), (3, 5, 2), (2, 64, 65), (257, 3, 129)])
+def test_rs_degenerate_grids(W, H, N):
+    g = Grid(W, H)
+    s = spot_cloud(1, N, g)
+    say("rs degenerate", W, H, N)
+    phi = to_np(hg.rs(g, OPTICS, s, 4))
+    want = oracle.rs(g, OPTICS, s, 4)
+    assert err_stats(wrapped(phi, want))["max"] < 1e-3
+
+
+def _run_and_compare(g, s, I, c, seed, tag):
+    say(tag, g.W, g.H, s.n, I, c)
+    if c is None:
+        phi_g = hg.wgs(g, OPTICS, s, I, seed)
+        tr = oracle.Trace()
+        phi_o = oracle.wgs(g, OPTICS, s, I, seed, tr)
+        _, Vg = hg.cswgs(g, OPTICS, s, I, 1.0, seed, trace=True)  # c = 1: same sets
+    else:
+        phi_g, Vg = hg.cswgs(g, OPTICS, s, I, c, seed, trace=True)
+        tr = oracle.Trace()
+        phi_o = oracle.cswgs(g, OPTICS, s, I, c, seed, tr)
+    eg, ug, _ = hg.metrics(g, OPTICS, s, phi_g)
+    eo, uo, _ = oracle.metrics(g, OPTICS, s, phi_o)
+    st = err_stats(wrapped(to_np(phi_g), phi_o))
+    e1 = rel_mag_err(Vg[0], tr.V[0])
+    print(tag, "e", eg, eo, "u", ug, uo, "V^1 rel", e1, "Phi", st)
+    assert abs(eg - eo) <= EU_TOL and abs(ug - uo) <= EU_TOL
+    assert e1 <= REL_V
+    return st
+
+
+def test_wgs_256_n16_i20():
+    g = Grid(256, 256)
+    _run_and_compare(g, spot_cloud(0, 16, g), 20, None, 0, "wgs")
+
+
+@pytest.mark.parametrize("c", [1 / 16, 1 / 4, 1.0])
+def test_cswgs_256_n16_i20(c):
+    g = Grid(256, 256)
+    _run_and_compare(g, spot_cloud(0, 16, g), 20, c, 0, "cswgs")
+
+
+def test_cswgs_ragged():
+    g = Grid(300, 170)
+    _run_and_compare(g, spot_cloud(3, 37, g, z_half_mm=0.1), 8, 0.1, 11, "cswgs ragged")
+
+
+def test_cswgs_512_n200():
+    g = Grid(512, 512)
+    _run_and_compare(g, spot_cloud(4, 200, g, z_half_mm=0.1), 10, 1 / 16, 4, "cswgs 512 N=200")
+
+
+def test_iterations_zero_is_rs_and_one_is_wgs():
+    import torch
+    g = Grid(128, 96)
+    s = spot_cloud(2, 12, g)
+    say("schedule identities")
+    a = hg.rs(g, OPTICS, s, 9)
+    b = hg.wgs(g, OPTICS, s, 0, 9)
+    c = hg.cswgs(g, OPTICS, s, 0, 0.25, 9)
+    d = hg.cswgs(g, OPTICS, s, 1, 0.25, 9)
+    e = hg.wgs(g, OPTICS, s, 1, 9)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b) and torch.equal(a, c) and torch.equal(d, e)
+
+
+def test_single_spot_stays_converged():
+    g = Grid(200, 150)
+    s = spot_cloud(6, 1, g)
+    say("single spot wgs")
+    phi, V = hg.cswgs(g, OPTICS, s, 5, 0.25, 3, trace=True)
+    assert np.allclose(np.abs(V), 1.0, atol=2e-6)
+    e, u, _ = hg.metrics(g, OPTICS, s, phi)
+    assert abs(e - 1) < 1e-6 and u == 1.0
+
+
+def test_deterministic_bitwise():
+    import torch
+    g = Grid(1152, 1152)
+    s = spot_cloud(1, 100, g)
+    say("determinism 1152")
+    a = hg.cswgs(g, OPTICS, s, 30, 1 / 16, 1)
+    b = hg.cswgs(g, OPTICS, s, 30, 1 / 16, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_streams_do_not_interfere():
+    import torch
+    g = Grid(512, 512)
+    s1 = spot_cloud(1, 50, g)
+    s2 = spot_cloud(2, 80, g)
+    say("two streams")
+    ref1 = hg.cswgs(g, OPTICS, s1, 10, 1 / 8, 1)
+    ref2 = hg.cswgs(g, OPTICS, s2, 10, 1 / 8, 2)
+    st1, st2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(st1):
+        a = hg.cswgs(g, OPTICS, s1, 10, 1 / 8, 1)
+    with torch.cuda.stream(st2):
+        b = hg.cswgs(g, OPTICS, s2, 10, 1 / 8, 2)
+    torch.cuda.synchronize()
+    assert torch.equal(a, ref1) and torch.equal(b, ref2)
+
+
+# ------------------------------------------------- full-size cases ---
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name + ".json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name", ["cswgs_1152x1152_n100_i30_c16_seed0",
+                                  "wgs_1152x1152_n100_i30_seed0",
+                                  "cswgs_1920x1152_n150_i20_c16_seed3"])
+def test_full_size_against_stored_oracle(name):
+    path = os.path.join(GOLDEN, name + ".json")
+    if not os.path.exists(path):
+        pytest.skip(f"stored oracle result {name} not generated")
+    gd = _golden(name)
+    g = Grid(gd["W"], gd["H"])
+    s = spot_cloud(gd["seed"], gd["n"], g, z_half_mm=gd["z_half_mm"])
+    say("full size", name)
+    c = gd["compression"]
+    if c is None:
+        phi, V = hg.cswgs(g, OPTICS, s, gd["iterations"], 1.0, gd["seed"], trace=True)
+        phi = hg.wgs(g, OPTICS, s, gd["iterations"], gd["seed"])
+    else:
+        phi, V = hg.cswgs(g, OPTICS, s, gd["iterations"], c, gd["seed"], trace=True)
+    e, u, inten = hg.metrics(g, OPTICS, s, phi)
+    V1 = np.array(gd["V1"])
+    V1 = V1[:, 0] + 1j * V1[:, 1]
+    e1 = rel_mag_err(V[0], V1)
+    pix = np.array(gd["sample_pixels"])
+    st = err_stats(wrapped(to_np(phi)[pix], np.array(gd["sample_phi"])))
+    print(name, "e", e, gd["e"], "u", u, gd["u"], "V^1 rel", e1, "Phi sample", st)
+    assert abs(e - gd["e"]) <= EU_TOL and abs(u - gd["u"]) <= EU_TOL
+    assert e1 <= REL_V
