@@ -142,12 +142,12 @@ def main():
     torch.cuda.synchronize()
     hg.timing_enable(False)
     kern = {}
-    for name in ("k_iter_subset", "k_iter_full", "k_update", "k_backprop_phi"):
+    for name in ("k_pass_subset", "k_pass_full", "k_backprop_phi"):
         ms, cnt = hg.timing_read(name)
         kern[name] = {"total_ms": ms, "launches": cnt, "avg_us": 1000.0 * ms / max(cnt, 1)}
     dominant = max(kern, key=lambda k: kern[k]["total_ms"])
     m = math.ceil(COMP * W * H)
-    pixels = {"k_iter_subset": m, "k_iter_full": W * H}
+    pixels = {"k_pass_subset": m, "k_pass_full": W * H}
     if dominant in pixels:
         flops = pixels[dominant] * N * (FLOPS_BACK + FLOPS_FWD)
     else:

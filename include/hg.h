@@ -209,8 +209,8 @@ hg_status hg_release(void);
 /* Kernel timing for benchmarks.  While enabled, every launch of the
  * iteration kernels is bracketed by two HIP events recorded on the stream it
  * runs on.  hg_timing_read synchronises those events and returns, for the
- * kernel family `name` ("k_iter_subset", "k_iter_full", "k_update",
- * "k_backprop_phi"), the summed
+ * kernel family `name` ("k_pass_subset": compressed iterations, "k_pass_full":
+ * full-grid iterations, "k_backprop_phi": the final hologram), the summed
  * duration in ms and the number of launches since the last reset. */
 hg_status hg_timing_enable(int on);
 hg_status hg_timing_reset(void);

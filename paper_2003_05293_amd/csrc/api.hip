@@ -104,6 +104,8 @@ struct Workspace {
   DevBuf<uint32_t> tab;           // 6 * 2^h Feistel tables
   DevBuf<int32_t> perm;           // M random order
   DevBuf<float2> partial;         // blocks * N
+  DevBuf<double2> gpart;          // groups * N
+  DevBuf<unsigned> counters;      // groups + 1, zero between passes
   DevBuf<double2> V;              // N, or iterations * N when tracing
   DevBuf<int32_t> status;         // 1
   DevBuf<double2> Ex, Ey, mpart;  // metrics
@@ -189,6 +191,8 @@ struct Workspace {
     tab.release();
     perm.release();
     partial.release();
+    gpart.release();
+    counters.release();
     V.release();
     status.release();
     Ex.release();
@@ -315,6 +319,17 @@ hg_status build_order(Workspace* ws, int64_t M, uint64_t seed) {
   return HG_OK;
 }
 
+// Scratch of a pass of `count` pixels; counters are cleared by a fill kernel
+// (never by a memset node) so that the sequence can be graph-captured.
+hg_status reserve_pass(Workspace* ws, const hg::PassPlan& plan, int N) {
+  HG_TRY(ws->partial.reserve((size_t)plan.blocks * N));
+  HG_TRY(ws->gpart.reserve((size_t)plan.ngroups * N));
+  const size_t before = ws->counters.cap;
+  HG_TRY(ws->counters.reserve((size_t)plan.ngroups + 1));
+  if (ws->counters.cap != before) hg::launch_zero_counters(ws->counters.p, (int)ws->counters.cap, ws->stream);
+  return HG_OK;
+}
+
 hg::PixelSet all_pixels(int32_t M) {
   hg::PixelSet ps;
   ps.perm = nullptr;
@@ -359,27 +374,25 @@ hg_status run_iterations(const hg_grid* g, const hg_optics* o, const hg_spots* s
 
   HG_TRY(upload_spots(ws, g, o, s, seed, on_device, nullptr, nullptr, nullptr));
   if (compressed) HG_TRY(build_order(ws, M, seed));
-  const int blocks_all = hg::iter_blocks(M, hg::iter_ppt(M));
-  const int blocks_sub = hg::iter_blocks(m, hg::iter_ppt(m));
-  HG_TRY(ws->partial.reserve((size_t)(blocks_all > blocks_sub ? blocks_all : blocks_sub) * N));
+  const hg::PassPlan plan_all = hg::plan_pass(M);
+  const hg::PassPlan plan_sub = hg::plan_pass(m);
+  HG_TRY(reserve_pass(ws, plan_all, N));
+  HG_TRY(reserve_pass(ws, plan_sub, N));
   HG_TRY(ws->V.reserve((size_t)N * (trace_host && iterations > 0 ? iterations : 1)));
 
   for (int32_t j = 1; j <= iterations; ++j) {
     hg::PixelSet ps = all_pixels(M);
-    if (compressed && j < iterations) {
+    const bool sub = compressed && j < iterations;
+    if (sub) {
       ps.perm = ws->perm.p;
       ps.start = (int64_t)(j - 1) * m % M;
       ps.count = m;
     }
-    const int ppt = hg::iter_ppt(ps.count);
-    const int nblk = hg::iter_blocks(ps.count, ppt);
     double2* Vj = ws->V.p + (trace_host ? (size_t)(j - 1) * N : 0);
-    ws->timed_launch(ps.count == M ? "k_iter_full" : "k_iter_subset", [&] {
-      hg::launch_iter(ws->sp.p, N, g->W, g->H, ps, ppt, ws->partial.p, ws->stream);
-    });
-    ws->timed_launch("k_update", [&] {
-      hg::launch_update(ws->partial.p, nblk, N, 1.0 / (double)ps.count, ws->sp.p, Vj,
-                        ws->status.p, ws->stream);
+    ws->timed_launch(sub ? "k_pass_subset" : "k_pass_full", [&] {
+      hg::launch_pass(sub ? plan_sub : plan_all, ws->sp.p, N, g->W, g->H, ps, nullptr,
+                      ws->partial.p, ws->gpart.p, ws->counters.p, Vj, ws->status.p, true,
+                      ws->stream);
     });
   }
   ws->timed_launch("k_backprop_phi", [&] {
@@ -543,13 +556,11 @@ hg_status hg_forward(const hg_grid* grid, const hg_optics* optics, const hg_spot
   const int32_t M = grid->W * grid->H;
   HG_TRY(upload_spots(ws, grid, optics, spots, 0, false, nullptr, nullptr, nullptr));
   const hg::PixelSet ps = index_set(idx_dev, m, M);
-  const int ppt = hg::iter_ppt(ps.count);
-  const int nblk = hg::iter_blocks(ps.count, ppt);
-  HG_TRY(ws->partial.reserve((size_t)nblk * N));
+  const hg::PassPlan plan = hg::plan_pass(ps.count);
+  HG_TRY(reserve_pass(ws, plan, N));
   HG_TRY(ws->V.reserve(N));
-  hg::launch_forward_phi(ws->sp.p, N, grid->W, grid->H, ps, phi_dev, ppt, ws->partial.p,
-                         ws->stream);
-  hg::launch_reduce(ws->partial.p, nblk, N, 1.0 / (double)ps.count, ws->V.p, ws->stream);
+  hg::launch_pass(plan, ws->sp.p, N, grid->W, grid->H, ps, phi_dev, ws->partial.p, ws->gpart.p,
+                  ws->counters.p, ws->V.p, ws->status.p, false, ws->stream);
   HG_TRY(check_launch());
   HG_HIP(hipMemcpyAsync(V_out, ws->V.p, sizeof(double2) * N, hipMemcpyDeviceToHost, ws->stream));
   HG_HIP(hipStreamSynchronize(ws->stream));
@@ -587,12 +598,11 @@ hg_status hg_step(const hg_grid* grid, const hg_optics* optics, const hg_spots* 
   const int N = spots->n;
   HG_TRY(upload_spots(ws, grid, optics, spots, 0, false, w, theta, nullptr));
   const hg::PixelSet ps = index_set(idx_dev, m, grid->W * grid->H);
-  const int ppt = hg::iter_ppt(ps.count);
-  const int nblk = hg::iter_blocks(ps.count, ppt);
-  HG_TRY(ws->partial.reserve((size_t)nblk * N));
+  const hg::PassPlan plan = hg::plan_pass(ps.count);
+  HG_TRY(reserve_pass(ws, plan, N));
   HG_TRY(ws->V.reserve(N));
-  hg::launch_iter(ws->sp.p, N, grid->W, grid->H, ps, ppt, ws->partial.p, ws->stream);
-  hg::launch_reduce(ws->partial.p, nblk, N, 1.0 / (double)ps.count, ws->V.p, ws->stream);
+  hg::launch_pass(plan, ws->sp.p, N, grid->W, grid->H, ps, nullptr, ws->partial.p, ws->gpart.p,
+                  ws->counters.p, ws->V.p, ws->status.p, false, ws->stream);
   HG_TRY(check_launch());
   HG_HIP(hipMemcpyAsync(V_out, ws->V.p, sizeof(double2) * N, hipMemcpyDeviceToHost, ws->stream));
   HG_HIP(hipStreamSynchronize(ws->stream));

@@ -64,53 +64,6 @@ __device__ __forceinline__ float2 backprop_field(const SpotRec* __restrict__ sp,
 // spots (64 per chunk), waves split the tile's pixels; the pixel record read
 // is uniform across the wave (an LDS broadcast).  Each block writes one
 // partial sum per spot: the waves' sums added in wave order.
-__device__ __forceinline__ void forward_term(float cx, float cy, float cz, const float4& a,
-                                             float ui, float& vr, float& vi) {
-  const float t = fmaf(cx, a.x, fmaf(cy, a.y, cz * a.z));
-  float sn, cs;
-  sincos_turns(t, sn, cs);
-  // u * conj(e^{i 2 pi t})
-  vr = fmaf(a.w, cs, fmaf(ui, sn, vr));
-  vi = fmaf(ui, cs, fmaf(-a.w, sn, vi));
-}
-
-__device__ __forceinline__ void forward_tile(const SpotRec* __restrict__ sp, int N,
-                                             const float4* __restrict__ px,
-                                             const float* __restrict__ pui, int npix,
-                                             float2 (*red)[64], float2* __restrict__ partial) {
-  // the wave index is uniform across the wave: keep the pixel loop scalar
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  for (int n0 = 0; n0 < N; n0 += 64) {
-    const int n = n0 + lane;
-    float cx = 0.f, cy = 0.f, cz = 0.f;
-    if (n < N) {
-      cx = sp[n].cx;
-      cy = sp[n].cy;
-      cz = sp[n].cz;
-    }
-    float vr = 0.f, vi = 0.f;
-    int k = wave;
-    for (; k + 3 * kWaves < npix; k += 4 * kWaves) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) forward_term(cx, cy, cz, px[k + u * kWaves], pui[k + u * kWaves], vr, vi);
-    }
-    for (; k < npix; k += kWaves) forward_term(cx, cy, cz, px[k], pui[k], vr, vi);
-    red[wave][lane] = make_float2(vr, vi);
-    __syncthreads();
-    if (wave == 0 && n < N) {
-      float2 acc = red[0][lane];
-#pragma unroll
-      for (int w = 1; w < kWaves; ++w) {
-        acc.x += red[w][lane].x;
-        acc.y += red[w][lane].y;
-      }
-      partial[(int64_t)blockIdx.x * N + n] = acc;
-    }
-    __syncthreads();
-  }
-}
-
 // ---------------------------------------------------------------- setup ---
 
 // Spot coefficients in FP64, rounded once to FP32.  Spot values that are not
@@ -167,6 +120,23 @@ __global__ void k_tables(uint64_t seed, int h, uint32_t* __restrict__ tab) {
   tab[k] = feistel_table_entry(seed, r, R, h);
 }
 
+// pi(k) for every k < M.  The Feistel tables are staged in LDS when they fit
+// in 48 KB (h <= 11, M <= 4^11); otherwise they are read from global memory.
+constexpr int kPermThreads = 512;
+constexpr int kPermLdsHalfBits = 11;
+
+__global__ __launch_bounds__(kPermThreads) void k_perm_lds(int32_t M, int h,
+                                                          const uint32_t* __restrict__ tab_g,
+                                                          int32_t* __restrict__ perm) {
+  __shared__ uint32_t tab[kFeistelRounds << kPermLdsHalfBits];
+  const int total = kFeistelRounds << h;
+  for (int k = threadIdx.x; k < total; k += kPermThreads) tab[k] = tab_g[k];
+  __syncthreads();
+  const int32_t stride = gridDim.x * kPermThreads;
+  for (int32_t k = blockIdx.x * kPermThreads + threadIdx.x; k < M; k += stride)
+    perm[k] = (int32_t)permute((uint32_t)k, (uint32_t)M, tab, h);
+}
+
 __global__ void k_perm(int32_t M, int h, const uint32_t* __restrict__ tab,
                        int32_t* __restrict__ perm) {
   const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -182,161 +152,337 @@ __global__ void k_gather(PixelSet ps, int32_t* __restrict__ out) {
 
 // ------------------------------------------------------------ iteration ---
 
-// One fused iteration body over a pixel set: back-propagation of eq. (1)
-// with the current (A, th), normalised to the unit phasor u = e^{i Phi},
-// then the forward partial sums of eq. (3) over the same pixels.  Phi is
-// never stored: the next forward step reads it only on these pixels.
-template <int PPT>
-__global__ __launch_bounds__(kBlock) void k_iter(const SpotRec* __restrict__ sp, int N, int W,
-                                                 int H, PixelSet ps,
-                                                 float2* __restrict__ partial) {
-  __shared__ float4 px[kBlock * PPT];
-  __shared__ float pui[kBlock * PPT];
-  __shared__ float2 red[kWaves][64];
-  const int32_t base = blockIdx.x * (kBlock * PPT);
-#pragma unroll
-  for (int k = 0; k < PPT; ++k) {
-    const int qi = k * kBlock + threadIdx.x;
-    const int32_t q = base + qi;
-    float4 rec = make_float4(0.f, 0.f, 0.f, 0.f);
-    float ui = 0.f;
-    if (q < ps.count) {
-      const PixCoord c = pixel_coord(pixel_of(ps, q), W, H);
-      const float2 S = backprop_field(sp, N, c);
-      const float m2 = S.x * S.x + S.y * S.y;
-      float ur = 1.f;
-      if (m2 > 0.f) {
-        const float inv = rsqrtf(m2);
-        ur = S.x * inv;
-        ui = S.y * inv;
-      }
-      rec = make_float4(c.Lx, c.Ly, c.Q, ur);
-    }
-    px[qi] = rec;
-    pui[qi] = ui;
-  }
-  __syncthreads();
-  const int npix = min(kBlock * PPT, ps.count - base);
-  forward_tile(sp, N, px, pui, npix, red, partial);
+// One pass over a pixel set, in tiles of kTile pixels:
+//  phase 1  back-propagation (eq. 1) of the current state, the spot sum
+//           split over the block's waves (wave w adds spots
+//           [w N/4, (w+1) N/4) for all kTile pixels, lane = pixel, spot
+//           records uniform across the wave); the four partial fields are
+//           added in wave order and normalised to u = e^{i Phi};
+//           or, with FROM_PHI, u = e^{i Phi} of a stored hologram;
+//  phase 2  forward projection (eq. 3): lanes map to spots (groups of Lg
+//           lanes, R = 64/Lg replicas each taking every R-th pixel), waves
+//           to (spot chunk, pixel slice) units; each lane keeps its running
+//           sum across all tiles of the block;
+//  tail     the block's per-spot sums go to partial[block]; the last block
+//           of each group of blocks to finish adds its group's partials (in
+//           block order, FP64), and the last group to finish adds the group
+//           sums (in group order), divides by |Omega| and, when asked,
+//           applies the weight update of eqs. (4)-(6) in place.
+// Every sum is taken in an order fixed by the pass size alone, so results
+// do not depend on scheduling.
+constexpr int kTile = 64;
+
+struct PassArgs {
+  SpotRec* sp;           // spot records (updated in place when update != 0)
+  int N, W, H;
+  PixelSet ps;
+  const float* phi;      // FROM_PHI: stored hologram, [H][W]
+  int tiles;             // ceil(ps.count / kTile)
+  int group_size;        // blocks per first-level group
+  int ngroups;
+  float2* partial;       // [gridDim.x][N]
+  double2* gpart;        // [ngroups][N]
+  unsigned* counters;    // [ngroups + 1], zero on entry, zero again on exit
+  double inv_count;      // 1 / |Omega|
+  double2* V;            // [N] spot fields of this pass
+  int32_t* status;
+  int update;
+};
+
+__device__ __forceinline__ void forward_term(float cx, float cy, float cz, const float4& a,
+                                             float ui, float& vr, float& vi) {
+  const float t = fmaf(cx, a.x, fmaf(cy, a.y, cz * a.z));
+  float sn, cs;
+  sincos_turns(t, sn, cs);
+  // u * conj(e^{i 2 pi t})
+  vr = fmaf(a.w, cs, fmaf(ui, sn, vr));
+  vi = fmaf(ui, cs, fmaf(-a.w, sn, vi));
 }
 
-// Forward partial sums of a stored hologram Phi (radians) over a pixel set.
-template <int PPT>
-__global__ __launch_bounds__(kBlock) void k_forward_phi(const SpotRec* __restrict__ sp, int N,
-                                                        int W, int H, PixelSet ps,
-                                                        const float* __restrict__ phi,
-                                                        float2* __restrict__ partial) {
-  __shared__ float4 px[kBlock * PPT];
-  __shared__ float pui[kBlock * PPT];
-  __shared__ float2 red[kWaves][64];
-  const int32_t base = blockIdx.x * (kBlock * PPT);
-  constexpr float kInvTwoPi = 0.15915494309189535f;
-#pragma unroll
-  for (int k = 0; k < PPT; ++k) {
-    const int qi = k * kBlock + threadIdx.x;
-    const int32_t q = base + qi;
-    float4 rec = make_float4(0.f, 0.f, 0.f, 0.f);
-    float ui = 0.f;
-    if (q < ps.count) {
-      const int32_t p = pixel_of(ps, q);
-      const PixCoord c = pixel_coord(p, W, H);
-      float sn, cs;
-      sincos_turns(phi[p] * kInvTwoPi, sn, cs);
-      rec = make_float4(c.Lx, c.Ly, c.Q, cs);
-      ui = sn;
-    }
-    px[qi] = rec;
-    pui[qi] = ui;
-  }
-  __syncthreads();
-  const int npix = min(kBlock * PPT, ps.count - base);
-  forward_tile(sp, N, px, pui, npix, red, partial);
+// Spot-lane layout of phase 2 for N spots.
+struct LaneMap {
+  int Lg;   // lanes per spot group (8, 16, 32 or 64)
+  int R;    // replicas per wave = 64 / Lg
+  int nch;  // spot chunks = ceil(N / Lg)
+  int S;    // pixel slices per chunk
+  int U;    // units = nch * S
+};
+
+__host__ __device__ inline LaneMap lane_map(int N) {
+  LaneMap m;
+  const int n = N < 64 ? N : 64;
+  m.Lg = n <= 8 ? 8 : n <= 16 ? 16 : n <= 32 ? 32 : 64;
+  m.R = 64 / m.Lg;
+  m.nch = (N + m.Lg - 1) / m.Lg;
+  m.S = m.nch >= kWaves ? 1 : kWaves / m.nch;
+  m.U = m.nch * m.S;
+  return m;
 }
 
-// Sum the per-block partials of each spot in FP64, in a fixed order:
-// slice s of the block's threads adds blocks s, s+S, s+2S, ...; the slices
-// are then added in slice order by the slice-0 thread of the spot, which
-// writes V_n = sum * inv_count.  Spot n is always finalised by thread
-// n mod kChunk; the return value is that thread's sum of |V_n| (0 for the
-// other threads).
-constexpr int kChunk = 128;
-constexpr int kSlices = kUpdateThreads / kChunk;
+// Cross-block hand-off of the pass sums.  The L2 caches of the XCDs are not
+// coherent with each other, and an agent-scope fence would write back and
+// invalidate the whole L2 of every block's XCD (measured: 4x slower pass).
+// Instead the partial sums are written and read with device-scope accesses
+// (coherent across XCDs, not left dirty in any L2), each writer waits until
+// its own writes have completed before the block's counter increment, and
+// the counters are device-scope read-modify-writes.  The block that sees the
+// last increment of a group therefore reads every partial of that group.
+__device__ __forceinline__ void store_dev(float2* p, float2 v) {
+  uint64_t bits;
+  __builtin_memcpy(&bits, &v, sizeof(bits));
+  __hip_atomic_store(reinterpret_cast<uint64_t*>(p), bits, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float2 load_dev(const float2* p) {
+  const uint64_t bits = __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+  float2 v;
+  __builtin_memcpy(&v, &bits, sizeof(v));
+  return v;
+}
+__device__ __forceinline__ void store_dev(double2* p, double2 v) {
+  double* d = reinterpret_cast<double*>(p);
+  __hip_atomic_store(d, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(d + 1, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double2 load_dev(const double2* p) {
+  const double* d = reinterpret_cast<const double*>(p);
+  return make_double2(__hip_atomic_load(d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                      __hip_atomic_load(d + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
 
-__device__ double reduce_partials(const float2* __restrict__ partial, int nblk, int N,
-                                  double inv_count, double2* __restrict__ V) {
-  __shared__ double rre[kSlices][kChunk];
-  __shared__ double rim[kSlices][kChunk];
-  const int c = threadIdx.x % kChunk;
-  const int s = threadIdx.x / kChunk;
-  double magsum = 0.0;
-  for (int n0 = 0; n0 < N; n0 += kChunk) {
+// Sum over rows k = k0, k0 + step, ... < k1 of src[k * N + n], in that
+// order, in FP64.  Loads are issued kBatch at a time so that their latency
+// overlaps; out-of-range slots contribute exact zeros.
+constexpr int kBatch = 8;
+template <typename T>
+__device__ __forceinline__ double2 ordered_column_sum(const T* __restrict__ src, int N, int n,
+                                                      int k0, int k1, int step) {
+  double re = 0.0, im = 0.0;
+  for (int k = k0; k < k1; k += step * kBatch) {
+    T v[kBatch];
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      const int kk = k + b * step;
+      v[b] = kk < k1 ? load_dev(src + (int64_t)kk * N + n) : T{};
+    }
+#pragma unroll
+    for (int b = 0; b < kBatch; ++b) {
+      re += (double)v[b].x;
+      im += (double)v[b].y;
+    }
+  }
+  return make_double2(re, im);
+}
+
+// Returns true in the block that made the last of `expected` increments.
+__device__ __forceinline__ bool arrive_last(unsigned* counter, unsigned expected, int* flag) {
+  __builtin_amdgcn_s_waitcnt(0);  // this thread's device-scope writes are complete
+  __syncthreads();
+  if (threadIdx.x == 0) *flag = atomicAdd(counter, 1u) == expected - 1u;
+  __syncthreads();
+  return *flag != 0;
+}
+
+// Adds this block's partials into the group / global sums (see above).
+__device__ void pass_tail(const PassArgs& a) {
+  __shared__ int last;
+  __shared__ double mred[kBlock];
+  __shared__ double2 cred[kBlock];
+  const int N = a.N;
+  // thread = (spot lane c, slice s): Npad spot lanes, S slices
+  int Npad = 1;
+  while (Npad < N && Npad < kBlock) Npad <<= 1;
+  const int S = kBlock / Npad;
+  const int c = threadIdx.x % Npad, s = threadIdx.x / Npad;
+
+  const int g = blockIdx.x / a.group_size;
+  const int b0 = g * a.group_size;
+  const int b1 = min(b0 + a.group_size, (int)gridDim.x);
+  if (!arrive_last(&a.counters[g], (unsigned)(b1 - b0), &last)) return;
+  for (int n0 = 0; n0 < N; n0 += Npad) {
     const int n = n0 + c;
-    double are = 0.0, aim = 0.0;
-    if (n < N) {
-      for (int b = s; b < nblk; b += kSlices) {
-        const float2 v = partial[(int64_t)b * N + n];
-        are += (double)v.x;
-        aim += (double)v.y;
-      }
-    }
-    rre[s][c] = are;
-    rim[s][c] = aim;
+    cred[threadIdx.x] = n < N ? ordered_column_sum(a.partial, N, n, b0 + s, b1, S)
+                              : make_double2(0.0, 0.0);
     __syncthreads();
     if (s == 0 && n < N) {
-      double tr = rre[0][c], ti = rim[0][c];
-#pragma unroll
-      for (int k = 1; k < kSlices; ++k) {
-        tr += rre[k][c];
-        ti += rim[k][c];
+      double2 t = cred[c];
+      for (int k = 1; k < S; ++k) {
+        t.x += cred[k * Npad + c].x;
+        t.y += cred[k * Npad + c].y;
       }
-      tr *= inv_count;
-      ti *= inv_count;
-      V[n] = make_double2(tr, ti);
-      magsum += sqrt(tr * tr + ti * ti);
+      store_dev(a.gpart + (int64_t)g * N + n, t);
     }
     __syncthreads();
   }
-  return magsum;
-}
-
-__global__ __launch_bounds__(kUpdateThreads) void k_reduce(const float2* __restrict__ partial,
-                                                           int nblk, int N, double inv_count,
-                                                           double2* __restrict__ V) {
-  reduce_partials(partial, nblk, N, inv_count, V);
-}
-
-// eqs. (4)-(6): w_n <- w_n * mean_k |V_k| / |V_n|, theta_n <- arg V_n,
-// A_n = a_n^0 w_n.  A spot whose field is zero or not finite keeps its
-// state and raises the numeric status flag.  Each spot is updated by the
-// thread that finalised its V_n, so V is read back by its own writer.
-__global__ __launch_bounds__(kUpdateThreads) void k_update(const float2* __restrict__ partial,
-                                                           int nblk, int N, double inv_count,
-                                                           SpotRec* __restrict__ sp,
-                                                           double2* __restrict__ V,
-                                                           int32_t* __restrict__ status) {
-  __shared__ double msum[kUpdateThreads];
-  msum[threadIdx.x] = reduce_partials(partial, nblk, N, inv_count, V);
-  __syncthreads();
-  for (int stride = kUpdateThreads / 2; stride > 0; stride >>= 1) {
-    if (threadIdx.x < stride) msum[threadIdx.x] += msum[threadIdx.x + stride];
+  if (!arrive_last(&a.counters[a.ngroups], (unsigned)a.ngroups, &last)) return;
+  // global sums, |V_n| and their total (thread (c, 0) owns spot n = n0 + c)
+  double magsum = 0.0;
+  for (int n0 = 0; n0 < N; n0 += Npad) {
+    const int n = n0 + c;
+    cred[threadIdx.x] = n < N ? ordered_column_sum(a.gpart, N, n, s, a.ngroups, S)
+                              : make_double2(0.0, 0.0);
+    __syncthreads();
+    if (s == 0 && n < N) {
+      double2 t = cred[c];
+      for (int k = 1; k < S; ++k) {
+        t.x += cred[k * Npad + c].x;
+        t.y += cred[k * Npad + c].y;
+      }
+      t.x *= a.inv_count;
+      t.y *= a.inv_count;
+      a.V[n] = t;
+      magsum += sqrt(t.x * t.x + t.y * t.y);
+    }
     __syncthreads();
   }
-  const double mean = msum[0] / (double)N;
-  if (threadIdx.x >= kChunk) return;
-  for (int n = threadIdx.x; n < N; n += kChunk) {
-    const double2 v = V[n];
+  // the counters are ready for the next pass (kernel end orders these writes)
+  for (int k = threadIdx.x; k <= a.ngroups; k += kBlock) a.counters[k] = 0u;
+  if (!a.update) return;
+  mred[threadIdx.x] = magsum;
+  __syncthreads();
+  for (int stride = kBlock / 2; stride > 0; stride >>= 1) {
+    if (threadIdx.x < stride) mred[threadIdx.x] += mred[threadIdx.x + stride];
+    __syncthreads();
+  }
+  const double mean = mred[0] / (double)N;
+  if (s != 0) return;
+  // eqs. (4)-(6): w_n <- w_n mean/|V_n|, theta_n <- arg V_n, A_n = a_n^0 w_n.
+  for (int n = c; n < N; n += Npad) {
+    const double2 v = a.V[n];  // written above by this same thread
     const double mag = sqrt(v.x * v.x + v.y * v.y);
-    SpotRec r = sp[n];
+    SpotRec r = a.sp[n];
     const double w = (double)r.w * (mean / mag);
     if (!(mag > 0.0) || !isfinite(w)) {
-      status[0] = 4;  // HG_ENUMERIC
+      a.status[0] = 4;  // HG_ENUMERIC
       continue;
     }
     r.w = (float)w;
     r.A = (float)(w * (double)r.a0);
     r.th = (float)(atan2(v.y, v.x) / (2.0 * M_PI));
-    sp[n] = r;
+    a.sp[n] = r;
   }
+}
+
+template <int MAXU, bool FROM_PHI>
+__global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
+  __shared__ float2 sw[kWaves][kTile];
+  __shared__ float4 px[kTile];
+  __shared__ float pui[kTile];
+  __shared__ float2 red[kWaves * MAXU][64];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int N = a.N;
+  const LaneMap lm = lane_map(N);
+  const int g = lane % lm.Lg, r = lane / lm.Lg;
+  const SpotRec* __restrict__ sp = a.sp;
+
+  float cx[MAXU], cy[MAXU], cz[MAXU], vr[MAXU], vi[MAXU];
+#pragma unroll
+  for (int k = 0; k < MAXU; ++k) {
+    const int u = wave + k * kWaves;
+    const int n = (u / lm.S) * lm.Lg + g;
+    cx[k] = cy[k] = cz[k] = 0.f;
+    vr[k] = vi[k] = 0.f;
+    if (u < lm.U && n < N) {
+      cx[k] = sp[n].cx;
+      cy[k] = sp[n].cy;
+      cz[k] = sp[n].cz;
+    }
+  }
+  const int n_lo = (wave * N) / kWaves, n_hi = ((wave + 1) * N) / kWaves;
+
+  for (int tile = blockIdx.x; tile < a.tiles; tile += gridDim.x) {
+    const int32_t q = tile * kTile + lane;
+    const bool valid = q < a.ps.count;
+    if (FROM_PHI) {
+      if (wave == 0) {
+        float4 rec = make_float4(0.f, 0.f, 0.f, 0.f);
+        float ui = 0.f;
+        if (valid) {
+          const int32_t p = pixel_of(a.ps, q);
+          const PixCoord c = pixel_coord(p, a.W, a.H);
+          float sn, cs;
+          sincos_turns(a.phi[p] * 0.15915494309189535f, sn, cs);
+          rec = make_float4(c.Lx, c.Ly, c.Q, cs);
+          ui = sn;
+        }
+        px[lane] = rec;
+        pui[lane] = ui;
+      }
+      __syncthreads();
+    } else {
+      PixCoord c{0.f, 0.f, 0.f};
+      if (valid) c = pixel_coord(pixel_of(a.ps, q), a.W, a.H);
+      float sr = 0.f, si = 0.f;
+#pragma unroll 4
+      for (int n = n_lo; n < n_hi; ++n) {
+        const SpotRec s = sp[n];
+        const float t = fmaf(s.cx, c.Lx, fmaf(s.cy, c.Ly, fmaf(s.cz, c.Q, s.th)));
+        float sn, cs;
+        sincos_turns(t, sn, cs);
+        sr = fmaf(s.A, cs, sr);
+        si = fmaf(s.A, sn, si);
+      }
+      sw[wave][lane] = make_float2(sr, si);
+      __syncthreads();
+      if (wave == 0) {
+        float4 rec = make_float4(0.f, 0.f, 0.f, 0.f);
+        float ui = 0.f;
+        if (valid) {
+          float2 S = sw[0][lane];
+#pragma unroll
+          for (int w = 1; w < kWaves; ++w) {
+            S.x += sw[w][lane].x;
+            S.y += sw[w][lane].y;
+          }
+          const float m2 = S.x * S.x + S.y * S.y;
+          float ur = 1.f;
+          if (m2 > 0.f) {
+            const float inv = rsqrtf(m2);
+            ur = S.x * inv;
+            ui = S.y * inv;
+          }
+          rec = make_float4(c.Lx, c.Ly, c.Q, ur);
+        }
+        px[lane] = rec;
+        pui[lane] = ui;
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < MAXU; ++k) {
+      const int u = wave + k * kWaves;
+      if (u < lm.U) {
+        const int sl = u % lm.S;
+        const int j0 = (sl * kTile) / lm.S + r, j1 = ((sl + 1) * kTile) / lm.S;
+        for (int j = j0; j < j1; j += lm.R) forward_term(cx[k], cy[k], cz[k], px[j], pui[j], vr[k], vi[k]);
+      }
+    }
+    __syncthreads();
+  }
+  // block partials: spot n = c*Lg + g of chunk c sums units (c, s) over
+  // slices s and replicas r, in that order.
+#pragma unroll
+  for (int k = 0; k < MAXU; ++k) {
+    const int u = wave + k * kWaves;
+    if (u < lm.U) red[u][lane] = make_float2(vr[k], vi[k]);
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < lm.nch * lm.Lg; idx += kBlock) {
+    const int ch = idx / lm.Lg, gg = idx % lm.Lg;
+    const int n = ch * lm.Lg + gg;
+    if (n >= N) continue;
+    float2 acc = make_float2(0.f, 0.f);
+    for (int sl = 0; sl < lm.S; ++sl)
+      for (int rr = 0; rr < lm.R; ++rr) {
+        const float2 v = red[ch * lm.S + sl][rr * lm.Lg + gg];
+        acc.x += v.x;
+        acc.y += v.y;
+      }
+    store_dev(a.partial + (int64_t)blockIdx.x * N + n, acc);
+  }
+  pass_tail(a);
 }
 
 // Final hologram on a pixel set: Phi = atan2(Im S, Re S), written to out[q].
@@ -458,7 +604,13 @@ void launch_tables(uint64_t seed, int h, uint32_t* tab, hipStream_t s) {
 }
 
 void launch_perm(int32_t M, int h, const uint32_t* tab, int32_t* perm, hipStream_t s) {
-  hipLaunchKernelGGL(k_perm, dim3(ceil_div(M, 256)), dim3(256), 0, s, M, h, tab, perm);
+  if (h <= kPermLdsHalfBits) {
+    int blocks = ceil_div(M, kPermThreads * 4);
+    blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
+    hipLaunchKernelGGL(k_perm_lds, dim3(blocks), dim3(kPermThreads), 0, s, M, h, tab, perm);
+  } else {
+    hipLaunchKernelGGL(k_perm, dim3(ceil_div(M, 256)), dim3(256), 0, s, M, h, tab, perm);
+  }
 }
 
 void launch_gather(const PixelSet& ps, int32_t* out, hipStream_t s) {
@@ -466,51 +618,62 @@ void launch_gather(const PixelSet& ps, int32_t* out, hipStream_t s) {
   hipLaunchKernelGGL(k_gather, dim3(ceil_div(ps.count, 256)), dim3(256), 0, s, ps, out);
 }
 
-int iter_ppt(int32_t count) {
-  // keep at least ~1000 blocks in flight before packing more pixels per block
-  if (count >= 4 * 1024 * kBlock) return 4;
-  if (count >= 2 * 1024 * kBlock) return 2;
-  return 1;
+int pass_tiles(int32_t count) { return ceil_div(count, kTile); }
+
+PassPlan plan_pass(int32_t count) {
+  PassPlan p;
+  p.tiles = pass_tiles(count);
+  // one tile per block while that gives up to 4096 blocks, then loop
+  p.blocks = p.tiles < 4096 ? p.tiles : 4096;
+  if (p.blocks < 1) p.blocks = 1;
+  int gs = 1;
+  while (gs * gs < p.blocks) ++gs;
+  p.group_size = gs;
+  p.ngroups = ceil_div(p.blocks, gs);
+  return p;
 }
 
-int iter_blocks(int32_t count, int ppt) { return ceil_div(count, (int64_t)kBlock * ppt); }
-
-void launch_iter(const SpotRec* sp, int N, int W, int H, const PixelSet& ps, int ppt,
-                 float2* partial, hipStream_t s) {
-  const dim3 grid(iter_blocks(ps.count, ppt)), block(kBlock);
-  switch (ppt) {
-    case 4: hipLaunchKernelGGL(k_iter<4>, grid, block, 0, s, sp, N, W, H, ps, partial); break;
-    case 2: hipLaunchKernelGGL(k_iter<2>, grid, block, 0, s, sp, N, W, H, ps, partial); break;
-    default: hipLaunchKernelGGL(k_iter<1>, grid, block, 0, s, sp, N, W, H, ps, partial); break;
+void launch_pass(const PassPlan& plan, SpotRec* sp, int N, int W, int H, const PixelSet& ps,
+                 const float* phi, float2* partial, double2* gpart, unsigned* counters,
+                 double2* V, int32_t* status, bool update, hipStream_t s) {
+  PassArgs a;
+  a.sp = sp;
+  a.N = N;
+  a.W = W;
+  a.H = H;
+  a.ps = ps;
+  a.phi = phi;
+  a.tiles = plan.tiles;
+  a.group_size = plan.group_size;
+  a.ngroups = plan.ngroups;
+  a.partial = partial;
+  a.gpart = gpart;
+  a.counters = counters;
+  a.inv_count = 1.0 / (double)ps.count;
+  a.V = V;
+  a.status = status;
+  a.update = update ? 1 : 0;
+  const dim3 grid(plan.blocks), block(kBlock);
+  const LaneMap lm = lane_map(N);
+  const int units_per_wave = ceil_div(lm.U, kWaves);
+  if (phi) {
+    if (units_per_wave <= 1) hipLaunchKernelGGL((k_pass<1, true>), grid, block, 0, s, a);
+    else if (units_per_wave <= 4) hipLaunchKernelGGL((k_pass<4, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_pass<16, true>), grid, block, 0, s, a);
+  } else {
+    if (units_per_wave <= 1) hipLaunchKernelGGL((k_pass<1, false>), grid, block, 0, s, a);
+    else if (units_per_wave <= 4) hipLaunchKernelGGL((k_pass<4, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_pass<16, false>), grid, block, 0, s, a);
   }
 }
 
-void launch_forward_phi(const SpotRec* sp, int N, int W, int H, const PixelSet& ps,
-                        const float* phi, int ppt, float2* partial, hipStream_t s) {
-  const dim3 grid(iter_blocks(ps.count, ppt)), block(kBlock);
-  switch (ppt) {
-    case 4:
-      hipLaunchKernelGGL(k_forward_phi<4>, grid, block, 0, s, sp, N, W, H, ps, phi, partial);
-      break;
-    case 2:
-      hipLaunchKernelGGL(k_forward_phi<2>, grid, block, 0, s, sp, N, W, H, ps, phi, partial);
-      break;
-    default:
-      hipLaunchKernelGGL(k_forward_phi<1>, grid, block, 0, s, sp, N, W, H, ps, phi, partial);
-      break;
-  }
+__global__ void k_zero_u32(unsigned* p, int n) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = 0u;
 }
 
-void launch_update(const float2* partial, int nblk, int N, double inv_count, SpotRec* sp,
-                   double2* V, int32_t* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_update, dim3(1), dim3(kUpdateThreads), 0, s, partial, nblk, N, inv_count,
-                     sp, V, status);
-}
-
-void launch_reduce(const float2* partial, int nblk, int N, double inv_count, double2* V,
-                   hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kUpdateThreads), 0, s, partial, nblk, N, inv_count,
-                     V);
+void launch_zero_counters(unsigned* counters, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u32, dim3(ceil_div(n, 256)), dim3(256), 0, s, counters, n);
 }
 
 void launch_backprop_phi(const SpotRec* sp, int N, int W, int H, const PixelSet& ps, float* out,

@@ -59,21 +59,24 @@ void launch_perm(int32_t M, int h, const uint32_t* tab, int32_t* perm, hipStream
 void launch_gather(const PixelSet& ps, int32_t* out, hipStream_t s);
 
 // ---- iteration ----
-// Blocks used by a fused/forward pass over `count` pixels.
-int iter_blocks(int32_t count, int ppt);
-int iter_ppt(int32_t count);
-// Fused back-propagation + forward partial sums over the pixel set.
-void launch_iter(const SpotRec* sp, int N, int W, int H, const PixelSet& ps, int ppt,
-                 float2* partial, hipStream_t s);
-// Forward partial sums of a given hologram over the pixel set.
-void launch_forward_phi(const SpotRec* sp, int N, int W, int H, const PixelSet& ps,
-                        const float* phi, int ppt, float2* partial, hipStream_t s);
-// Reduce partials (FP64), update w and theta (eqs. 4-6), record V.
-void launch_update(const float2* partial, int nblk, int N, double inv_count, SpotRec* sp,
-                   double2* V_out /*nullable*/, int32_t* status, hipStream_t s);
-// Reduce partials to V without touching the state.
-void launch_reduce(const float2* partial, int nblk, int N, double inv_count, double2* V_out,
-                   hipStream_t s);
+// Launch geometry of one pass over `count` pixels (a function of count only,
+// so the summation order of a pass never depends on the batch or device).
+struct PassPlan {
+  int tiles;       // pixel tiles of 64
+  int blocks;      // grid size; block b handles tiles b, b + blocks, ...
+  int group_size;  // blocks per first-level reduction group
+  int ngroups;
+};
+PassPlan plan_pass(int32_t count);
+// One pass: back-propagation of the state in `sp` (or, with phi != nullptr,
+// the stored hologram phi) on the pixel set, forward projection over the same
+// set, deterministic reduction to V (N complex, FP64) and, if `update`, the
+// weight update of eqs. (4)-(6) written back to sp.  `counters` must be zero
+// on entry (ngroups + 1 words) and is zero again when the pass ends.
+void launch_pass(const PassPlan& plan, SpotRec* sp, int N, int W, int H, const PixelSet& ps,
+                 const float* phi, float2* partial, double2* gpart, unsigned* counters,
+                 double2* V, int32_t* status, bool update, hipStream_t s);
+void launch_zero_counters(unsigned* counters, int n, hipStream_t s);
 // Final hologram: Phi = arg(sum_n A_n e^{i 2 pi (t_n + th_n)}) on the set,
 // written compactly (out[q]) or, for all pixels, at out[p].
 void launch_backprop_phi(const SpotRec* sp, int N, int W, int H, const PixelSet& ps, float* out,

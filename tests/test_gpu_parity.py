@@ -287,14 +287,22 @@ def test_single_spot_stays_converged():
 
 
 def test_deterministic_bitwise():
+    """Repeated runs are bit-identical: the cross-block hand-off of the pass
+    sums has a fixed order and reads every partial (a stale read would
+    change the result)."""
     import torch
     g = Grid(1152, 1152)
-    s = spot_cloud(1, 100, g)
-    say("determinism 1152")
-    a = hg.cswgs(g, OPTICS, s, 30, 1 / 16, 1)
-    b = hg.cswgs(g, OPTICS, s, 30, 1 / 16, 1)
-    torch.cuda.synchronize()
-    assert torch.equal(a, b)
+    clouds = [spot_cloud(1, 100, g), spot_cloud(2, 60, g)]
+    say("determinism 1152, 12 interleaved runs")
+    ref = [hg.cswgs(g, OPTICS, s, 30, 1 / 16, k + 1).clone() for k, s in enumerate(clouds)]
+    for rep in range(5):
+        for k, s in enumerate(clouds):
+            out = hg.cswgs(g, OPTICS, s, 30, 1 / 16, k + 1)
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref[k]), (rep, k)
+    _, V1 = hg.cswgs(g, OPTICS, clouds[0], 30, 1 / 16, 1, trace=True)
+    _, V2 = hg.cswgs(g, OPTICS, clouds[0], 30, 1 / 16, 1, trace=True)
+    assert np.array_equal(V1, V2)
 
 
 def test_streams_do_not_interfere():
