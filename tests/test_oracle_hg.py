@@ -290,6 +290,20 @@ def test_cswgs_improves_on_rs():
     assert u1 > u0 and u1 > 0.95
 
 
+def test_reading_literal_sign_flips_theta():
+    """Reading of eq. (3): with the printed sign e^{-i(Phi - phi_n)}, the
+    field of a one-spot hologram Phi = phi_1 + theta_1 has arg -theta_1, so
+    eq. (6) would flip theta every iteration; with the + sign it is kept."""
+    g = Grid(40, 30)
+    s = spot_cloud(3, 1, g)
+    th = 1.1
+    Phi = H.backward(g, OPTICS, s, [1.0], [th])
+    phi = H.spot_phase(g, OPTICS, s, np.arange(g.M))[:, 0]
+    literal = np.exp(-1j * (Phi - phi)).mean()
+    assert abs(np.angle(literal) + th) < 1e-12
+    assert abs(np.angle(H.forward(g, OPTICS, s, Phi)[0]) - th) < 1e-12
+
+
 # ------------------------------------------------------ mutations ----
 
 def _mut_forward_sign(grid, optics, spots, Phi_p, p=None):
