@@ -2,8 +2,12 @@
 //
 // Paper section 2: eq. (1) back-propagation, eq. (2) lens-and-prism phase,
 // eq. (3) forward projection, eqs. (4)-(6) weight update, eq. (7) metrics.
-// Section 3 of the paper recomputes phi_n per pixel instead of storing it;
+// The paper's GPU section recomputes phi_n per pixel rather than storing it;
 // the kernels here do the same, in turns, from per-spot coefficients.
+//
+// All iteration kernels are batched: a launch covers one pass of every job
+// listed in its descriptor array, and each block finds its job by a binary
+// search over the descriptors' first-block offsets.
 #include <math.h>
 
 #include "device_math.hpp"
@@ -13,14 +17,47 @@ namespace hg {
 
 namespace {
 
-inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+__host__ __device__ inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// Address-space views of pointers read from the job tables.  Without them
+// the compiler sees generic pointers and issues flat loads.  Spot records
+// are read-only while a pass reads them (its weight update runs after every
+// block of the pass has finished reading), so they are read through the
+// constant address space: uniform indices then become scalar loads.
+#define HG_CONST __attribute__((address_space(4)))
+#define HG_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const HG_CONST T* as_const(const T* p) {
+  return (const HG_CONST T*)p;
+}
+template <typename T>
+__device__ __forceinline__ const HG_GLOBAL T* as_global(const T* p) {
+  return (const HG_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ HG_GLOBAL T* as_global_mut(T* p) {
+  return (HG_GLOBAL T*)p;
+}
+
+// Index of the descriptor whose block range holds `block` (descriptors are
+// sorted by block_begin, the first starts at 0).  Uniform across the block.
+template <typename D>
+__device__ __forceinline__ int find_desc(const D* __restrict__ d, int n, int block) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d[mid].block_begin <= block) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
 
 __device__ __forceinline__ int32_t pixel_of(const PixelSet& ps, int32_t q) {
-  if (ps.idx) return ps.idx[q];
+  if (ps.idx) return as_global(ps.idx)[q];
   if (ps.perm) {
     int64_t k = ps.start + q;
     if (k >= ps.M) k -= ps.M;
-    return ps.perm[k];
+    return as_global(ps.perm)[k];
   }
   return q;
 }
@@ -42,54 +79,85 @@ __device__ __forceinline__ PixCoord pixel_coord(int32_t p, int W, int H) {
   return c;
 }
 
-// Field of eq. (1) at one pixel: S = sum_n A_n e^{i 2 pi (t_n + th_n)}.
+// Field of eq. (1) at one pixel over spots [n0, n1): sum A_n e^{i 2 pi (t_n + th_n)}.
 // The spot loop index is uniform across the wave, so the records come in
 // through scalar loads and feed the vector ALU as scalar operands.
-__device__ __forceinline__ float2 backprop_field(const SpotRec* __restrict__ sp, int N,
+__device__ __forceinline__ float2 backprop_field(const SpotRec* spg, int n0, int n1,
                                                  const PixCoord& c) {
+  const HG_CONST SpotRec* sp = as_const(spg);
   float sr = 0.f, si = 0.f;
 #pragma unroll 4
-  for (int n = 0; n < N; ++n) {
-    const SpotRec s = sp[n];
-    const float t = fmaf(s.cx, c.Lx, fmaf(s.cy, c.Ly, fmaf(s.cz, c.Q, s.th)));
+  for (int n = n0; n < n1; ++n) {
+    const float scx = sp[n].cx, scy = sp[n].cy, scz = sp[n].cz, sth = sp[n].th, sA = sp[n].A;
+    const float t = fmaf(scx, c.Lx, fmaf(scy, c.Ly, fmaf(scz, c.Q, sth)));
     float sn, cs;
     sincos_turns(t, sn, cs);
-    sr = fmaf(s.A, cs, sr);
-    si = fmaf(s.A, sn, si);
+    sr = fmaf(sA, cs, sr);
+    si = fmaf(sA, sn, si);
   }
   return make_float2(sr, si);
 }
 
-// Forward partial sums over a tile of pixels held in LDS.  Lanes map to
-// spots (64 per chunk), waves split the tile's pixels; the pixel record read
-// is uniform across the wave (an LDS broadcast).  Each block writes one
-// partial sum per spot: the waves' sums added in wave order.
 // ---------------------------------------------------------------- setup ---
 
-// Spot coefficients in FP64, rounded once to FP32.  Spot values that are not
-// finite, or amplitudes that are not positive, raise the argument status
-// flag (device-resident inputs cannot be checked on the host).
-__global__ void k_setup(SetupArgs a, SpotPtrs in, SpotRec* __restrict__ sp,
-                        double* __restrict__ th0, int32_t* __restrict__ status) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= a.N) return;
-  const double x = in.x[n], y = in.y[n], z = in.z[n], amp = in.amp[n];
-  if (!isfinite(x) || !isfinite(y) || !isfinite(z) || !(amp > 0.0) || !isfinite(amp))
-    status[0] = 1;  // HG_EINVAL
-  const double lf = a.lambda_mm * a.focal_mm;
-  const double lf2 = lf * a.focal_mm;
-  SpotRec r;
-  r.cx = (float)(x * a.pitch_mm / (2.0 * lf));
-  r.cy = (float)(y * a.pitch_mm / (2.0 * lf));
-  r.cz = (float)(z * a.pitch_mm * a.pitch_mm / (4.0 * lf2));
-  const double u = theta0_turns(a.seed, (uint64_t)n);
-  r.th = (float)u;
-  r.A = (float)amp;
-  r.a0 = (float)amp;
-  r.w = 1.0f;
-  r.pad = 0.0f;
-  sp[n] = r;
-  if (th0) th0[n] = (2.0 * M_PI) * u;
+// Spot coefficients in FP64, rounded once to FP32; theta^0 from Philox;
+// w = 1; pass counters cleared.  Spot values that are not finite, or
+// amplitudes that are not positive, raise the argument status flag
+// (device-resident inputs cannot be checked on the host).  Blocks with
+// blockIdx.y > 0 fill the Feistel round tables of compressed jobs.
+__global__ __launch_bounds__(256) void k_setup_batch(const JobDev* __restrict__ jobs) {
+  const JobDev& jb = jobs[blockIdx.x];
+  if (blockIdx.y == 0) {
+    const double lf = jb.lambda_mm * jb.focal_mm;
+    const double lf2 = lf * jb.focal_mm;
+    for (int n = threadIdx.x; n < jb.N; n += blockDim.x) {
+      const double x = jb.in.x[n], y = jb.in.y[n], z = jb.in.z[n], amp = jb.in.amp[n];
+      if (!isfinite(x) || !isfinite(y) || !isfinite(z) || !(amp > 0.0) || !isfinite(amp))
+        jb.status[0] = 1;  // HG_EINVAL
+      SpotRec r;
+      r.cx = (float)(x * jb.pitch_mm / (2.0 * lf));
+      r.cy = (float)(y * jb.pitch_mm / (2.0 * lf));
+      r.cz = (float)(z * jb.pitch_mm * jb.pitch_mm / (4.0 * lf2));
+      r.th = (float)theta0_turns(jb.seed, (uint64_t)n);
+      r.A = (float)amp;
+      r.a0 = (float)amp;
+      r.w = 1.0f;
+      r.pad = 0.0f;
+      jb.sp[n] = r;
+    }
+    for (int k = threadIdx.x; k < jb.counters_len; k += blockDim.x) jb.counters[k] = 0u;
+  } else if (jb.compressed) {
+    const int total = kFeistelRounds << jb.h;
+    const int stride = (gridDim.y - 1) * blockDim.x;
+    for (int k = (blockIdx.y - 1) * blockDim.x + threadIdx.x; k < total; k += stride)
+      jb.tab[k] = feistel_table_entry(jb.seed, k >> jb.h, (uint32_t)k & ((1u << jb.h) - 1u), jb.h);
+  }
+}
+
+// pi(k) for every k < M of each compressed job.  With LDS, the Feistel
+// tables (h <= 11: 48 KB) are staged in LDS; otherwise read from memory.
+constexpr int kPermThreads = 512;
+constexpr int kPermLdsHalfBits = 11;
+constexpr int kPermPerThread = 4;
+
+template <bool LDS>
+__global__ __launch_bounds__(kPermThreads) void k_perm_batch(const JobDev* __restrict__ jobs,
+                                                             const JobSlice* __restrict__ slices,
+                                                             int nslices) {
+  __shared__ uint32_t tab_s[LDS ? (kFeistelRounds << kPermLdsHalfBits) : 1];
+  const int si = find_desc(slices, nslices, blockIdx.x);
+  const JobDev& jb = jobs[slices[si].job];
+  const int lb = blockIdx.x - slices[si].block_begin;
+  const int nb = ceil_div(jb.M, (int64_t)kPermThreads * kPermPerThread);
+  const uint32_t* tab = jb.tab;
+  if (LDS) {
+    const int total = kFeistelRounds << jb.h;
+    for (int k = threadIdx.x; k < total; k += kPermThreads) tab_s[k] = jb.tab[k];
+    __syncthreads();
+    tab = tab_s;
+  }
+  for (int32_t k = lb * kPermThreads + threadIdx.x; k < jb.M; k += nb * kPermThreads)
+    jb.perm[k] = (int32_t)permute((uint32_t)k, (uint32_t)jb.M, tab, jb.h);
 }
 
 __global__ void k_theta0(uint64_t seed, int count, double* __restrict__ out) {
@@ -111,39 +179,6 @@ __global__ void k_set_state(int N, const double* __restrict__ wth, SpotRec* __re
   sp[n] = r;
 }
 
-__global__ void k_tables(uint64_t seed, int h, uint32_t* __restrict__ tab) {
-  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t size = 1u << h;
-  if (k >= (uint32_t)kFeistelRounds * size) return;
-  const int r = (int)(k >> h);
-  const uint32_t R = k & (size - 1u);
-  tab[k] = feistel_table_entry(seed, r, R, h);
-}
-
-// pi(k) for every k < M.  The Feistel tables are staged in LDS when they fit
-// in 48 KB (h <= 11, M <= 4^11); otherwise they are read from global memory.
-constexpr int kPermThreads = 512;
-constexpr int kPermLdsHalfBits = 11;
-
-__global__ __launch_bounds__(kPermThreads) void k_perm_lds(int32_t M, int h,
-                                                          const uint32_t* __restrict__ tab_g,
-                                                          int32_t* __restrict__ perm) {
-  __shared__ uint32_t tab[kFeistelRounds << kPermLdsHalfBits];
-  const int total = kFeistelRounds << h;
-  for (int k = threadIdx.x; k < total; k += kPermThreads) tab[k] = tab_g[k];
-  __syncthreads();
-  const int32_t stride = gridDim.x * kPermThreads;
-  for (int32_t k = blockIdx.x * kPermThreads + threadIdx.x; k < M; k += stride)
-    perm[k] = (int32_t)permute((uint32_t)k, (uint32_t)M, tab, h);
-}
-
-__global__ void k_perm(int32_t M, int h, const uint32_t* __restrict__ tab,
-                       int32_t* __restrict__ perm) {
-  const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= M) return;
-  perm[k] = (int32_t)permute((uint32_t)k, (uint32_t)M, tab, h);
-}
-
 __global__ void k_gather(PixelSet ps, int32_t* __restrict__ out) {
   const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= ps.count) return;
@@ -152,13 +187,13 @@ __global__ void k_gather(PixelSet ps, int32_t* __restrict__ out) {
 
 // ------------------------------------------------------------ iteration ---
 
-// One pass over a pixel set, in tiles of kTile pixels:
+// One pass of one job over a pixel set, in tiles of kTile pixels:
 //  phase 1  back-propagation (eq. 1) of the current state, the spot sum
 //           split over the block's waves (wave w adds spots
 //           [w N/4, (w+1) N/4) for all kTile pixels, lane = pixel, spot
 //           records uniform across the wave); the four partial fields are
 //           added in wave order and normalised to u = e^{i Phi};
-//           or, with FROM_PHI, u = e^{i Phi} of a stored hologram;
+//           or, for a forward test pass, u = e^{i Phi} of a stored hologram;
 //  phase 2  forward projection (eq. 3): lanes map to spots (groups of Lg
 //           lanes, R = 64/Lg replicas each taking every R-th pixel), waves
 //           to (spot chunk, pixel slice) units; each lane keeps its running
@@ -168,26 +203,8 @@ __global__ void k_gather(PixelSet ps, int32_t* __restrict__ out) {
 //           block order, FP64), and the last group to finish adds the group
 //           sums (in group order), divides by |Omega| and, when asked,
 //           applies the weight update of eqs. (4)-(6) in place.
-// Every sum is taken in an order fixed by the pass size alone, so results
-// do not depend on scheduling.
-constexpr int kTile = 64;
-
-struct PassArgs {
-  SpotRec* sp;           // spot records (updated in place when update != 0)
-  int N, W, H;
-  PixelSet ps;
-  const float* phi;      // FROM_PHI: stored hologram, [H][W]
-  int tiles;             // ceil(ps.count / kTile)
-  int group_size;        // blocks per first-level group
-  int ngroups;
-  float2* partial;       // [gridDim.x][N]
-  double2* gpart;        // [ngroups][N]
-  unsigned* counters;    // [ngroups + 1], zero on entry, zero again on exit
-  double inv_count;      // 1 / |Omega|
-  double2* V;            // [N] spot fields of this pass
-  int32_t* status;
-  int update;
-};
+// Every sum is taken in an order fixed by the job's pass alone, so results
+// depend neither on scheduling nor on the other jobs of the batch.
 
 __device__ __forceinline__ void forward_term(float cx, float cy, float cz, const float4& a,
                                              float ui, float& vr, float& vi) {
@@ -230,23 +247,23 @@ __host__ __device__ inline LaneMap lane_map(int N) {
 __device__ __forceinline__ void store_dev(float2* p, float2 v) {
   uint64_t bits;
   __builtin_memcpy(&bits, &v, sizeof(bits));
-  __hip_atomic_store(reinterpret_cast<uint64_t*>(p), bits, __ATOMIC_RELAXED,
+  __hip_atomic_store(as_global_mut(reinterpret_cast<uint64_t*>(p)), bits, __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ float2 load_dev(const float2* p) {
-  const uint64_t bits = __hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
+  const uint64_t bits = __hip_atomic_load(as_global(reinterpret_cast<const uint64_t*>(p)),
+                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   float2 v;
   __builtin_memcpy(&v, &bits, sizeof(v));
   return v;
 }
 __device__ __forceinline__ void store_dev(double2* p, double2 v) {
-  double* d = reinterpret_cast<double*>(p);
+  HG_GLOBAL double* d = as_global_mut(reinterpret_cast<double*>(p));
   __hip_atomic_store(d, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_store(d + 1, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ double2 load_dev(const double2* p) {
-  const double* d = reinterpret_cast<const double*>(p);
+  const HG_GLOBAL double* d = as_global(reinterpret_cast<const double*>(p));
   return make_double2(__hip_atomic_load(d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
                       __hip_atomic_load(d + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
@@ -284,8 +301,25 @@ __device__ __forceinline__ bool arrive_last(unsigned* counter, unsigned expected
   return *flag != 0;
 }
 
+// Everything one (virtual) block of a pass needs, uniform across the block.
+struct PassCtx {
+  SpotRec* sp;
+  int N, W, H;
+  PixelSet ps;
+  const float* phi;
+  int tiles, group_size, ngroups;
+  int lb, nb;  // this block within the pass, blocks of the pass
+  float2* partial;
+  double2* gpart;
+  unsigned* counters;
+  double inv_count;
+  double2* V;
+  int32_t* status;
+  int update, from_phi;
+};
+
 // Adds this block's partials into the group / global sums (see above).
-__device__ void pass_tail(const PassArgs& a) {
+__device__ void pass_tail(const PassCtx& a) {
   __shared__ int last;
   __shared__ double mred[kBlock];
   __shared__ double2 cred[kBlock];
@@ -296,9 +330,9 @@ __device__ void pass_tail(const PassArgs& a) {
   const int S = kBlock / Npad;
   const int c = threadIdx.x % Npad, s = threadIdx.x / Npad;
 
-  const int g = blockIdx.x / a.group_size;
+  const int g = a.lb / a.group_size;
   const int b0 = g * a.group_size;
-  const int b1 = min(b0 + a.group_size, (int)gridDim.x);
+  const int b1 = min(b0 + a.group_size, a.nb);
   if (!arrive_last(&a.counters[g], (unsigned)(b1 - b0), &last)) return;
   for (int n0 = 0; n0 < N; n0 += Npad) {
     const int n = n0 + c;
@@ -364,12 +398,9 @@ __device__ void pass_tail(const PassArgs& a) {
   }
 }
 
-template <int MAXU, bool FROM_PHI>
-__global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
-  __shared__ float2 sw[kWaves][kTile];
-  __shared__ float4 px[kTile];
-  __shared__ float pui[kTile];
-  __shared__ float2 red[kWaves * MAXU][64];
+template <int MAXU>
+__device__ void pass_block(const PassCtx& a, float2 (*sw)[kTile], float4* px, float* pui,
+                           float2 (*red)[64]) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int N = a.N;
@@ -385,17 +416,18 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
     cx[k] = cy[k] = cz[k] = 0.f;
     vr[k] = vi[k] = 0.f;
     if (u < lm.U && n < N) {
-      cx[k] = sp[n].cx;
-      cy[k] = sp[n].cy;
-      cz[k] = sp[n].cz;
+      const HG_GLOBAL SpotRec* rec = as_global(sp + n);
+      cx[k] = rec->cx;
+      cy[k] = rec->cy;
+      cz[k] = rec->cz;
     }
   }
   const int n_lo = (wave * N) / kWaves, n_hi = ((wave + 1) * N) / kWaves;
 
-  for (int tile = blockIdx.x; tile < a.tiles; tile += gridDim.x) {
+  for (int tile = a.lb; tile < a.tiles; tile += a.nb) {
     const int32_t q = tile * kTile + lane;
     const bool valid = q < a.ps.count;
-    if (FROM_PHI) {
+    if (a.from_phi) {
       if (wave == 0) {
         float4 rec = make_float4(0.f, 0.f, 0.f, 0.f);
         float ui = 0.f;
@@ -403,7 +435,7 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
           const int32_t p = pixel_of(a.ps, q);
           const PixCoord c = pixel_coord(p, a.W, a.H);
           float sn, cs;
-          sincos_turns(a.phi[p] * 0.15915494309189535f, sn, cs);
+          sincos_turns(as_global(a.phi)[p] * 0.15915494309189535f, sn, cs);
           rec = make_float4(c.Lx, c.Ly, c.Q, cs);
           ui = sn;
         }
@@ -414,17 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
     } else {
       PixCoord c{0.f, 0.f, 0.f};
       if (valid) c = pixel_coord(pixel_of(a.ps, q), a.W, a.H);
-      float sr = 0.f, si = 0.f;
-#pragma unroll 4
-      for (int n = n_lo; n < n_hi; ++n) {
-        const SpotRec s = sp[n];
-        const float t = fmaf(s.cx, c.Lx, fmaf(s.cy, c.Ly, fmaf(s.cz, c.Q, s.th)));
-        float sn, cs;
-        sincos_turns(t, sn, cs);
-        sr = fmaf(s.A, cs, sr);
-        si = fmaf(s.A, sn, si);
-      }
-      sw[wave][lane] = make_float2(sr, si);
+      sw[wave][lane] = backprop_field(sp, n_lo, n_hi, c);
       __syncthreads();
       if (wave == 0) {
         float4 rec = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -456,7 +478,8 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
       if (u < lm.U) {
         const int sl = u % lm.S;
         const int j0 = (sl * kTile) / lm.S + r, j1 = ((sl + 1) * kTile) / lm.S;
-        for (int j = j0; j < j1; j += lm.R) forward_term(cx[k], cy[k], cz[k], px[j], pui[j], vr[k], vi[k]);
+        for (int j = j0; j < j1; j += lm.R)
+          forward_term(cx[k], cy[k], cz[k], px[j], pui[j], vr[k], vi[k]);
       }
     }
     __syncthreads();
@@ -480,20 +503,59 @@ __global__ __launch_bounds__(kBlock) void k_pass(PassArgs a) {
         acc.x += v.x;
         acc.y += v.y;
       }
-    store_dev(a.partial + (int64_t)blockIdx.x * N + n, acc);
+    store_dev(a.partial + (int64_t)a.lb * N + n, acc);
   }
   pass_tail(a);
 }
 
+// Batched pass launch: blocks [descs[i].block_begin, descs[i+1].block_begin)
+// work on pass i.
+template <int MAXU>
+__global__ __launch_bounds__(kBlock) void k_pass_batch(const JobDev* __restrict__ jobs,
+                                                       const PassDesc* __restrict__ descs,
+                                                       int ndesc) {
+  __shared__ float2 sw[kWaves][kTile];
+  __shared__ float4 px[kTile];
+  __shared__ float pui[kTile];
+  __shared__ float2 red[kWaves * MAXU][64];
+  const int di = find_desc(descs, ndesc, blockIdx.x);
+  const PassDesc& d = descs[di];
+  const JobDev& jb = jobs[d.job];
+  PassCtx a;
+  a.sp = jb.sp;
+  a.N = jb.N;
+  a.W = jb.W;
+  a.H = jb.H;
+  a.ps = d.ps;
+  a.phi = jb.phi;
+  a.tiles = d.plan.tiles;
+  a.group_size = d.plan.group_size;
+  a.ngroups = d.plan.ngroups;
+  a.lb = blockIdx.x - d.block_begin;
+  a.nb = d.plan.blocks;
+  a.partial = jb.partial;
+  a.gpart = jb.gpart;
+  a.counters = jb.counters;
+  a.inv_count = d.inv_count;
+  a.V = d.V;
+  a.status = jb.status;
+  a.update = d.update;
+  a.from_phi = d.from_phi;
+  pass_block<MAXU>(a, sw, px, pui, red);
+}
+
 // Final hologram on a pixel set: Phi = atan2(Im S, Re S), written to out[q].
-__global__ __launch_bounds__(kBlock) void k_backprop_phi(const SpotRec* __restrict__ sp, int N,
-                                                         int W, int H, PixelSet ps,
-                                                         float* __restrict__ out) {
-  const int32_t q = blockIdx.x * kBlock + threadIdx.x;
-  if (q >= ps.count) return;
-  const PixCoord c = pixel_coord(pixel_of(ps, q), W, H);
-  const float2 S = backprop_field(sp, N, c);
-  out[q] = atan2f(S.y, S.x);
+__global__ __launch_bounds__(kBlock) void k_backprop_batch(const JobDev* __restrict__ jobs,
+                                                           const BackDesc* __restrict__ descs,
+                                                           int ndesc) {
+  const int di = find_desc(descs, ndesc, blockIdx.x);
+  const BackDesc& d = descs[di];
+  const JobDev& jb = jobs[d.job];
+  const int32_t q = (blockIdx.x - d.block_begin) * kBlock + threadIdx.x;
+  if (q >= d.ps.count) return;
+  const PixCoord c = pixel_coord(pixel_of(d.ps, q), jb.W, jb.H);
+  const float2 S = backprop_field(jb.sp, 0, jb.N, c);
+  as_global_mut(d.out)[q] = atan2f(S.y, S.x);
 }
 
 // -------------------------------------------------------------- metrics ---
@@ -581,13 +643,48 @@ __global__ void k_metric_reduce(const double2* __restrict__ partial, int nblk, i
   V[n] = make_double2(re * inv_count, im * inv_count);
 }
 
+
 }  // namespace
 
 // ------------------------------------------------------------ launchers ---
 
-void launch_setup(const SetupArgs& a, const SpotPtrs& in, SpotRec* sp, double* th0,
-                  int32_t* status, hipStream_t s) {
-  hipLaunchKernelGGL(k_setup, dim3(ceil_div(a.N, 256)), dim3(256), 0, s, a, in, sp, th0, status);
+PassPlan plan_pass(int32_t count, int32_t block_cap) {
+  PassPlan p;
+  p.tiles = ceil_div(count, kTile);
+  if (p.tiles < 1) p.tiles = 1;
+  p.blocks = p.tiles < block_cap ? p.tiles : block_cap;
+  if (p.blocks < 1) p.blocks = 1;
+  int gs = 1;
+  while (gs * gs < p.blocks) ++gs;
+  p.group_size = gs;
+  p.ngroups = ceil_div(p.blocks, gs);
+  return p;
+}
+
+int setup_table_blocks(int max_h) {
+  if (max_h <= 0) return 0;
+  const int total = kFeistelRounds << max_h;
+  int b = ceil_div(total, 256 * 4);
+  return b > 64 ? 64 : b;
+}
+
+void launch_setup_batch(const JobDev* jobs, int njobs, int max_h, hipStream_t s) {
+  if (njobs <= 0) return;
+  hipLaunchKernelGGL(k_setup_batch, dim3(njobs, 1 + setup_table_blocks(max_h)), dim3(256), 0, s,
+                     jobs);
+}
+
+int perm_blocks(int32_t M) { return ceil_div(M, (int64_t)kPermThreads * kPermPerThread); }
+
+void launch_perm_batch(const JobDev* jobs, const JobSlice* slices, int nslices, int total_blocks,
+                       bool lds, hipStream_t s) {
+  if (nslices <= 0 || total_blocks <= 0) return;
+  if (lds)
+    hipLaunchKernelGGL(k_perm_batch<true>, dim3(total_blocks), dim3(kPermThreads), 0, s, jobs,
+                       slices, nslices);
+  else
+    hipLaunchKernelGGL(k_perm_batch<false>, dim3(total_blocks), dim3(kPermThreads), 0, s, jobs,
+                       slices, nslices);
 }
 
 void launch_theta0(uint64_t seed, int count, double* out, hipStream_t s) {
@@ -598,89 +695,32 @@ void launch_set_state(int N, const double* wth, SpotRec* sp, hipStream_t s) {
   hipLaunchKernelGGL(k_set_state, dim3(ceil_div(N, 256)), dim3(256), 0, s, N, wth, sp);
 }
 
-void launch_tables(uint64_t seed, int h, uint32_t* tab, hipStream_t s) {
-  const int total = kFeistelRounds << h;
-  hipLaunchKernelGGL(k_tables, dim3(ceil_div(total, 256)), dim3(256), 0, s, seed, h, tab);
-}
-
-void launch_perm(int32_t M, int h, const uint32_t* tab, int32_t* perm, hipStream_t s) {
-  if (h <= kPermLdsHalfBits) {
-    int blocks = ceil_div(M, kPermThreads * 4);
-    blocks = blocks < 1 ? 1 : (blocks > 1024 ? 1024 : blocks);
-    hipLaunchKernelGGL(k_perm_lds, dim3(blocks), dim3(kPermThreads), 0, s, M, h, tab, perm);
-  } else {
-    hipLaunchKernelGGL(k_perm, dim3(ceil_div(M, 256)), dim3(256), 0, s, M, h, tab, perm);
-  }
-}
-
 void launch_gather(const PixelSet& ps, int32_t* out, hipStream_t s) {
   if (ps.count <= 0) return;
   hipLaunchKernelGGL(k_gather, dim3(ceil_div(ps.count, 256)), dim3(256), 0, s, ps, out);
 }
 
-int pass_tiles(int32_t count) { return ceil_div(count, kTile); }
-
-PassPlan plan_pass(int32_t count) {
-  PassPlan p;
-  p.tiles = pass_tiles(count);
-  // one tile per block while that gives up to 4096 blocks, then loop
-  p.blocks = p.tiles < 4096 ? p.tiles : 4096;
-  if (p.blocks < 1) p.blocks = 1;
-  int gs = 1;
-  while (gs * gs < p.blocks) ++gs;
-  p.group_size = gs;
-  p.ngroups = ceil_div(p.blocks, gs);
-  return p;
-}
-
-void launch_pass(const PassPlan& plan, SpotRec* sp, int N, int W, int H, const PixelSet& ps,
-                 const float* phi, float2* partial, double2* gpart, unsigned* counters,
-                 double2* V, int32_t* status, bool update, hipStream_t s) {
-  PassArgs a;
-  a.sp = sp;
-  a.N = N;
-  a.W = W;
-  a.H = H;
-  a.ps = ps;
-  a.phi = phi;
-  a.tiles = plan.tiles;
-  a.group_size = plan.group_size;
-  a.ngroups = plan.ngroups;
-  a.partial = partial;
-  a.gpart = gpart;
-  a.counters = counters;
-  a.inv_count = 1.0 / (double)ps.count;
-  a.V = V;
-  a.status = status;
-  a.update = update ? 1 : 0;
-  const dim3 grid(plan.blocks), block(kBlock);
+int pass_units_per_wave(int N) {
   const LaneMap lm = lane_map(N);
-  const int units_per_wave = ceil_div(lm.U, kWaves);
-  if (phi) {
-    if (units_per_wave <= 1) hipLaunchKernelGGL((k_pass<1, true>), grid, block, 0, s, a);
-    else if (units_per_wave <= 4) hipLaunchKernelGGL((k_pass<4, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_pass<16, true>), grid, block, 0, s, a);
-  } else {
-    if (units_per_wave <= 1) hipLaunchKernelGGL((k_pass<1, false>), grid, block, 0, s, a);
-    else if (units_per_wave <= 4) hipLaunchKernelGGL((k_pass<4, false>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_pass<16, false>), grid, block, 0, s, a);
-  }
+  return ceil_div(lm.U, kWaves);
 }
 
-__global__ void k_zero_u32(unsigned* p, int n) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) p[k] = 0u;
+void launch_pass_batch(const JobDev* jobs, const PassDesc* descs, int ndesc, int total_blocks,
+                       int max_units, hipStream_t s) {
+  if (ndesc <= 0 || total_blocks <= 0) return;
+  const dim3 grid(total_blocks), block(kBlock);
+  if (max_units <= 1) hipLaunchKernelGGL(k_pass_batch<1>, grid, block, 0, s, jobs, descs, ndesc);
+  else if (max_units <= 4) hipLaunchKernelGGL(k_pass_batch<4>, grid, block, 0, s, jobs, descs, ndesc);
+  else hipLaunchKernelGGL(k_pass_batch<16>, grid, block, 0, s, jobs, descs, ndesc);
 }
 
-void launch_zero_counters(unsigned* counters, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_u32, dim3(ceil_div(n, 256)), dim3(256), 0, s, counters, n);
-}
+int backprop_blocks(int32_t count) { return ceil_div(count, kBlock); }
 
-void launch_backprop_phi(const SpotRec* sp, int N, int W, int H, const PixelSet& ps, float* out,
-                         hipStream_t s) {
-  if (ps.count <= 0) return;
-  hipLaunchKernelGGL(k_backprop_phi, dim3(ceil_div(ps.count, kBlock)), dim3(kBlock), 0, s, sp, N,
-                     W, H, ps, out);
+void launch_backprop_batch(const JobDev* jobs, const BackDesc* descs, int ndesc,
+                           int total_blocks, hipStream_t s) {
+  if (ndesc <= 0 || total_blocks <= 0) return;
+  hipLaunchKernelGGL(k_backprop_batch, dim3(total_blocks), dim3(kBlock), 0, s, jobs, descs,
+                     ndesc);
 }
 
 void launch_metric_tables(const SetupArgs& a, const SpotPtrs& in, double2* Ex, double2* Ey,

@@ -1,5 +1,11 @@
 // Internal interface between the kernels (kernels.hip) and the host runtime
-// (api.hip).  Nothing here is part of the public C ABI.
+// (runtime.hip, api.hip, engine.hip).  Nothing here is part of the C ABI.
+//
+// Every kernel works on a batch: a table of holograms ("jobs") resident in
+// device memory, and per launch a list of descriptors, each naming one job and
+// the slice of the grid that works on it.  A single hologram is a batch of
+// one.  The launch geometry of a job's pass depends only on that job, so a
+// hologram computed alone or inside any batch gives bit-identical results.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,28 +25,6 @@ struct alignas(32) SpotRec {
   float A, a0, w, pad;
 };
 
-// Optics and grid constants needed by the setup kernels.
-struct SetupArgs {
-  int32_t N;
-  int32_t W, H;
-  double pitch_mm, lambda_mm, focal_mm;
-  uint64_t seed;
-};
-
-constexpr int kBlock = 256;          // threads per block of the pixel kernels
-constexpr int kWaves = kBlock / 64;  // wave64s per block
-constexpr int kUpdateThreads = 1024;
-
-// Pixel set of a pass: either all pixels 0..count-1 (perm == nullptr) or
-// perm[(start + q) mod M] for q < count, or explicit indices idx[q].
-struct PixelSet {
-  const int32_t* perm;  // random order of [0, M) or nullptr
-  const int32_t* idx;   // explicit pixel list or nullptr
-  int64_t start;        // window start in the order (< M)
-  int32_t count;        // number of pixels in the set
-  int32_t M;            // W*H
-};
-
 // Device arrays of the N spot coordinates (mm) and target amplitudes.
 struct SpotPtrs {
   const double* x;
@@ -49,40 +33,109 @@ struct SpotPtrs {
   const double* amp;
 };
 
+constexpr int kBlock = 256;          // threads per block of the pixel kernels
+constexpr int kWaves = kBlock / 64;  // wave64s per block
+constexpr int kTile = 64;            // pixels per tile of a pass
+constexpr int kFeistelRoundsHost = 6;  // rounds of the pixel permutation
+
+// Launch geometry of one pass over `count` pixels.
+struct PassPlan {
+  int32_t tiles;       // ceil(count / kTile)
+  int32_t blocks;      // blocks of this pass; block b handles tiles b, b + blocks, ...
+  int32_t group_size;  // blocks per first-level reduction group
+  int32_t ngroups;
+};
+// One tile per block up to `block_cap` blocks, groups of ceil(sqrt(blocks)).
+PassPlan plan_pass(int32_t count, int32_t block_cap);
+constexpr int32_t kDefaultBlockCap = 4096;
+
+// One hologram resident on the device.
+struct JobDev {
+  int32_t W, H, N, M;
+  int32_t iterations;
+  int32_t m;           // pixels of a compressed pass (M if not compressed)
+  int32_t compressed;  // 1: passes 1..I-1 use windows of the random order
+  int32_t h;           // Feistel half width (compressed only)
+  uint64_t seed;
+  double pitch_mm, lambda_mm, focal_mm;
+  SpotPtrs in;         // spot inputs (device)
+  SpotRec* sp;         // [N] iteration state
+  uint32_t* tab;       // [6 << h] Feistel tables (compressed only)
+  int32_t* perm;       // [M] random pixel order (compressed only)
+  float* phi;          // [H][W] output hologram (or input of a forward test pass)
+  float2* partial;     // [max pass blocks][N]
+  double2* gpart;      // [max pass groups][N]
+  unsigned* counters;  // [max pass groups + 1]
+  int32_t counters_len;
+  int32_t trace;       // V is [iterations][N] instead of [N]
+  double2* V;
+  int32_t* status;     // sticky status word of the caller's stream
+};
+
+// Pixel set of a pass: all pixels 0..count-1 (perm == idx == nullptr),
+// perm[(start + q) mod M] for q < count, or explicit indices idx[q].
+struct PixelSet {
+  const int32_t* perm;
+  const int32_t* idx;
+  int64_t start;
+  int32_t count;
+  int32_t M;
+};
+
+// One pass of one job inside a batched launch.
+struct PassDesc {
+  int32_t block_begin;  // first block of the launch working on this pass
+  int32_t job;
+  PixelSet ps;
+  PassPlan plan;
+  int32_t update;       // apply eqs. (4)-(6) after the sums
+  int32_t from_phi;     // forward of job.phi instead of back-propagation
+  double inv_count;
+  double2* V;           // spot fields of this pass, [N]
+};
+
+// Final hologram of one job over a pixel set, written compactly to out[q].
+struct BackDesc {
+  int32_t block_begin;
+  int32_t job;
+  PixelSet ps;
+  float* out;
+};
+
+// One job's share of a batched setup / permutation launch.
+struct JobSlice {
+  int32_t block_begin;
+  int32_t job;
+};
+
 // ---- setup (FP64) ----
-void launch_setup(const SetupArgs& a, const SpotPtrs& in, SpotRec* sp,
-                  double* theta0_out /*nullable*/, int32_t* status, hipStream_t s);
+// Spot records, theta^0, state and pass counters of every job, plus the
+// Feistel tables of the compressed jobs; grid = njobs x (1 + table blocks).
+int setup_table_blocks(int max_h);
+void launch_setup_batch(const JobDev* jobs, int njobs, int max_h, hipStream_t s);
+// Random pixel order of the compressed jobs; slices[] maps blocks to jobs.
+int perm_blocks(int32_t M);
+void launch_perm_batch(const JobDev* jobs, const JobSlice* slices, int nslices, int total_blocks,
+                       bool lds, hipStream_t s);
 void launch_theta0(uint64_t seed, int count, double* out, hipStream_t s);
-void launch_set_state(int N, const double* wth /*w: N, theta: N*/, SpotRec* sp, hipStream_t s);
-void launch_tables(uint64_t seed, int h, uint32_t* tab, hipStream_t s);
-void launch_perm(int32_t M, int h, const uint32_t* tab, int32_t* perm, hipStream_t s);
+void launch_set_state(int N, const double* wth, SpotRec* sp, hipStream_t s);
 void launch_gather(const PixelSet& ps, int32_t* out, hipStream_t s);
 
 // ---- iteration ----
-// Launch geometry of one pass over `count` pixels (a function of count only,
-// so the summation order of a pass never depends on the batch or device).
-struct PassPlan {
-  int tiles;       // pixel tiles of 64
-  int blocks;      // grid size; block b handles tiles b, b + blocks, ...
-  int group_size;  // blocks per first-level reduction group
-  int ngroups;
-};
-PassPlan plan_pass(int32_t count);
-// One pass: back-propagation of the state in `sp` (or, with phi != nullptr,
-// the stored hologram phi) on the pixel set, forward projection over the same
-// set, deterministic reduction to V (N complex, FP64) and, if `update`, the
-// weight update of eqs. (4)-(6) written back to sp.  `counters` must be zero
-// on entry (ngroups + 1 words) and is zero again when the pass ends.
-void launch_pass(const PassPlan& plan, SpotRec* sp, int N, int W, int H, const PixelSet& ps,
-                 const float* phi, float2* partial, double2* gpart, unsigned* counters,
-                 double2* V, int32_t* status, bool update, hipStream_t s);
-void launch_zero_counters(unsigned* counters, int n, hipStream_t s);
-// Final hologram: Phi = arg(sum_n A_n e^{i 2 pi (t_n + th_n)}) on the set,
-// written compactly (out[q]) or, for all pixels, at out[p].
-void launch_backprop_phi(const SpotRec* sp, int N, int W, int H, const PixelSet& ps, float* out,
-                         hipStream_t s);
+// Units of phase-2 work per wave for N spots (selects the kernel variant).
+int pass_units_per_wave(int N);
+void launch_pass_batch(const JobDev* jobs, const PassDesc* descs, int ndesc, int total_blocks,
+                       int max_units, hipStream_t s);
+void launch_backprop_batch(const JobDev* jobs, const BackDesc* descs, int ndesc,
+                           int total_blocks, hipStream_t s);
+int backprop_blocks(int32_t count);
 
 // ---- metrics (FP64) ----
+struct SetupArgs {
+  int32_t N;
+  int32_t W, H;
+  double pitch_mm, lambda_mm, focal_mm;
+};
 void launch_metric_tables(const SetupArgs& a, const SpotPtrs& in, double2* Ex, double2* Ey,
                           hipStream_t s);
 int metric_blocks(int H);

@@ -1,0 +1,475 @@
+// Host runtime of libhg: error state, staging, validation, batch planning and
+// the RS / WGS / CS-WGS schedules (paper section 2) as batched launches.
+#include "runtime.hpp"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+
+namespace hg {
+
+// ------------------------------------------------------------------ errors --
+
+namespace {
+thread_local std::string g_err;
+}
+
+hg_status set_error(hg_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+const char* last_error() { return g_err.c_str(); }
+
+// ----------------------------------------------------------------- staging --
+
+hg_status Staging::acquire(size_t bytes) {
+  if (pending) {
+    HG_HIP(hipEventSynchronize(done));
+    pending = false;
+  }
+  if (bytes > cap) {
+    if (p) HG_HIP(hipHostFree(p));
+    p = nullptr;
+    cap = 0;
+    HG_HIP(hipHostMalloc((void**)&p, bytes, hipHostMallocDefault));
+    cap = bytes;
+  }
+  if (!done) HG_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+  return HG_OK;
+}
+
+hg_status Staging::mark_copied(hipStream_t s) {
+  HG_HIP(hipEventRecord(done, s));
+  pending = true;
+  return HG_OK;
+}
+
+void Staging::release() {
+  if (pending && done) (void)hipEventSynchronize(done);
+  if (p) (void)hipHostFree(p);
+  if (done) (void)hipEventDestroy(done);
+  p = nullptr;
+  cap = 0;
+  done = nullptr;
+  pending = false;
+}
+
+// -------------------------------------------------------------- validation --
+
+namespace {
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+}  // namespace
+
+hg_status validate_grid(const hg_grid* g) {
+  if (!g) return set_error(HG_EINVAL, "grid must be non-NULL");
+  if (g->W < 1 || g->H < 1 || g->W > 8192 || g->H > 8192)
+    return set_error(HG_EINVAL, "grid W and H must be in [1, 8192]");
+  if (!finite_pos(g->pitch_mm)) return set_error(HG_EINVAL, "pitch_mm must be positive and finite");
+  return HG_OK;
+}
+
+hg_status validate_spec(const hg_grid* g, const hg_optics* o, const hg_spots* s, bool on_device) {
+  if (!g || !o || !s) return set_error(HG_EINVAL, "grid, optics and spots must be non-NULL");
+  HG_TRY(validate_grid(g));
+  if (!finite_pos(o->lambda_mm) || !finite_pos(o->focal_mm))
+    return set_error(HG_EINVAL, "lambda_mm and focal_mm must be positive and finite");
+  if (s->n < 1 || s->n > HG_MAX_SPOTS)
+    return set_error(HG_EINVAL, "spot count must be in [1, HG_MAX_SPOTS]");
+  if (!s->x_mm || !s->y_mm || !s->z_mm || !s->amp)
+    return set_error(HG_EINVAL, "spot arrays must be non-NULL");
+  if (on_device) return HG_OK;  // values are checked by the setup kernel
+  for (int n = 0; n < s->n; ++n) {
+    if (!std::isfinite(s->x_mm[n]) || !std::isfinite(s->y_mm[n]) || !std::isfinite(s->z_mm[n]))
+      return set_error(HG_EINVAL, "spot coordinates must be finite");
+    if (!finite_pos(s->amp[n]))
+      return set_error(HG_EINVAL, "spot amplitudes must be positive and finite");
+  }
+  return HG_OK;
+}
+
+hg_status make_spec(const hg_grid* g, const hg_optics* o, const hg_spots* s, int32_t iterations,
+                    double compression, uint64_t seed, uint32_t flags, float* phi,
+                    double* trace_host, JobSpec* out) {
+  const bool on_device = (flags & HG_SPOTS_ON_DEVICE) != 0;
+  HG_TRY(validate_spec(g, o, s, on_device));
+  if (iterations < 0 || iterations > HG_MAX_ITERATIONS)
+    return set_error(HG_EINVAL, "iterations must be in [0, HG_MAX_ITERATIONS]");
+  JobSpec j;
+  j.W = g->W;
+  j.H = g->H;
+  j.pitch_mm = g->pitch_mm;
+  j.lambda_mm = o->lambda_mm;
+  j.focal_mm = o->focal_mm;
+  j.N = s->n;
+  j.x = s->x_mm;
+  j.y = s->y_mm;
+  j.z = s->z_mm;
+  j.amp = s->amp;
+  j.spots_on_device = on_device;
+  j.iterations = iterations;
+  j.compression = compression;
+  j.seed = seed;
+  j.precision = flags & HG_PREC_MASK;
+  j.phi = phi;
+  j.trace_host = trace_host;
+  *out = j;
+  return HG_OK;
+}
+
+// ------------------------------------------------------------------ timing --
+
+namespace {
+std::atomic<bool> g_timing{false};
+struct TimedLaunch {
+  const char* name;
+  hipEvent_t start, stop;
+};
+struct Totals {
+  double ms = 0.0;
+  int64_t launches = 0;
+};
+std::mutex g_tmu;
+std::vector<TimedLaunch> g_pending;
+std::map<std::string, Totals> g_totals;
+std::vector<hipEvent_t> g_pool;
+
+hipEvent_t pool_event() {
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void drain_locked() {
+  for (const TimedLaunch& t : g_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(t.stop) == hipSuccess &&
+        hipEventElapsedTime(&ms, t.start, t.stop) == hipSuccess) {
+      Totals& tt = g_totals[t.name];
+      tt.ms += ms;
+      tt.launches += 1;
+    }
+    g_pool.push_back(t.start);
+    g_pool.push_back(t.stop);
+  }
+  g_pending.clear();
+}
+}  // namespace
+
+bool timing_enabled() { return g_timing.load(std::memory_order_relaxed); }
+void timing_enable(bool on) { g_timing.store(on); }
+
+hipEvent_t timing_start(hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  hipEvent_t e = pool_event();
+  if (e) (void)hipEventRecord(e, s);
+  return e;
+}
+
+void timing_stop(hipStream_t s, const char* name, hipEvent_t start) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  if (!start) return;
+  hipEvent_t e = pool_event();
+  if (!e) return;
+  (void)hipEventRecord(e, s);
+  g_pending.push_back(TimedLaunch{name, start, e});
+}
+
+hg_status timing_reset() {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  drain_locked();
+  g_totals.clear();
+  return HG_OK;
+}
+
+hg_status timing_read(const char* name, double* total_ms, int64_t* launches) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  drain_locked();
+  auto it = g_totals.find(name);
+  *total_ms = it == g_totals.end() ? 0.0 : it->second.ms;
+  *launches = it == g_totals.end() ? 0 : it->second.launches;
+  return HG_OK;
+}
+
+// ------------------------------------------------------------------- batch --
+
+namespace {
+
+int half_bits(int64_t M) {
+  int h = 1;
+  while ((int64_t(1) << (2 * h)) < M) ++h;
+  return h;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+PixelSet all_pixels(int32_t M) {
+  PixelSet ps;
+  ps.perm = nullptr;
+  ps.idx = nullptr;
+  ps.start = 0;
+  ps.count = M;
+  ps.M = M;
+  return ps;
+}
+
+}  // namespace
+
+hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
+                       int32_t* status_dev) {
+  specs_.assign(specs, specs + count);
+  jobs_.assign(count, JobDev{});
+  struct Off {
+    size_t sp, tab, perm, partial, gpart, counters, V;
+  };
+  std::vector<Off> off(count);
+  std::vector<PassPlan> plan_all(count), plan_sub(count);
+  std::vector<size_t> raw_off(count, 0);
+  size_t bytes = 0;
+  auto take = [&](size_t n) {
+    bytes = align_up(bytes, 256);
+    const size_t o = bytes;
+    bytes += n;
+    return o;
+  };
+  // host-resident spot inputs first, contiguous, so that one copy moves them
+  host_spot_bytes_ = 0;
+  for (int i = 0; i < count; ++i)
+    if (!specs[i].spots_on_device) {
+      raw_off[i] = host_spot_bytes_;
+      host_spot_bytes_ += sizeof(double) * 4 * (size_t)specs[i].N;
+    }
+  const size_t raw_base = take(host_spot_bytes_);
+  int max_rounds = 0;
+  max_h_ = 0;
+  perm_lds_ = true;
+  for (int i = 0; i < count; ++i) {
+    const JobSpec& s = specs[i];
+    JobDev& j = jobs_[i];
+    j.W = s.W;
+    j.H = s.H;
+    j.N = s.N;
+    j.M = s.W * s.H;
+    j.iterations = s.iterations;
+    j.compressed = (s.compression > 0.0 && s.iterations >= 2) ? 1 : 0;
+    j.m = j.compressed ? (int32_t)std::ceil(s.compression * (double)j.M) : j.M;
+    j.h = j.compressed ? half_bits(j.M) : 0;
+    j.seed = s.seed;
+    j.pitch_mm = s.pitch_mm;
+    j.lambda_mm = s.lambda_mm;
+    j.focal_mm = s.focal_mm;
+    j.phi = s.phi;
+    j.trace = s.trace_host ? 1 : 0;
+    j.status = status_dev;
+    plan_all[i] = plan_pass(j.M, tp.full_block_cap);
+    plan_sub[i] = j.compressed ? plan_pass(j.m, tp.subset_block_cap) : plan_all[i];
+    const int max_blocks = std::max(plan_all[i].blocks, plan_sub[i].blocks);
+    const int max_groups = std::max(plan_all[i].ngroups, plan_sub[i].ngroups);
+    j.counters_len = max_groups + 1;
+    off[i].sp = take(sizeof(SpotRec) * (size_t)s.N);
+    off[i].tab = j.compressed ? take(sizeof(uint32_t) * ((size_t)kFeistelRoundsHost << j.h)) : 0;
+    off[i].perm = j.compressed ? take(sizeof(int32_t) * (size_t)j.M) : 0;
+    off[i].partial = take(sizeof(float2) * (size_t)max_blocks * s.N);
+    off[i].gpart = take(sizeof(double2) * (size_t)max_groups * s.N);
+    off[i].counters = take(sizeof(unsigned) * (size_t)j.counters_len);
+    off[i].V = take(sizeof(double2) * (size_t)s.N *
+                    (s.trace_host && s.iterations > 0 ? s.iterations : 1));
+    max_rounds = std::max(max_rounds, s.iterations);
+    if (j.compressed) {
+      max_h_ = std::max(max_h_, j.h);
+      if (j.h > 11) perm_lds_ = false;
+    }
+  }
+  HG_TRY(arena_.reserve(std::max<size_t>(bytes, 256)));
+  char* base = arena_.p;
+  for (int i = 0; i < count; ++i) {
+    const JobSpec& s = specs[i];
+    JobDev& j = jobs_[i];
+    if (s.spots_on_device) {
+      j.in = SpotPtrs{s.x, s.y, s.z, s.amp};
+    } else {
+      const double* r = reinterpret_cast<const double*>(base + raw_base + raw_off[i]);
+      j.in = SpotPtrs{r, r + s.N, r + 2 * s.N, r + 3 * s.N};
+    }
+    j.sp = reinterpret_cast<SpotRec*>(base + off[i].sp);
+    j.tab = j.compressed ? reinterpret_cast<uint32_t*>(base + off[i].tab) : nullptr;
+    j.perm = j.compressed ? reinterpret_cast<int32_t*>(base + off[i].perm) : nullptr;
+    j.partial = reinterpret_cast<float2*>(base + off[i].partial);
+    j.gpart = reinterpret_cast<double2*>(base + off[i].gpart);
+    j.counters = reinterpret_cast<unsigned*>(base + off[i].counters);
+    j.V = reinterpret_cast<double2*>(base + off[i].V);
+  }
+  // iteration rounds: round r runs iteration r + 1 of every job with I > r
+  pass_.clear();
+  round_first_.clear();
+  round_count_.clear();
+  round_blocks_.clear();
+  round_units_.clear();
+  round_kind_.clear();
+  for (int r = 0; r < max_rounds; ++r) {
+    const int first = (int)pass_.size();
+    int blocks = 0, units = 1;
+    bool any_sub = false, any_full = false;
+    for (int i = 0; i < count; ++i) {
+      const JobDev& j = jobs_[i];
+      if (r >= j.iterations) continue;
+      const int it = r + 1;
+      const bool sub = j.compressed && it < j.iterations;
+      PassDesc d;
+      d.block_begin = blocks;
+      d.job = i;
+      d.ps = all_pixels(j.M);
+      if (sub) {
+        d.ps.perm = j.perm;
+        d.ps.start = (int64_t)(it - 1) * j.m % j.M;
+        d.ps.count = j.m;
+      }
+      d.plan = sub ? plan_sub[i] : plan_all[i];
+      d.update = 1;
+      d.from_phi = 0;
+      d.inv_count = 1.0 / (double)d.ps.count;
+      d.V = j.V + (j.trace ? (size_t)(it - 1) * j.N : 0);
+      blocks += d.plan.blocks;
+      units = std::max(units, pass_units_per_wave(j.N));
+      (sub ? any_sub : any_full) = true;
+      pass_.push_back(d);
+    }
+    round_first_.push_back(first);
+    round_count_.push_back((int)pass_.size() - first);
+    round_blocks_.push_back(blocks);
+    round_units_.push_back(units);
+    round_kind_.push_back(any_sub && any_full ? kRoundMixed : any_sub ? kRoundSubset : kRoundFull);
+  }
+  back_.clear();
+  back_blocks_ = 0;
+  perm_.clear();
+  perm_blocks_ = 0;
+  for (int i = 0; i < count; ++i) {
+    const JobDev& j = jobs_[i];
+    if (j.phi) {
+      BackDesc b;
+      b.block_begin = back_blocks_;
+      b.job = i;
+      b.ps = all_pixels(j.M);
+      b.out = j.phi;
+      back_.push_back(b);
+      back_blocks_ += backprop_blocks(j.M);
+    }
+    if (j.compressed) {
+      perm_.push_back(JobSlice{perm_blocks_, i});
+      perm_blocks_ += perm_blocks(j.M);
+    }
+  }
+  // descriptor tables: [JobDev][PassDesc][BackDesc][JobSlice]
+  size_t tb = 0;
+  const size_t t_jobs = tb;
+  tb = align_up(tb + sizeof(JobDev) * count, 256);
+  const size_t t_pass = tb;
+  tb = align_up(tb + sizeof(PassDesc) * pass_.size(), 256);
+  const size_t t_back = tb;
+  tb = align_up(tb + sizeof(BackDesc) * back_.size(), 256);
+  const size_t t_perm = tb;
+  tb = align_up(tb + sizeof(JobSlice) * perm_.size(), 256);
+  table_bytes_ = tb;
+  HG_TRY(table_.reserve(std::max<size_t>(tb, 256)));
+  jobs_dev_ = reinterpret_cast<JobDev*>(table_.p + t_jobs);
+  pass_dev_ = reinterpret_cast<PassDesc*>(table_.p + t_pass);
+  back_dev_ = reinterpret_cast<BackDesc*>(table_.p + t_back);
+  perm_dev_ = reinterpret_cast<JobSlice*>(table_.p + t_perm);
+  HG_TRY(staging_.acquire(tb + host_spot_bytes_));
+  std::memset(staging_.p, 0, tb);
+  std::memcpy(staging_.p + t_jobs, jobs_.data(), sizeof(JobDev) * count);
+  if (!pass_.empty()) std::memcpy(staging_.p + t_pass, pass_.data(), sizeof(PassDesc) * pass_.size());
+  if (!back_.empty()) std::memcpy(staging_.p + t_back, back_.data(), sizeof(BackDesc) * back_.size());
+  if (!perm_.empty()) std::memcpy(staging_.p + t_perm, perm_.data(), sizeof(JobSlice) * perm_.size());
+  for (int i = 0; i < count; ++i) {
+    const JobSpec& s = specs[i];
+    if (s.spots_on_device) continue;
+    double* dst = reinterpret_cast<double*>(staging_.p + tb + raw_off[i]);
+    std::memcpy(dst, s.x, sizeof(double) * s.N);
+    std::memcpy(dst + s.N, s.y, sizeof(double) * s.N);
+    std::memcpy(dst + 2 * s.N, s.z, sizeof(double) * s.N);
+    std::memcpy(dst + 3 * s.N, s.amp, sizeof(double) * s.N);
+  }
+  raw_base_ = raw_base;
+  return HG_OK;
+}
+
+hg_status Batch::enqueue_prologue(hipStream_t s) {
+  HG_HIP(hipMemcpyAsync(table_.p, staging_.p, table_bytes_, hipMemcpyHostToDevice, s));
+  if (host_spot_bytes_)
+    HG_HIP(hipMemcpyAsync(arena_.p + raw_base_, staging_.p + table_bytes_, host_spot_bytes_,
+                          hipMemcpyHostToDevice, s));
+  HG_TRY(staging_.mark_copied(s));
+  timed(s, "k_setup", [&] { launch_setup_batch(jobs_dev_, count(), max_h_, s); });
+  if (perm_blocks_ > 0)
+    timed(s, "k_perm", [&] {
+      launch_perm_batch(jobs_dev_, perm_dev_, (int)perm_.size(), perm_blocks_, perm_lds_, s);
+    });
+  return HG_OK;
+}
+
+hg_status Batch::enqueue(hipStream_t s) {
+  HG_TRY(enqueue_prologue(s));
+  static const char* kNames[] = {"k_pass_subset", "k_pass_full", "k_pass_mixed"};
+  for (size_t r = 0; r < round_first_.size(); ++r) {
+    timed(s, kNames[round_kind_[r]], [&] {
+      launch_pass_batch(jobs_dev_, pass_dev_ + round_first_[r], round_count_[r], round_blocks_[r],
+                        round_units_[r], s);
+    });
+  }
+  if (!back_.empty())
+    timed(s, "k_backprop_phi", [&] {
+      launch_backprop_batch(jobs_dev_, back_dev_, (int)back_.size(), back_blocks_, s);
+    });
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    return set_error(HG_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+  return HG_OK;
+}
+
+hg_status Batch::fetch_traces(hipStream_t s) {
+  bool any = false;
+  for (size_t i = 0; i < specs_.size(); ++i) {
+    const JobSpec& sp = specs_[i];
+    if (!sp.trace_host || sp.iterations <= 0) continue;
+    HG_HIP(hipMemcpyAsync(sp.trace_host, jobs_[i].V,
+                          sizeof(double2) * (size_t)sp.N * sp.iterations, hipMemcpyDeviceToHost,
+                          s));
+    any = true;
+  }
+  if (any) HG_HIP(hipStreamSynchronize(s));
+  return HG_OK;
+}
+
+hg_status Batch::upload_custom(const void* bytes, size_t size, hipStream_t s, void** dev) {
+  HG_TRY(custom_staging_.acquire(size));
+  std::memcpy(custom_staging_.p, bytes, size);
+  HG_TRY(custom_.reserve(size));
+  HG_HIP(hipMemcpyAsync(custom_.p, custom_staging_.p, size, hipMemcpyHostToDevice, s));
+  HG_TRY(custom_staging_.mark_copied(s));
+  *dev = custom_.p;
+  return HG_OK;
+}
+
+void Batch::release() {
+  staging_.release();
+  custom_staging_.release();
+  arena_.release();
+  table_.release();
+  custom_.release();
+  jobs_dev_ = nullptr;
+  pass_dev_ = nullptr;
+  back_dev_ = nullptr;
+  perm_dev_ = nullptr;
+}
+
+}  // namespace hg

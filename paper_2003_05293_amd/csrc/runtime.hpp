@@ -1,0 +1,162 @@
+// Host runtime of libhg: device buffers, batch planning and the RS / WGS /
+// CS-WGS schedules (paper section 2) enqueued as batched launches.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "hg.h"
+#include "kernels.hpp"
+
+namespace hg {
+
+// Thread-local error message of the C ABI.
+hg_status set_error(hg_status st, const std::string& msg);
+const char* last_error();
+
+#define HG_HIP(expr)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return ::hg::set_error(e_ == hipErrorOutOfMemory ? HG_ENOMEM : HG_EDEVICE,     \
+                             std::string(#expr) + " failed: " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define HG_TRY(expr)              \
+  do {                            \
+    hg_status st_ = (expr);       \
+    if (st_ != HG_OK) return st_; \
+  } while (0)
+
+// Device buffer that grows on demand and is never shrunk.  Growing waits for
+// the device first: queued kernels may still be reading the old buffer.
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t cap = 0;
+  hg_status reserve(size_t n) {
+    if (n <= cap) return HG_OK;
+    if (p) HG_HIP(hipDeviceSynchronize());
+    release();
+    HG_HIP(hipMalloc((void**)&p, n * sizeof(T)));
+    cap = n;
+    return HG_OK;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+};
+
+// Pinned host staging area whose refill waits for the copy that last read it.
+struct Staging {
+  char* p = nullptr;
+  size_t cap = 0;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+  hg_status acquire(size_t bytes);             // waits for the previous copy, grows
+  hg_status mark_copied(hipStream_t s);        // records the event after the copies
+  void release();
+};
+
+// Host description of one hologram.
+struct JobSpec {
+  int32_t W = 0, H = 0;
+  double pitch_mm = 0, lambda_mm = 0, focal_mm = 0;
+  int32_t N = 0;
+  const double *x = nullptr, *y = nullptr, *z = nullptr, *amp = nullptr;
+  bool spots_on_device = false;
+  int32_t iterations = 0;
+  double compression = -1.0;  // <= 0: plain WGS (no random order)
+  uint64_t seed = 0;
+  uint32_t precision = HG_PREC_FP32;
+  float* phi = nullptr;       // output hologram (device)
+  double* trace_host = nullptr;
+};
+
+// Launch-geometry parameters (chosen per shape by the autotuner).
+struct TuneParams {
+  int32_t full_block_cap = kDefaultBlockCap;
+  int32_t subset_block_cap = kDefaultBlockCap;
+};
+
+// Validation of the host-visible parts of a hologram description.
+hg_status validate_grid(const hg_grid* g);
+hg_status validate_spec(const hg_grid* g, const hg_optics* o, const hg_spots* s, bool on_device);
+hg_status make_spec(const hg_grid* g, const hg_optics* o, const hg_spots* s, int32_t iterations,
+                    double compression, uint64_t seed, uint32_t flags, float* phi,
+                    double* trace_host, JobSpec* out);
+
+// Kernel timing (hg_timing_*).  While enabled, `timed` brackets a launch
+// with two events recorded on its stream; hg_timing_read drains them.
+bool timing_enabled();
+void timing_enable(bool on);
+hipEvent_t timing_start(hipStream_t s);
+void timing_stop(hipStream_t s, const char* name, hipEvent_t start);
+hg_status timing_reset();
+hg_status timing_read(const char* name, double* total_ms, int64_t* launches);
+
+template <typename F>
+void timed(hipStream_t s, const char* name, F&& launch) {
+  if (!timing_enabled()) {
+    launch();
+    return;
+  }
+  hipEvent_t a = timing_start(s);
+  launch();
+  timing_stop(s, name, a);
+}
+
+// A batch of holograms planned for one launch sequence.  Plans, device
+// scratch and the descriptor tables are kept and reused by later builds.
+class Batch {
+ public:
+  // Plans the jobs and lays out their scratch; allocates as needed.
+  hg_status build(const JobSpec* specs, int count, const TuneParams& tp, int32_t* status_dev);
+  // Uploads the tables (and host spot arrays), then the whole schedule:
+  // setup, random orders, one pass launch per iteration round, final phase.
+  hg_status enqueue(hipStream_t s);
+  // Setup and random orders only (for the single-step calls).
+  hg_status enqueue_prologue(hipStream_t s);
+  // Copies the traces of the jobs that asked for one and waits for them.
+  hg_status fetch_traces(hipStream_t s);
+
+  int count() const { return (int)specs_.size(); }
+  const JobDev& job(int i) const { return jobs_[i]; }
+  const JobDev* jobs_device() const { return jobs_dev_; }
+  // A descriptor area on the device for ad-hoc single launches.
+  hg_status upload_custom(const void* bytes, size_t size, hipStream_t s, void** dev);
+  void release();
+
+ private:
+  std::vector<JobSpec> specs_;
+  std::vector<JobDev> jobs_;
+  std::vector<PassDesc> pass_;          // every round's descriptors, concatenated
+  std::vector<int> round_first_, round_count_, round_blocks_, round_units_, round_kind_;
+  std::vector<BackDesc> back_;
+  int back_blocks_ = 0;
+  std::vector<JobSlice> perm_;
+  int perm_blocks_ = 0;
+  bool perm_lds_ = true;
+  int max_h_ = 0;
+  size_t host_spot_bytes_ = 0;
+  size_t raw_base_ = 0;
+  DevBuf<char> arena_;
+  DevBuf<char> table_;
+  DevBuf<char> custom_;
+  JobDev* jobs_dev_ = nullptr;
+  PassDesc* pass_dev_ = nullptr;
+  BackDesc* back_dev_ = nullptr;
+  JobSlice* perm_dev_ = nullptr;
+  size_t table_bytes_ = 0;
+  Staging staging_;
+  Staging custom_staging_;
+};
+
+// Round kinds for timing tags.
+enum RoundKind { kRoundSubset = 0, kRoundFull = 1, kRoundMixed = 2 };
+
+}  // namespace hg
