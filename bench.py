@@ -85,6 +85,54 @@ def cpu_baseline(grid, optics, spots, seed):
     }
 
 
+def _time_batch(torch, batch, stream, runs):
+    batch.run(stream)
+    stream.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(runs):
+        batch.run(stream)
+    b.record(stream)
+    stream.synchronize()
+    return a.elapsed_time(b) / runs
+
+
+def batched_forms(hg, grid, optics, steps, bsize):
+    """Batched forms: `bsize` holograms of the headline size (distinct
+    clouds and seeds) in one graph-captured batch, and the 64-hologram mixed
+    batch (sizes 512^2 .. 1920x1152, N in [8, 200], z within +-0.1 mm)."""
+    import numpy as np
+    import torch
+    from workload import spot_cloud, mixed_batch
+    stream = torch.cuda.Stream()
+    out = {}
+    jobs = [hg.DeviceJob.from_spots(grid, optics, spot_cloud(100 + k, N, grid), ITER, COMP,
+                                    100 + k) for k in range(bsize)]
+    batch = hg.Batch(jobs, use_graph=True)
+    runs = max(1, steps // bsize + 1)
+    ms = _time_batch(torch, batch, stream, runs)
+    out["fp32_batched"] = {"holograms_per_s": round(1000.0 * bsize / ms, 3),
+                           "ms_per_batch": round(ms, 4), "batch": bsize, "runs": runs,
+                           "how": f"{bsize} holograms of this workload per graph-captured batch"}
+    print(f"[bench] batched x{bsize}: {ms:.3f} ms per batch", file=sys.stderr, flush=True)
+    batch.close()
+    del jobs
+    mixed = mixed_batch(0, count=64)
+    mjobs = [hg.DeviceJob.from_spots(j.grid, optics, j.spots, j.iterations, j.compression, j.seed)
+             for j in mixed]
+    terms = sum((j.grid.M * 3 + 2 * (j.iterations - 1) * math.ceil(j.compression * j.grid.M))
+                * j.spots.n for j in mixed)
+    batch = hg.Batch(mjobs, use_graph=True)
+    ms = _time_batch(torch, batch, stream, 3)
+    out["fp32_mixed64"] = {"holograms_per_s": round(64000.0 / ms, 3), "ms_per_batch": round(ms, 4),
+                           "terms_per_s": round(terms / (ms * 1e-3), 1),
+                           "how": "64 mixed holograms (sizes 512^2..1920x1152, N 8..200, I 30, "
+                                  "c 1/16) per graph-captured batch"}
+    print(f"[bench] mixed64: {ms:.3f} ms per batch", file=sys.stderr, flush=True)
+    batch.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +140,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--form", default="fp32", choices=["fp32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch", type=int, default=32, help="holograms per batched launch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the hologram "
@@ -175,6 +225,11 @@ def main():
         accuracy.update({"e_oracle": gd["e"], "u_oracle": gd["u"],
                          "e_abs_err": abs(e - gd["e"]), "u_abs_err": abs(u - gd["u"])})
 
+    forms = {"fp32": {"holograms_per_s": round(value, 3), "ms_per_hologram": round(ms_per_step, 5),
+                      "how": "one hologram per call, back to back on one stream"}}
+    if not args.no_batched:
+        forms.update(batched_forms(hg, grid, OPTICS, args.steps, args.batch))
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a sample", file=sys.stderr, flush=True)
@@ -188,7 +243,7 @@ def main():
         "config": {"workload": WORKLOAD, "W": W, "H": H, "N": N, "iterations": ITER,
                    "compression": COMP, "form": args.form, "clouds": CLOUDS,
                    "spots": "resident in HBM"},
-        "roofline": roofline, "accuracy": accuracy, "cpu_baseline": cpu,
+        "roofline": roofline, "accuracy": accuracy, "forms": forms, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 

@@ -156,6 +156,60 @@ hg_status hg_metrics(const hg_grid *grid, const hg_optics *optics,
                      double *u, double *intensities, void *stream);
 
 /* ---------------------------------------------------------------------- */
+/* Batches: many holograms per launch                                     */
+/* ---------------------------------------------------------------------- */
+
+/* One hologram of a batch.  The schedule is that of hg_cswgs (compression
+ * in (0, 1]; iterations = 0 gives RS).  spots are host arrays, or device
+ * arrays when flags has HG_SPOTS_ON_DEVICE.  phi_dev receives Phi^I,
+ * float32 [H][W].  trace_V: NULL or host [iterations][N][2] doubles. */
+typedef struct hg_job {
+  hg_grid grid;
+  hg_optics optics;
+  hg_spots spots;
+  int32_t iterations;
+  double compression;
+  uint64_t seed;
+  uint32_t flags;
+  float *phi_dev;
+  double *trace_V;
+} hg_job;
+
+/* Launch geometry of the passes, 0 meaning the default: a pass of P pixels
+ * runs on min(ceil(P/64), cap) blocks (full-grid and compressed passes have
+ * separate caps).  It fixes the summation order, so results are
+ * bit-identical for equal caps and may differ in the last bits otherwise.
+ * Chosen per shape by the package's autotuner. */
+typedef struct hg_tune {
+  int32_t full_block_cap;
+  int32_t subset_block_cap;
+} hg_tune;
+
+/* Runs `count` holograms together (paper section 2 for each; the paper
+ * computes one hologram at a time): one launch per iteration round covers
+ * every hologram still iterating, so the per-iteration reductions of one
+ * hologram overlap the work of the others.  Each hologram's result is
+ * bit-identical to computing it alone with the same tune.  tune may be
+ * NULL.  Asynchronous unless a job asks for a trace. */
+hg_status hg_cswgs_batch(int32_t count, const hg_job *jobs, const hg_tune *tune,
+                         void *stream);
+
+/* A reusable batch: planned and allocated once, then run any number of
+ * times.  Every job must have HG_SPOTS_ON_DEVICE (each run reads the spot
+ * arrays' current contents) and no trace.  With use_graph != 0 the first
+ * run on a stream captures the whole schedule (setup, random orders, all
+ * iteration rounds, final phases) as a HIP graph and later runs replay it;
+ * the stream must then not be the NULL stream.  The batch owns its scratch
+ * and releases it in hg_batch_destroy; runs of one batch share that scratch,
+ * so they must not overlap (issue them on one stream).  Errors found on the
+ * device (non-finite spot values) are not reported by the runs. */
+typedef struct hg_batch hg_batch;
+hg_status hg_batch_create(int32_t count, const hg_job *jobs, const hg_tune *tune,
+                          int32_t use_graph, hg_batch **out);
+hg_status hg_batch_run(hg_batch *batch, void *stream);
+hg_status hg_batch_destroy(hg_batch *batch);
+
+/* ---------------------------------------------------------------------- */
 /* Single steps, for testing each kernel against the oracle               */
 /* ---------------------------------------------------------------------- */
 

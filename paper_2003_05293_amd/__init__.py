@@ -25,6 +25,7 @@ __all__ = [
     "HGError", "lib_path", "load", "version", "last_error", "release",
     "rs", "wgs", "cswgs", "metrics", "theta0", "subset", "forward", "backward", "step",
     "PREC_FP32", "PREC_MIXED", "cswgs_device", "timing_enable", "timing_reset", "timing_read",
+    "DeviceJob", "cswgs_batch", "Batch",
 ]
 
 PREC_FP32 = 0
@@ -61,6 +62,17 @@ class _Spots(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("x_mm", _DP), ("y_mm", _DP), ("z_mm", _DP), ("amp", _DP)]
 
 
+class _Job(ctypes.Structure):
+    _fields_ = [("grid", _Grid), ("optics", _Optics), ("spots", _Spots),
+                ("iterations", ctypes.c_int32), ("compression", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32),
+                ("phi_dev", ctypes.c_void_p), ("trace_V", _DP)]
+
+
+class _Tune(ctypes.Structure):
+    _fields_ = [("full_block_cap", ctypes.c_int32), ("subset_block_cap", ctypes.c_int32)]
+
+
 class _Params(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("compression", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("trace_V", _DP)]
@@ -94,6 +106,10 @@ def load():
         "hg_backward": [G, O, S, _DP, _DP, vp, i32, u32, vp, vp],
         "hg_step": [G, O, S, _DP, _DP, vp, i32, u32, _DP, vp],
         "hg_release": [],
+        "hg_cswgs_batch": [i32, c.POINTER(_Job), c.POINTER(_Tune), vp],
+        "hg_batch_create": [i32, c.POINTER(_Job), c.POINTER(_Tune), i32, c.POINTER(vp)],
+        "hg_batch_run": [vp, vp],
+        "hg_batch_destroy": [vp],
         "hg_timing_enable": [c.c_int],
         "hg_timing_reset": [],
         "hg_timing_read": [c.c_char_p, _DP, c.POINTER(c.c_int64)],
@@ -360,3 +376,86 @@ def timing_read(name: str):
     cnt = ctypes.c_int64()
     _check(load().hg_timing_read(name.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
     return ms.value, cnt.value
+
+
+# ---------------------------------------------------------------- batches ---
+
+class DeviceJob:
+    """One hologram of a batch with its spot arrays and output on the GPU.
+
+    spots_dev: float64 GPU tensor (4, N) holding x_mm, y_mm, z_mm, amp;
+    phi: float32 GPU tensor of W*H elements (allocated if None)."""
+
+    def __init__(self, grid, optics, spots_dev, iterations: int, compression: float, seed: int,
+                 phi=None, precision: str = "fp32"):
+        import torch
+        if (not isinstance(spots_dev, torch.Tensor) or spots_dev.dtype != torch.float64
+                or not spots_dev.is_cuda or spots_dev.dim() != 2 or spots_dev.shape[0] != 4
+                or not spots_dev.is_contiguous()):
+            raise TypeError("spots_dev must be a contiguous float64 GPU tensor of shape (4, N)")
+        self.grid, self.optics, self.spots_dev = grid, optics, spots_dev
+        self.iterations, self.compression, self.seed = int(iterations), float(compression), int(seed)
+        self.phi = _new_phi(grid) if phi is None else phi
+        self.flags = _flags(precision) | SPOTS_ON_DEVICE
+
+    @classmethod
+    def from_spots(cls, grid, optics, spots, iterations, compression, seed, **kw):
+        import torch
+        dev = torch.tensor(np.stack([np.asarray(spots.x_mm), np.asarray(spots.y_mm),
+                                     np.asarray(spots.z_mm), np.asarray(spots.amp)]),
+                           dtype=torch.float64, device="cuda")
+        return cls(grid, optics, dev, iterations, compression, seed, **kw)
+
+    def _struct(self) -> _Job:
+        n = int(self.spots_dev.shape[1])
+        base = self.spots_dev.data_ptr()
+        ptrs = [ctypes.cast(ctypes.c_void_p(base + 8 * n * k), _DP) for k in range(4)]
+        return _Job(_grid(self.grid), _optics(self.optics), _Spots(n, *ptrs), self.iterations,
+                    self.compression, self.seed, self.flags,
+                    _dev_f32(self.phi, self.grid.W * self.grid.H, "phi"), None)
+
+
+def _tune(tune):
+    if tune is None:
+        return None
+    if isinstance(tune, dict):
+        return _Tune(int(tune.get("full_block_cap", 0)), int(tune.get("subset_block_cap", 0)))
+    return _Tune(int(tune[0]), int(tune[1]))
+
+
+def cswgs_batch(jobs, tune=None, stream=None):
+    """Runs a list of DeviceJob together (one launch per iteration round)."""
+    lib = load()
+    arr = (_Job * len(jobs))(*[j._struct() for j in jobs])
+    t = _tune(tune)
+    _check(lib.hg_cswgs_batch(len(jobs), arr, ctypes.byref(t) if t else None, _stream(stream)))
+    return [j.phi for j in jobs]
+
+
+class Batch:
+    """A reusable batch (planned once; runs replay a captured HIP graph when
+    use_graph).  Keep the DeviceJob objects alive while the batch exists."""
+
+    def __init__(self, jobs, tune=None, use_graph: bool = True):
+        lib = load()
+        self.jobs = list(jobs)
+        arr = (_Job * len(self.jobs))(*[j._struct() for j in self.jobs])
+        t = _tune(tune)
+        h = ctypes.c_void_p()
+        _check(lib.hg_batch_create(len(self.jobs), arr, ctypes.byref(t) if t else None,
+                                   1 if use_graph else 0, ctypes.byref(h)))
+        self._h = h
+
+    def run(self, stream=None):
+        _check(load().hg_batch_run(self._h, _stream(stream)))
+
+    def close(self):
+        if self._h:
+            _check(load().hg_batch_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

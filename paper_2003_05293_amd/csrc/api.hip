@@ -184,7 +184,45 @@ hg_status single_pass(Workspace* ws, const hg::PixelSet& ps, bool from_phi, doub
   return ws->take_status();
 }
 
+hg::TuneParams tune_params(const hg_tune* t) {
+  hg::TuneParams tp;
+  if (t && t->full_block_cap > 0) tp.full_block_cap = t->full_block_cap;
+  if (t && t->subset_block_cap > 0) tp.subset_block_cap = t->subset_block_cap;
+  return tp;
+}
+
+hg_status job_specs(int32_t count, const hg_job* jobs, const hg_tune* tune,
+                    std::vector<hg::JobSpec>* out) {
+  if (count < 1 || !jobs) return set_error(HG_EINVAL, "count must be >= 1 and jobs non-NULL");
+  if (tune && (tune->full_block_cap < 0 || tune->subset_block_cap < 0))
+    return set_error(HG_EINVAL, "tune caps must be >= 0");
+  out->resize(count);
+  for (int32_t i = 0; i < count; ++i) {
+    const hg_job& j = jobs[i];
+    hg_status st = check_compression(j.compression);
+    if (st == HG_OK) st = validate_flags(j.flags, HG_SPOTS_ON_DEVICE);
+    if (st == HG_OK)
+      st = hg::make_spec(&j.grid, &j.optics, &j.spots, j.iterations, j.compression, j.seed,
+                         j.flags, j.phi_dev, j.trace_V, &(*out)[i]);
+    if (st == HG_OK && !j.phi_dev) st = set_error(HG_EINVAL, "phi_dev must be non-NULL");
+    if (st != HG_OK) return set_error(st, "job " + std::to_string(i) + ": " + hg::last_error());
+  }
+  return HG_OK;
+}
+
 }  // namespace
+
+// A planned batch that owns its scratch; runs replay a captured graph.
+struct hg_batch {
+  int device = 0;
+  hg::Batch batch;
+  hg::DevBuf<int32_t> status;
+  bool use_graph = false;
+  hipStream_t captured_on = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::mutex mu;
+};
 
 extern "C" {
 
@@ -383,6 +421,96 @@ hg_status hg_step(const hg_grid* grid, const hg_optics* optics, const hg_spots* 
   HG_TRY(ws->batch.enqueue_prologue(ws->stream));
   HG_TRY(set_state(ws, spots->n, w, theta));
   return single_pass(ws, pixel_set(idx_dev, m, grid->W * grid->H), false, V_out);
+}
+
+hg_status hg_cswgs_batch(int32_t count, const hg_job* jobs, const hg_tune* tune, void* stream) {
+  std::vector<hg::JobSpec> specs;
+  HG_TRY(job_specs(count, jobs, tune, &specs));
+  Workspace* ws = nullptr;
+  HG_TRY(get_workspace(stream, &ws));
+  std::lock_guard<std::mutex> lk(ws->mu);
+  HG_TRY(ws->init_status());
+  HG_TRY(ws->batch.build(specs.data(), count, tune_params(tune), ws->status.p));
+  HG_TRY(ws->batch.enqueue(ws->stream));
+  bool trace = false;
+  for (const auto& s : specs) trace = trace || s.trace_host;
+  if (trace) {
+    HG_TRY(ws->batch.fetch_traces(ws->stream));
+    HG_TRY(ws->take_status());
+  }
+  return HG_OK;
+}
+
+hg_status hg_batch_create(int32_t count, const hg_job* jobs, const hg_tune* tune,
+                          int32_t use_graph, hg_batch** out) {
+  if (!out) return set_error(HG_EINVAL, "out must be non-NULL");
+  std::vector<hg::JobSpec> specs;
+  HG_TRY(job_specs(count, jobs, tune, &specs));
+  for (int32_t i = 0; i < count; ++i) {
+    if (!specs[i].spots_on_device)
+      return set_error(HG_EINVAL, "hg_batch_create: every job needs HG_SPOTS_ON_DEVICE");
+    if (specs[i].trace_host) return set_error(HG_EINVAL, "hg_batch_create: traces are not allowed");
+  }
+  auto b = std::make_unique<hg_batch>();
+  HG_HIP(hipGetDevice(&b->device));
+  b->use_graph = use_graph != 0;
+  HG_TRY(b->status.reserve(1));
+  HG_HIP(hipMemset(b->status.p, 0, sizeof(int32_t)));
+  HG_TRY(b->batch.build(specs.data(), count, tune_params(tune), b->status.p));
+  *out = b.release();
+  return HG_OK;
+}
+
+hg_status hg_batch_run(hg_batch* b, void* stream) {
+  if (!b) return set_error(HG_EINVAL, "batch must be non-NULL");
+  std::lock_guard<std::mutex> lk(b->mu);
+  hipStream_t s = (hipStream_t)stream;
+  if (!b->use_graph) return b->batch.enqueue(s);
+  if (!s) return set_error(HG_EINVAL, "graph runs need a non-NULL stream");
+  if (b->exec && b->captured_on != s) {
+    (void)hipGraphExecDestroy(b->exec);
+    (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+  }
+  if (!b->exec) {
+    HG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const hg_status st = b->batch.enqueue(s, true);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (st != HG_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess)
+      return set_error(HG_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(e));
+    b->graph = g;
+    HG_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    b->captured_on = s;
+  }
+  hg::timed(s, "hg_batch", [&] { (void)hipGraphLaunch(b->exec, s); });
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    return set_error(HG_EDEVICE, std::string("graph launch failed: ") + hipGetErrorString(e));
+  return HG_OK;
+}
+
+hg_status hg_batch_destroy(hg_batch* b) {
+  if (!b) return HG_OK;
+  {
+    std::lock_guard<std::mutex> lk(b->mu);
+    int cur = 0;
+    const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+    (void)hipSetDevice(b->device);
+    (void)hipDeviceSynchronize();
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->batch.release();
+    b->status.release();
+    if (have_cur) (void)hipSetDevice(cur);
+  }
+  delete b;
+  return HG_OK;
 }
 
 hg_status hg_timing_enable(int on) {

@@ -403,31 +403,39 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
   return HG_OK;
 }
 
-hg_status Batch::enqueue_prologue(hipStream_t s) {
+hg_status Batch::enqueue_prologue(hipStream_t s, bool capture) {
   HG_HIP(hipMemcpyAsync(table_.p, staging_.p, table_bytes_, hipMemcpyHostToDevice, s));
   if (host_spot_bytes_)
     HG_HIP(hipMemcpyAsync(arena_.p + raw_base_, staging_.p + table_bytes_, host_spot_bytes_,
                           hipMemcpyHostToDevice, s));
-  HG_TRY(staging_.mark_copied(s));
-  timed(s, "k_setup", [&] { launch_setup_batch(jobs_dev_, count(), max_h_, s); });
+  if (!capture) HG_TRY(staging_.mark_copied(s));
+  auto run = [&](const char* name, auto&& launch) {
+    if (capture) launch();
+    else timed(s, name, launch);
+  };
+  run("k_setup", [&] { launch_setup_batch(jobs_dev_, count(), max_h_, s); });
   if (perm_blocks_ > 0)
-    timed(s, "k_perm", [&] {
+    run("k_perm", [&] {
       launch_perm_batch(jobs_dev_, perm_dev_, (int)perm_.size(), perm_blocks_, perm_lds_, s);
     });
   return HG_OK;
 }
 
-hg_status Batch::enqueue(hipStream_t s) {
-  HG_TRY(enqueue_prologue(s));
+hg_status Batch::enqueue(hipStream_t s, bool capture) {
+  HG_TRY(enqueue_prologue(s, capture));
+  auto run = [&](const char* name, auto&& launch) {
+    if (capture) launch();
+    else timed(s, name, launch);
+  };
   static const char* kNames[] = {"k_pass_subset", "k_pass_full", "k_pass_mixed"};
   for (size_t r = 0; r < round_first_.size(); ++r) {
-    timed(s, kNames[round_kind_[r]], [&] {
+    run(kNames[round_kind_[r]], [&] {
       launch_pass_batch(jobs_dev_, pass_dev_ + round_first_[r], round_count_[r], round_blocks_[r],
                         round_units_[r], s);
     });
   }
   if (!back_.empty())
-    timed(s, "k_backprop_phi", [&] {
+    run("k_backprop_phi", [&] {
       launch_backprop_batch(jobs_dev_, back_dev_, (int)back_.size(), back_blocks_, s);
     });
   hipError_t e = hipGetLastError();

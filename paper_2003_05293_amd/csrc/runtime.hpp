@@ -118,9 +118,11 @@ class Batch {
   hg_status build(const JobSpec* specs, int count, const TuneParams& tp, int32_t* status_dev);
   // Uploads the tables (and host spot arrays), then the whole schedule:
   // setup, random orders, one pass launch per iteration round, final phase.
-  hg_status enqueue(hipStream_t s);
+  // With `capture`, the enqueue is being recorded into a graph: no event is
+  // recorded and no launch is timed.
+  hg_status enqueue(hipStream_t s, bool capture = false);
   // Setup and random orders only (for the single-step calls).
-  hg_status enqueue_prologue(hipStream_t s);
+  hg_status enqueue_prologue(hipStream_t s, bool capture = false);
   // Copies the traces of the jobs that asked for one and waits for them.
   hg_status fetch_traces(hipStream_t s);
 
