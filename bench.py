@@ -133,6 +133,31 @@ def batched_forms(hg, grid, optics, steps, bsize):
     return out
 
 
+def served_form(hg, optics, seconds):
+    """Served form: Poisson arrivals at 60 requests/s (N uniform in [10, 150],
+    1152^2 or 1920x1152, CS-WGS 20 iterations, c = 1/16) replayed in real time
+    through the continuous-batching engine."""
+    import torch
+    from paper_2003_05293_amd import serve
+    from workload import poisson_stream
+    reqs = poisson_stream(0, rate_hz=60.0, duration_s=seconds, iterations=20)
+    stream = torch.cuda.Stream()
+    eng = hg.Engine(16 << 30, max_slots=64)
+    warm = poisson_stream(1, rate_hz=60.0, duration_s=0.5, iterations=20)
+    serve.replay(warm, optics, eng, stream)
+    res = serve.replay(reqs, optics, eng, stream)
+    eng.close()
+    print(f"[bench] served {res.completed} requests in {res.wall_s:.2f} s, p50 "
+          f"{1e3 * res.percentile(50):.3f} ms, p99 {1e3 * res.percentile(99):.3f} ms",
+          file=sys.stderr, flush=True)
+    return {"holograms_per_s": round(res.completed / res.wall_s, 3),
+            "offered_per_s": 60.0, "requests": len(reqs), "completed": res.completed,
+            "p50_ms": round(1e3 * res.percentile(50), 4), "p99_ms": round(1e3 * res.percentile(99), 4),
+            "engine_steps": res.steps, "seconds": seconds,
+            "how": "Poisson 60/s, N in [10,150], 1152^2 or 1920x1152, I 20, c 1/16, "
+                   "continuous batching, latency arrival -> observed completion"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +167,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch", type=int, default=32, help="holograms per batched launch")
+    ap.add_argument("--serve-seconds", type=float, default=30.0,
+                    help="length of the served Poisson stream (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the hologram "
@@ -229,6 +256,8 @@ def main():
                       "how": "one hologram per call, back to back on one stream"}}
     if not args.no_batched:
         forms.update(batched_forms(hg, grid, OPTICS, args.steps, args.batch))
+    if args.serve_seconds > 0:
+        forms["fp32_served"] = served_form(hg, OPTICS, args.serve_seconds)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -210,6 +210,52 @@ hg_status hg_batch_run(hg_batch *batch, void *stream);
 hg_status hg_batch_destroy(hg_batch *batch);
 
 /* ---------------------------------------------------------------------- */
+/* Serving: continuous batching of hologram requests                      */
+/* ---------------------------------------------------------------------- */
+
+/* An engine that admits hologram requests as device memory and slots free
+ * up and advances every admitted hologram by one iteration per step, in one
+ * batched launch, so that requests arriving while others run join the
+ * running batch at the next step (continuous batching).  Each hologram's
+ * launch geometry depends only on that hologram: a result is bit-identical
+ * to computing the same request alone (hg_cswgs_batch of one, same tune). */
+typedef struct hg_engine hg_engine;
+
+typedef struct hg_engine_config {
+  size_t mem_budget_bytes;  /* device scratch for admitted requests (one
+                               pool allocated at creation)                   */
+  int32_t max_slots;        /* holograms in flight at most (1 .. 4096)      */
+  hg_tune tune;             /* launch geometry, 0 = default                 */
+} hg_engine_config;
+
+/* Creates the engine on the current device. */
+hg_status hg_engine_create(const hg_engine_config *config, hg_engine **out);
+
+/* Queues a request (one hologram, as in hg_job; no trace).  Host spot
+ * arrays are copied; device spot arrays (HG_SPOTS_ON_DEVICE) and phi_dev
+ * must stay valid until the request is done.  Returns a ticket.  A request
+ * whose scratch can never fit the budget is rejected with HG_ENOMEM. */
+hg_status hg_engine_submit(hg_engine *engine, const hg_job *job, uint64_t *ticket);
+
+/* One engine step on `stream`: retires finished requests (their scratch
+ * returns to the pool once the device is done with it), admits queued
+ * requests in arrival order while a slot and room in the pool are free
+ * (HG_EBUSY-style waiting: a request that does not fit yet stays queued),
+ * sets them up, then launches one pass that advances every admitted
+ * hologram by one iteration and the final phase of those that completed
+ * their last iteration.  At most two steps are in flight on the device: a
+ * step waits for the one before the previous.  pending_out (may be NULL)
+ * receives the number of requests admitted or queued and not yet done. */
+hg_status hg_engine_step(hg_engine *engine, void *stream, int32_t *pending_out);
+
+/* done = 1 once the hologram of `ticket` is complete in its phi_dev buffer
+ * (the device has finished it); 0 otherwise.  Unknown tickets: HG_EINVAL. */
+hg_status hg_engine_poll(hg_engine *engine, uint64_t ticket, int32_t *done);
+
+/* Waits for the device, frees the pool and the engine. */
+hg_status hg_engine_destroy(hg_engine *engine);
+
+/* ---------------------------------------------------------------------- */
 /* Single steps, for testing each kernel against the oracle               */
 /* ---------------------------------------------------------------------- */
 

@@ -25,7 +25,7 @@ __all__ = [
     "HGError", "lib_path", "load", "version", "last_error", "release",
     "rs", "wgs", "cswgs", "metrics", "theta0", "subset", "forward", "backward", "step",
     "PREC_FP32", "PREC_MIXED", "cswgs_device", "timing_enable", "timing_reset", "timing_read",
-    "DeviceJob", "cswgs_batch", "Batch",
+    "DeviceJob", "cswgs_batch", "Batch", "Engine",
 ]
 
 PREC_FP32 = 0
@@ -73,6 +73,11 @@ class _Tune(ctypes.Structure):
     _fields_ = [("full_block_cap", ctypes.c_int32), ("subset_block_cap", ctypes.c_int32)]
 
 
+class _EngineConfig(ctypes.Structure):
+    _fields_ = [("mem_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
+                ("tune", _Tune)]
+
+
 class _Params(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("compression", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("trace_V", _DP)]
@@ -110,6 +115,11 @@ def load():
         "hg_batch_create": [i32, c.POINTER(_Job), c.POINTER(_Tune), i32, c.POINTER(vp)],
         "hg_batch_run": [vp, vp],
         "hg_batch_destroy": [vp],
+        "hg_engine_create": [c.POINTER(_EngineConfig), c.POINTER(vp)],
+        "hg_engine_submit": [vp, c.POINTER(_Job), c.POINTER(u64)],
+        "hg_engine_step": [vp, vp, c.POINTER(i32)],
+        "hg_engine_poll": [vp, u64, c.POINTER(i32)],
+        "hg_engine_destroy": [vp],
         "hg_timing_enable": [c.c_int],
         "hg_timing_reset": [],
         "hg_timing_read": [c.c_char_p, _DP, c.POINTER(c.c_int64)],
@@ -453,6 +463,58 @@ class Batch:
         if self._h:
             _check(load().hg_batch_destroy(self._h))
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- serving ---
+
+class Engine:
+    """Continuous-batching engine (hg_engine_*).  submit() queues a request
+    (host spot arrays are copied; the phi tensor must stay alive until the
+    request is done), step() admits and advances every request by one
+    iteration on the given stream, poll() reports completion."""
+
+    def __init__(self, mem_budget_bytes: int, max_slots: int = 64, tune=None):
+        lib = load()
+        t = _tune(tune) or _Tune(0, 0)
+        cfg = _EngineConfig(int(mem_budget_bytes), int(max_slots), t)
+        h = ctypes.c_void_p()
+        _check(lib.hg_engine_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, grid, optics, spots, iterations: int, compression: float, seed: int,
+               phi, precision: str = "fp32") -> int:
+        sa = _SpotArgs(spots)
+        job = _Job(_grid(grid), _optics(optics), sa.struct, int(iterations), float(compression),
+                   int(seed), _flags(precision), _dev_f32(phi, grid.W * grid.H, "phi"), None)
+        t = ctypes.c_uint64()
+        _check(load().hg_engine_submit(self._h, ctypes.byref(job), ctypes.byref(t)))
+        self._keep[t.value] = phi
+        return t.value
+
+    def step(self, stream=None) -> int:
+        n = ctypes.c_int32()
+        _check(load().hg_engine_step(self._h, _stream(stream), ctypes.byref(n)))
+        return n.value
+
+    def poll(self, ticket: int) -> bool:
+        d = ctypes.c_int32()
+        _check(load().hg_engine_poll(self._h, int(ticket), ctypes.byref(d)))
+        if d.value:
+            self._keep.pop(int(ticket), None)
+        return bool(d.value)
+
+    def close(self):
+        if self._h:
+            _check(load().hg_engine_destroy(self._h))
+            self._h = None
+            self._keep.clear()
 
     def __del__(self):
         try:

@@ -211,6 +211,8 @@ int half_bits(int64_t M) {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+}  // namespace
+
 PixelSet all_pixels(int32_t M) {
   PixelSet ps;
   ps.perm = nullptr;
@@ -221,18 +223,31 @@ PixelSet all_pixels(int32_t M) {
   return ps;
 }
 
-}  // namespace
-
-hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
-                       int32_t* status_dev) {
-  specs_.assign(specs, specs + count);
-  jobs_.assign(count, JobDev{});
-  struct Off {
-    size_t sp, tab, perm, partial, gpart, counters, V;
-  };
-  std::vector<Off> off(count);
-  std::vector<PassPlan> plan_all(count), plan_sub(count);
-  std::vector<size_t> raw_off(count, 0);
+JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev,
+                     bool raw_inline) {
+  JobLayout L;
+  JobDev& j = L.dev;
+  j = JobDev{};
+  j.W = s.W;
+  j.H = s.H;
+  j.N = s.N;
+  j.M = s.W * s.H;
+  j.iterations = s.iterations;
+  j.compressed = (s.compression > 0.0 && s.iterations >= 2) ? 1 : 0;
+  j.m = j.compressed ? (int32_t)std::ceil(s.compression * (double)j.M) : j.M;
+  j.h = j.compressed ? half_bits(j.M) : 0;
+  j.seed = s.seed;
+  j.pitch_mm = s.pitch_mm;
+  j.lambda_mm = s.lambda_mm;
+  j.focal_mm = s.focal_mm;
+  j.phi = s.phi;
+  j.trace = s.trace_host ? 1 : 0;
+  j.status = status_dev;
+  L.plan_all = plan_pass(j.M, tp.full_block_cap);
+  L.plan_sub = j.compressed ? plan_pass(j.m, tp.subset_block_cap) : L.plan_all;
+  const int max_blocks = std::max(L.plan_all.blocks, L.plan_sub.blocks);
+  const int max_groups = std::max(L.plan_all.ngroups, L.plan_sub.ngroups);
+  j.counters_len = max_groups + 1;
   size_t bytes = 0;
   auto take = [&](size_t n) {
     bytes = align_up(bytes, 256);
@@ -240,6 +255,63 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
     bytes += n;
     return o;
   };
+  L.raw_inline = raw_inline && !s.spots_on_device;
+  L.off_raw = L.raw_inline ? take(sizeof(double) * 4 * (size_t)s.N) : 0;
+  L.off_sp = take(sizeof(SpotRec) * (size_t)s.N);
+  L.off_tab = j.compressed ? take(sizeof(uint32_t) * ((size_t)kFeistelRoundsHost << j.h)) : 0;
+  L.off_perm = j.compressed ? take(sizeof(int32_t) * (size_t)j.M) : 0;
+  L.off_partial = take(sizeof(float2) * (size_t)max_blocks * s.N);
+  L.off_gpart = take(sizeof(double2) * (size_t)max_groups * s.N);
+  L.off_counters = take(sizeof(unsigned) * (size_t)j.counters_len);
+  L.off_V = take(sizeof(double2) * (size_t)s.N *
+                 (s.trace_host && s.iterations > 0 ? s.iterations : 1));
+  L.bytes = align_up(bytes, 256);
+  return L;
+}
+
+JobDev bind_job(const JobLayout& L, const JobSpec& s, char* base, const double* raw_ext) {
+  JobDev j = L.dev;
+  if (s.spots_on_device) {
+    j.in = SpotPtrs{s.x, s.y, s.z, s.amp};
+  } else {
+    const double* r = L.raw_inline ? reinterpret_cast<const double*>(base + L.off_raw) : raw_ext;
+    j.in = SpotPtrs{r, r + s.N, r + 2 * s.N, r + 3 * s.N};
+  }
+  j.sp = reinterpret_cast<SpotRec*>(base + L.off_sp);
+  j.tab = j.compressed ? reinterpret_cast<uint32_t*>(base + L.off_tab) : nullptr;
+  j.perm = j.compressed ? reinterpret_cast<int32_t*>(base + L.off_perm) : nullptr;
+  j.partial = reinterpret_cast<float2*>(base + L.off_partial);
+  j.gpart = reinterpret_cast<double2*>(base + L.off_gpart);
+  j.counters = reinterpret_cast<unsigned*>(base + L.off_counters);
+  j.V = reinterpret_cast<double2*>(base + L.off_V);
+  return j;
+}
+
+PassDesc iteration_desc(const JobDev& j, const JobLayout& L, int it, int index, int block_begin) {
+  const bool sub = j.compressed && it < j.iterations;
+  PassDesc d;
+  d.block_begin = block_begin;
+  d.job = index;
+  d.ps = all_pixels(j.M);
+  if (sub) {
+    d.ps.perm = j.perm;
+    d.ps.start = (int64_t)(it - 1) * j.m % j.M;
+    d.ps.count = j.m;
+  }
+  d.plan = sub ? L.plan_sub : L.plan_all;
+  d.update = 1;
+  d.from_phi = 0;
+  d.inv_count = 1.0 / (double)d.ps.count;
+  d.V = j.V + (j.trace ? (size_t)(it - 1) * j.N : 0);
+  return d;
+}
+
+hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
+                       int32_t* status_dev) {
+  specs_.assign(specs, specs + count);
+  jobs_.assign(count, JobDev{});
+  layouts_.resize(count);
+  std::vector<size_t> raw_off(count, 0), base_off(count, 0);
   // host-resident spot inputs first, contiguous, so that one copy moves them
   host_spot_bytes_ = 0;
   for (int i = 0; i < count; ++i)
@@ -247,66 +319,26 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
       raw_off[i] = host_spot_bytes_;
       host_spot_bytes_ += sizeof(double) * 4 * (size_t)specs[i].N;
     }
-  const size_t raw_base = take(host_spot_bytes_);
+  size_t bytes = align_up(host_spot_bytes_, 256);
   int max_rounds = 0;
   max_h_ = 0;
   perm_lds_ = true;
   for (int i = 0; i < count; ++i) {
-    const JobSpec& s = specs[i];
-    JobDev& j = jobs_[i];
-    j.W = s.W;
-    j.H = s.H;
-    j.N = s.N;
-    j.M = s.W * s.H;
-    j.iterations = s.iterations;
-    j.compressed = (s.compression > 0.0 && s.iterations >= 2) ? 1 : 0;
-    j.m = j.compressed ? (int32_t)std::ceil(s.compression * (double)j.M) : j.M;
-    j.h = j.compressed ? half_bits(j.M) : 0;
-    j.seed = s.seed;
-    j.pitch_mm = s.pitch_mm;
-    j.lambda_mm = s.lambda_mm;
-    j.focal_mm = s.focal_mm;
-    j.phi = s.phi;
-    j.trace = s.trace_host ? 1 : 0;
-    j.status = status_dev;
-    plan_all[i] = plan_pass(j.M, tp.full_block_cap);
-    plan_sub[i] = j.compressed ? plan_pass(j.m, tp.subset_block_cap) : plan_all[i];
-    const int max_blocks = std::max(plan_all[i].blocks, plan_sub[i].blocks);
-    const int max_groups = std::max(plan_all[i].ngroups, plan_sub[i].ngroups);
-    j.counters_len = max_groups + 1;
-    off[i].sp = take(sizeof(SpotRec) * (size_t)s.N);
-    off[i].tab = j.compressed ? take(sizeof(uint32_t) * ((size_t)kFeistelRoundsHost << j.h)) : 0;
-    off[i].perm = j.compressed ? take(sizeof(int32_t) * (size_t)j.M) : 0;
-    off[i].partial = take(sizeof(float2) * (size_t)max_blocks * s.N);
-    off[i].gpart = take(sizeof(double2) * (size_t)max_groups * s.N);
-    off[i].counters = take(sizeof(unsigned) * (size_t)j.counters_len);
-    off[i].V = take(sizeof(double2) * (size_t)s.N *
-                    (s.trace_host && s.iterations > 0 ? s.iterations : 1));
-    max_rounds = std::max(max_rounds, s.iterations);
+    layouts_[i] = layout_job(specs[i], tp, status_dev, false);
+    base_off[i] = bytes;
+    bytes += layouts_[i].bytes;
+    max_rounds = std::max(max_rounds, specs[i].iterations);
+    const JobDev& j = layouts_[i].dev;
     if (j.compressed) {
       max_h_ = std::max(max_h_, j.h);
       if (j.h > 11) perm_lds_ = false;
     }
   }
+  raw_base_ = 0;
   HG_TRY(arena_.reserve(std::max<size_t>(bytes, 256)));
-  char* base = arena_.p;
-  for (int i = 0; i < count; ++i) {
-    const JobSpec& s = specs[i];
-    JobDev& j = jobs_[i];
-    if (s.spots_on_device) {
-      j.in = SpotPtrs{s.x, s.y, s.z, s.amp};
-    } else {
-      const double* r = reinterpret_cast<const double*>(base + raw_base + raw_off[i]);
-      j.in = SpotPtrs{r, r + s.N, r + 2 * s.N, r + 3 * s.N};
-    }
-    j.sp = reinterpret_cast<SpotRec*>(base + off[i].sp);
-    j.tab = j.compressed ? reinterpret_cast<uint32_t*>(base + off[i].tab) : nullptr;
-    j.perm = j.compressed ? reinterpret_cast<int32_t*>(base + off[i].perm) : nullptr;
-    j.partial = reinterpret_cast<float2*>(base + off[i].partial);
-    j.gpart = reinterpret_cast<double2*>(base + off[i].gpart);
-    j.counters = reinterpret_cast<unsigned*>(base + off[i].counters);
-    j.V = reinterpret_cast<double2*>(base + off[i].V);
-  }
+  for (int i = 0; i < count; ++i)
+    jobs_[i] = bind_job(layouts_[i], specs[i], arena_.p + base_off[i],
+                        reinterpret_cast<const double*>(arena_.p + raw_off[i]));
   // iteration rounds: round r runs iteration r + 1 of every job with I > r
   pass_.clear();
   round_first_.clear();
@@ -321,25 +353,10 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
     for (int i = 0; i < count; ++i) {
       const JobDev& j = jobs_[i];
       if (r >= j.iterations) continue;
-      const int it = r + 1;
-      const bool sub = j.compressed && it < j.iterations;
-      PassDesc d;
-      d.block_begin = blocks;
-      d.job = i;
-      d.ps = all_pixels(j.M);
-      if (sub) {
-        d.ps.perm = j.perm;
-        d.ps.start = (int64_t)(it - 1) * j.m % j.M;
-        d.ps.count = j.m;
-      }
-      d.plan = sub ? plan_sub[i] : plan_all[i];
-      d.update = 1;
-      d.from_phi = 0;
-      d.inv_count = 1.0 / (double)d.ps.count;
-      d.V = j.V + (j.trace ? (size_t)(it - 1) * j.N : 0);
+      const PassDesc d = iteration_desc(j, layouts_[i], r + 1, i, blocks);
       blocks += d.plan.blocks;
       units = std::max(units, pass_units_per_wave(j.N));
-      (sub ? any_sub : any_full) = true;
+      (d.ps.count == j.M ? any_full : any_sub) = true;
       pass_.push_back(d);
     }
     round_first_.push_back(first);
@@ -399,7 +416,6 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
     std::memcpy(dst + 2 * s.N, s.z, sizeof(double) * s.N);
     std::memcpy(dst + 3 * s.N, s.amp, sizeof(double) * s.N);
   }
-  raw_base_ = raw_base;
   return HG_OK;
 }
 

@@ -90,6 +90,25 @@ hg_status make_spec(const hg_grid* g, const hg_optics* o, const hg_spots* s, int
                     double compression, uint64_t seed, uint32_t flags, float* phi,
                     double* trace_host, JobSpec* out);
 
+// Device scratch of one job, laid out relative to the job's base address.
+struct JobLayout {
+  JobDev dev;  // every field but the pointers
+  PassPlan plan_all, plan_sub;
+  size_t off_raw = 0, off_sp = 0, off_tab = 0, off_perm = 0, off_partial = 0, off_gpart = 0,
+         off_counters = 0, off_V = 0;
+  size_t bytes = 0;
+  bool raw_inline = false;  // the job's own scratch holds a copy of its spot arrays
+};
+// raw_inline: reserve room for the 4N input doubles of host-resident spots.
+JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev,
+                     bool raw_inline);
+// The JobDev of a job whose scratch starts at `base` (host spot copies at
+// raw_ext when the layout does not hold them itself).
+JobDev bind_job(const JobLayout& L, const JobSpec& s, char* base, const double* raw_ext);
+// Descriptor of iteration `it` (1-based) of job `index` in a launch.
+PassDesc iteration_desc(const JobDev& j, const JobLayout& L, int it, int index, int block_begin);
+PixelSet all_pixels(int32_t M);
+
 // Kernel timing (hg_timing_*).  While enabled, `timed` brackets a launch
 // with two events recorded on its stream; hg_timing_read drains them.
 bool timing_enabled();
@@ -136,6 +155,7 @@ class Batch {
  private:
   std::vector<JobSpec> specs_;
   std::vector<JobDev> jobs_;
+  std::vector<JobLayout> layouts_;
   std::vector<PassDesc> pass_;          // every round's descriptors, concatenated
   std::vector<int> round_first_, round_count_, round_blocks_, round_units_, round_kind_;
   std::vector<BackDesc> back_;
