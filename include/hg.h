@@ -100,6 +100,14 @@ typedef struct hg_spots {
  * device; a non-finite coordinate or a non-positive amplitude is reported
  * as HG_EINVAL by the next blocking call on the stream. */
 #define HG_SPOTS_ON_DEVICE 0x100u
+/* hg_params.flags, hg_job.flags and the single-step calls: compute full-grid
+ * passes with the per-pixel kernels (phase and sincos per pixel and spot,
+ * as in the paper's GPU section) instead of the default separable products
+ * (eq. 2 factorises into an x' part and a y' part, so a full-grid
+ * back-propagation is a complex matrix product over the spots and the
+ * full-grid forward sum a product over the pixel columns).  Both compute
+ * the same sums; the summation order differs. */
+#define HG_FULL_DIRECT 0x200u
 
 /* Extended parameters of hg_cswgs_ex. */
 typedef struct hg_params {

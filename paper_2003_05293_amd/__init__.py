@@ -31,6 +31,7 @@ __all__ = [
 PREC_FP32 = 0
 PREC_MIXED = 1
 SPOTS_ON_DEVICE = 0x100
+FULL_DIRECT = 0x200
 _PREC = {"fp32": PREC_FP32, "mixed": PREC_MIXED}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -249,14 +250,15 @@ def wgs(grid, optics, spots, iterations: int, seed: int, phi=None, stream=None):
 
 
 def cswgs(grid, optics, spots, iterations: int, compression: float, seed: int, phi=None,
-          stream=None, precision: str = "fp32", trace: bool = False):
+          stream=None, precision: str = "fp32", trace: bool = False, direct: bool = False):
     """Compressed-sensing WGS hologram.  With trace=True returns (phi, V)
-    where V[j-1] is the complex spot field of iteration j."""
+    where V[j-1] is the complex spot field of iteration j.  direct=True
+    computes the full-grid passes with the per-pixel kernels."""
     lib = load()
     phi = _new_phi(grid) if phi is None else phi
     sa = _SpotArgs(spots)
-    flags = _flags(precision)
-    if precision == "fp32" and not trace:
+    flags = _flags(precision) | (FULL_DIRECT if direct else 0)
+    if precision == "fp32" and not trace and not direct:
         _check(lib.hg_cswgs(_grid(grid), _optics(optics), sa.struct, int(iterations),
                             float(compression), int(seed),
                             _dev_f32(phi, grid.W * grid.H, "phi"), _stream(stream)))
@@ -317,9 +319,9 @@ def forward(grid, optics, spots, phi, idx=None, precision: str = "fp32",
 
 
 def backward(grid, optics, spots, w, theta, idx=None, out=None, precision: str = "fp32",
-             stream=None):
+             stream=None, direct: bool = False):
     """Phi (eq. 1) with weights w and phases theta at idx (compact) or at
-    all pixels."""
+    all pixels (separable products unless direct=True)."""
     lib = load()
     sa = _SpotArgs(spots)
     w = _f64(w, sa.n, "w")
@@ -328,15 +330,17 @@ def backward(grid, optics, spots, w, theta, idx=None, out=None, precision: str =
     count = m if idx is not None else grid.W * grid.H
     out = _new_phi(grid, count) if out is None else out
     _check(lib.hg_backward(_grid(grid), _optics(optics), sa.struct, w.ctypes.data_as(_DP),
-                           th.ctypes.data_as(_DP), ip, m, _flags(precision),
+                           th.ctypes.data_as(_DP), ip, m,
+                           _flags(precision) | (FULL_DIRECT if direct else 0),
                            _dev_f32(out, count, "out"), _stream(stream)))
     return out
 
 
 def step(grid, optics, spots, w, theta, idx=None, precision: str = "fp32",
-         stream=None) -> np.ndarray:
+         stream=None, direct: bool = False) -> np.ndarray:
     """One fused iteration body: back-propagate (w, theta) on the pixel set
-    and return the forward spot fields over the same set."""
+    and return the forward spot fields over the same set (the full grid uses
+    the separable products unless direct=True)."""
     lib = load()
     sa = _SpotArgs(spots)
     w = _f64(w, sa.n, "w")
@@ -344,7 +348,8 @@ def step(grid, optics, spots, w, theta, idx=None, precision: str = "fp32",
     ip, m = _dev_i32(idx, "idx")
     V = np.zeros(2 * sa.n)
     _check(lib.hg_step(_grid(grid), _optics(optics), sa.struct, w.ctypes.data_as(_DP),
-                       th.ctypes.data_as(_DP), ip, m, _flags(precision),
+                       th.ctypes.data_as(_DP), ip, m,
+                       _flags(precision) | (FULL_DIRECT if direct else 0),
                        V.ctypes.data_as(_DP), _stream(stream)))
     return V[0::2] + 1j * V[1::2]
 

@@ -184,6 +184,18 @@ hg_status single_pass(Workspace* ws, const hg::PixelSet& ps, bool from_phi, doub
   return ws->take_status();
 }
 
+// Runs a launch set built for the batch's single job (test hooks).
+hg_status single_set(Workspace* ws, hg::LaunchSet& set) {
+  char* dev = nullptr;
+  HG_TRY(ws->batch.custom_device(set.bytes(), &dev));
+  std::vector<char> host(std::max<size_t>(set.bytes(), 1));
+  set.stage(host.data(), dev);
+  void* up = nullptr;
+  HG_TRY(ws->batch.upload_custom(host.data(), host.size(), ws->stream, &up));
+  set.launch(ws->batch.jobs_device(), ws->stream, false);
+  return check_launch();
+}
+
 hg::TuneParams tune_params(const hg_tune* t) {
   hg::TuneParams tp;
   if (t && t->full_block_cap > 0) tp.full_block_cap = t->full_block_cap;
@@ -200,7 +212,7 @@ hg_status job_specs(int32_t count, const hg_job* jobs, const hg_tune* tune,
   for (int32_t i = 0; i < count; ++i) {
     const hg_job& j = jobs[i];
     hg_status st = check_compression(j.compression);
-    if (st == HG_OK) st = validate_flags(j.flags, HG_SPOTS_ON_DEVICE);
+    if (st == HG_OK) st = validate_flags(j.flags, HG_SPOTS_ON_DEVICE | HG_FULL_DIRECT);
     if (st == HG_OK)
       st = hg::make_spec(&j.grid, &j.optics, &j.spots, j.iterations, j.compression, j.seed,
                          j.flags, j.phi_dev, j.trace_V, &(*out)[i]);
@@ -251,7 +263,7 @@ hg_status hg_cswgs_ex(const hg_grid* grid, const hg_optics* optics, const hg_spo
                       const hg_params* params, float* phi_dev, void* stream) {
   if (!params) return set_error(HG_EINVAL, "params must be non-NULL");
   HG_TRY(check_compression(params->compression));
-  HG_TRY(validate_flags(params->flags, HG_SPOTS_ON_DEVICE));
+  HG_TRY(validate_flags(params->flags, HG_SPOTS_ON_DEVICE | HG_FULL_DIRECT));
   return run_one(grid, optics, spots, params->iterations, params->compression, params->seed,
                  params->flags, phi_dev, params->trace_V, stream);
 }
@@ -379,9 +391,10 @@ hg_status hg_forward(const hg_grid* grid, const hg_optics* optics, const hg_spot
 hg_status hg_backward(const hg_grid* grid, const hg_optics* optics, const hg_spots* spots,
                       const double* w, const double* theta, const int32_t* idx_dev, int32_t m,
                       uint32_t flags, float* phi_dev, void* stream) {
-  HG_TRY(validate_flags(flags, 0));
+  HG_TRY(validate_flags(flags, HG_FULL_DIRECT));
   hg::JobSpec spec;
-  HG_TRY(hg::make_spec(grid, optics, spots, 0, -1.0, 0, flags, nullptr, nullptr, &spec));
+  HG_TRY(hg::make_spec(grid, optics, spots, 0, -1.0, 0, flags, idx_dev ? nullptr : phi_dev,
+                       nullptr, &spec));
   HG_TRY(check_state(spots, w, theta));
   HG_TRY(check_set(grid, idx_dev, m));
   if (!phi_dev) return set_error(HG_EINVAL, "phi_dev must be non-NULL");
@@ -392,6 +405,11 @@ hg_status hg_backward(const hg_grid* grid, const hg_optics* optics, const hg_spo
   HG_TRY(ws->batch.build(&spec, 1, hg::TuneParams{}, ws->status.p));
   HG_TRY(ws->batch.enqueue_prologue(ws->stream));
   HG_TRY(set_state(ws, spots->n, w, theta));
+  if (!idx_dev && !(flags & HG_FULL_DIRECT)) {
+    hg::LaunchSet set;
+    set.add_final(ws->batch.job(0), ws->batch.layout(0), 0);
+    return single_set(ws, set);
+  }
   hg::BackDesc d;
   d.block_begin = 0;
   d.job = 0;
@@ -407,7 +425,7 @@ hg_status hg_backward(const hg_grid* grid, const hg_optics* optics, const hg_spo
 hg_status hg_step(const hg_grid* grid, const hg_optics* optics, const hg_spots* spots,
                   const double* w, const double* theta, const int32_t* idx_dev, int32_t m,
                   uint32_t flags, double* V_out, void* stream) {
-  HG_TRY(validate_flags(flags, 0));
+  HG_TRY(validate_flags(flags, HG_FULL_DIRECT));
   hg::JobSpec spec;
   HG_TRY(hg::make_spec(grid, optics, spots, 0, -1.0, 0, flags, nullptr, nullptr, &spec));
   HG_TRY(check_state(spots, w, theta));
@@ -420,6 +438,19 @@ hg_status hg_step(const hg_grid* grid, const hg_optics* optics, const hg_spots* 
   HG_TRY(ws->batch.build(&spec, 1, hg::TuneParams{}, ws->status.p));
   HG_TRY(ws->batch.enqueue_prologue(ws->stream));
   HG_TRY(set_state(ws, spots->n, w, theta));
+  if (!idx_dev && !(flags & HG_FULL_DIRECT)) {
+    // one full-grid iteration body with the separable products, no update
+    const hg::JobDev& j = ws->batch.job(0);
+    hg::JobDev jj = j;
+    jj.iterations = 1;
+    hg::LaunchSet set;
+    set.add_iteration(jj, ws->batch.layout(0), 1, 0);
+    set.sep[0].update = 0;
+    HG_TRY(single_set(ws, set));
+    HG_HIP(hipMemcpyAsync(V_out, j.V, sizeof(double2) * j.N, hipMemcpyDeviceToHost, ws->stream));
+    HG_HIP(hipStreamSynchronize(ws->stream));
+    return ws->take_status();
+  }
   return single_pass(ws, pixel_set(idx_dev, m, grid->W * grid->H), false, V_out);
 }
 

@@ -86,7 +86,7 @@ struct Slot {
 hg_status spec_from_job(const hg_job& j, hg::JobSpec* out) {
   if (!(j.compression > 0.0 && j.compression <= 1.0))
     return set_error(HG_EINVAL, "compression must be in (0, 1]");
-  if (j.flags & ~(HG_PREC_MASK | HG_SPOTS_ON_DEVICE))
+  if (j.flags & ~(HG_PREC_MASK | HG_SPOTS_ON_DEVICE | HG_FULL_DIRECT))
     return set_error(HG_EINVAL, "flags: unknown bits set");
   if ((j.flags & HG_PREC_MASK) != HG_PREC_FP32)
     return set_error(HG_EINVAL, "flags: only HG_PREC_FP32 is available in this build");
@@ -251,29 +251,18 @@ hg_status hg_engine_step(hg_engine* e, void* stream, int32_t* pending_out) {
     }
     newjobs.push_back(j);
   }
-  std::vector<hg::PassDesc> pass;
-  std::vector<hg::BackDesc> back;
+  hg::LaunchSet iter, fin;
   std::vector<int> finishing;
-  int pass_blocks = 0, back_blocks = 0, units = 1;
   for (int si = 0; si < e->max_slots; ++si) {
     Slot& sl = e->slots[si];
     if (!sl.used || sl.finishing) continue;
     const hg::JobDev& j = sl.dev;
     if (sl.next_it <= j.iterations) {
-      const hg::PassDesc d = hg::iteration_desc(j, sl.layout, sl.next_it, si, pass_blocks);
-      pass_blocks += d.plan.blocks;
-      units = std::max(units, hg::pass_units_per_wave(j.N));
-      pass.push_back(d);
+      iter.add_iteration(j, sl.layout, sl.next_it, si);
       sl.next_it += 1;
     }
     if (sl.next_it > j.iterations) {
-      hg::BackDesc b;
-      b.block_begin = back_blocks;
-      b.job = si;
-      b.ps = hg::all_pixels(j.M);
-      b.out = j.phi;
-      back.push_back(b);
-      back_blocks += hg::backprop_blocks(j.M);
+      fin.add_final(j, sl.layout, si);
       finishing.push_back(si);
     }
   }
@@ -284,12 +273,12 @@ hg_status hg_engine_step(hg_engine* e, void* stream, int32_t* pending_out) {
   o = align(o + sizeof(hg::JobDev) * table.size());
   const size_t o_new = o;
   o = align(o + sizeof(hg::JobDev) * newjobs.size());
-  const size_t o_pass = o;
-  o = align(o + sizeof(hg::PassDesc) * pass.size());
-  const size_t o_back = o;
-  o = align(o + sizeof(hg::BackDesc) * back.size());
   const size_t o_perm = o;
   o = align(o + sizeof(hg::JobSlice) * perm.size());
+  const size_t o_iter = o;
+  o += iter.bytes();
+  const size_t o_fin = o;
+  o += fin.bytes();
   const size_t table_bytes = o;
   size_t spot_bytes = 0;
   for (int si : fresh)
@@ -300,9 +289,9 @@ hg_status hg_engine_step(hg_engine* e, void* stream, int32_t* pending_out) {
   char* st = e->staging.p;
   std::memcpy(st + o_table, table.data(), sizeof(hg::JobDev) * table.size());
   if (!newjobs.empty()) std::memcpy(st + o_new, newjobs.data(), sizeof(hg::JobDev) * newjobs.size());
-  if (!pass.empty()) std::memcpy(st + o_pass, pass.data(), sizeof(hg::PassDesc) * pass.size());
-  if (!back.empty()) std::memcpy(st + o_back, back.data(), sizeof(hg::BackDesc) * back.size());
   if (!perm.empty()) std::memcpy(st + o_perm, perm.data(), sizeof(hg::JobSlice) * perm.size());
+  iter.stage(st + o_iter, e->step_buf.p + o_iter);
+  fin.stage(st + o_fin, e->step_buf.p + o_fin);
   HG_HIP(hipMemcpyAsync(e->step_buf.p, st, table_bytes, hipMemcpyHostToDevice, s));
   size_t so = table_bytes;
   for (int si : fresh) {
@@ -325,17 +314,8 @@ hg_status hg_engine_step(hg_engine* e, void* stream, int32_t* pending_out) {
                               (int)perm.size(), perm_blocks, perm_lds, s);
       });
   }
-  if (!pass.empty())
-    hg::timed(s, "k_pass_engine", [&] {
-      hg::launch_pass_batch(slots_dev, reinterpret_cast<const hg::PassDesc*>(e->step_buf.p + o_pass),
-                            (int)pass.size(), pass_blocks, units, s);
-    });
-  if (!back.empty())
-    hg::timed(s, "k_backprop_phi", [&] {
-      hg::launch_backprop_batch(slots_dev,
-                                reinterpret_cast<const hg::BackDesc*>(e->step_buf.p + o_back),
-                                (int)back.size(), back_blocks, s);
-    });
+  iter.launch(slots_dev, s, false);
+  fin.launch(slots_dev, s, false);
   const hipError_t le = hipGetLastError();
   if (le != hipSuccess)
     return set_error(HG_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(le));

@@ -558,6 +558,226 @@ __global__ __launch_bounds__(kBlock) void k_backprop_batch(const JobDev* __restr
   as_global_mut(d.out)[q] = atan2f(S.y, S.x);
 }
 
+// ------------------------------------------------- separable full passes ---
+
+// Separable factors of eq. (2) for the full-grid passes, from FP64 phases:
+//   F[n][i] = e^{i 2 pi fx_n(i)},  G[j][n] = e^{i 2 pi fy_n(j)},
+//   B[j][n] = A_n e^{i 2 pi (fy_n(j) + th_n)}   (current state A, th).
+__global__ __launch_bounds__(256) void k_sep_tables(const JobDev* __restrict__ jobs,
+                                                    const JobSlice* __restrict__ slices,
+                                                    int nslices) {
+  const int si = find_desc(slices, nslices, blockIdx.x);
+  const JobDev& jb = jobs[slices[si].job];
+  const int lb = blockIdx.x - slices[si].block_begin;
+  const int W = jb.W, H = jb.H, N = jb.N;
+  const int nb = ceil_div((int64_t)N * (W + H), 256);
+  const int64_t nF = (int64_t)N * W, total = nF + (int64_t)H * N;
+  const double lf = jb.lambda_mm * jb.focal_mm;
+  const double lf2 = lf * jb.focal_mm;
+  const double kxy = jb.pitch_mm / (2.0 * lf), kz = jb.pitch_mm * jb.pitch_mm / (4.0 * lf2);
+  for (int64_t k = (int64_t)lb * 256 + threadIdx.x; k < total; k += (int64_t)nb * 256) {
+    if (k < nF) {
+      const int n = (int)(k / W), i = (int)(k % W);
+      const double L = (double)(2 * i - (W - 1));
+      double t = jb.in.x[n] * kxy * L + jb.in.z[n] * kz * L * L;
+      t -= rint(t);
+      double s, c;
+      sincospi(2.0 * t, &s, &c);
+      jb.sepF[k] = make_float2((float)c, (float)s);
+    } else {
+      const int64_t kk = k - nF;
+      const int j = (int)(kk / N), n = (int)(kk % N);
+      const double L = (double)(2 * j - (H - 1));
+      double t = jb.in.y[n] * kxy * L + jb.in.z[n] * kz * L * L;
+      t -= rint(t);
+      double s, c;
+      sincospi(2.0 * t, &s, &c);
+      jb.sepG[kk] = make_float2((float)c, (float)s);
+      double tb = t + (double)jb.sp[n].th;
+      tb -= rint(tb);
+      sincospi(2.0 * tb, &s, &c);
+      const double A = (double)jb.sp[n].A;
+      jb.sepB[kk] = make_float2((float)(A * c), (float)(A * s));
+    }
+  }
+}
+
+constexpr int kGK = 16;  // K chunk of the separable products
+
+// float2 load through a global-address-space view (two adjacent floats).
+__device__ __forceinline__ float2 ldg2(const float2* p) {
+  const HG_GLOBAL float* f = as_global(reinterpret_cast<const float*>(p));
+  return make_float2(f[0], f[1]);
+}
+
+__device__ __forceinline__ void cmac(float2& acc, const float2& a, const float2& b) {
+  acc.x = fmaf(a.x, b.x, fmaf(-a.y, b.y, acc.x));
+  acc.y = fmaf(a.x, b.y, fmaf(a.y, b.x, acc.y));
+}
+
+// One 64 x 64 output tile (rows j, columns i) per block.  Thread (tr, tc)
+// of the 16 x 16 thread grid owns rows tr + 16 r and columns tc + 16 c
+// (r, c < 4), so LDS reads of a column group are conflict-free.
+//  phase A  S = B F over the N spots (FP32, K chunks of 16 in LDS);
+//  FINAL    Phi = atan2(S) is written and the block ends;
+//  else     u = S / |S| goes to LDS; phase B forms, per chunk of 64 spots,
+//           T[j][n] = sum_i u(j,i) conj(F_n(i)) over the tile's columns and
+//           the block's partial V_n = sum_j conj(G_n(j)) T[j][n] (rows in
+//           fixed order), which the pass tail reduces and applies.
+template <bool FINAL>
+__global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ jobs,
+                                                     const SepDesc* __restrict__ descs,
+                                                     int ndesc) {
+  __shared__ float2 As[kSepTile][kGK + 1];
+  __shared__ float2 Bs[kGK][kSepTile];
+  __shared__ float2 us[FINAL ? 1 : kSepTile][kSepTile + 1];
+  __shared__ float2 red[16][kSepTile];
+  const int di = find_desc(descs, ndesc, blockIdx.x);
+  const SepDesc& d = descs[di];
+  const JobDev& jb = jobs[d.job];
+  const int W = jb.W, H = jb.H, N = jb.N;
+  const int lb = blockIdx.x - d.block_begin;
+  const int j0 = (lb / d.tiles_x) * kSepTile, i0 = (lb % d.tiles_x) * kSepTile;
+  const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;
+  const float2* Bt = jb.sepB;
+  const float2* Ft = jb.sepF;
+
+  float2 acc[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = make_float2(0.f, 0.f);
+  for (int k0 = 0; k0 < N; k0 += kGK) {
+    for (int e = threadIdx.x; e < kSepTile * kGK; e += kBlock) {
+      const int r = e / kGK, kk = e % kGK, j = j0 + r, n = k0 + kk;
+      As[r][kk] = (j < H && n < N) ? ldg2(Bt + (int64_t)j * N + n) : make_float2(0.f, 0.f);
+    }
+    for (int e = threadIdx.x; e < kGK * kSepTile; e += kBlock) {
+      const int kk = e / kSepTile, c = e % kSepTile, n = k0 + kk, i = i0 + c;
+      Bs[kk][c] = (n < N && i < W) ? ldg2(Ft + (int64_t)n * W + i) : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < kGK; ++kk) {
+      float2 a[4], b[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a[r] = As[tr + 16 * r][kk];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tc + 16 * c];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cmac(acc[r][c], a[r], b[c]);
+    }
+    __syncthreads();
+  }
+  if (FINAL) {
+    HG_GLOBAL float* out = as_global_mut(d.out);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int j = j0 + tr + 16 * r, i = i0 + tc + 16 * c;
+        if (j < H && i < W) out[(int64_t)j * W + i] = atan2f(acc[r][c].y, acc[r][c].x);
+      }
+    return;
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int j = j0 + tr + 16 * r, i = i0 + tc + 16 * c;
+      float2 u = make_float2(0.f, 0.f);
+      if (j < H && i < W) {
+        const float m2 = acc[r][c].x * acc[r][c].x + acc[r][c].y * acc[r][c].y;
+        u = make_float2(1.f, 0.f);
+        if (m2 > 0.f) {
+          const float inv = rsqrtf(m2);
+          u = make_float2(acc[r][c].x * inv, acc[r][c].y * inv);
+        }
+      }
+      us[tr + 16 * r][tc + 16 * c] = u;
+    }
+  __syncthreads();
+  const float2* Gt = jb.sepG;
+  for (int n0 = 0; n0 < N; n0 += kSepTile) {
+    float2 t[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) t[r][c] = make_float2(0.f, 0.f);
+    for (int k0 = 0; k0 < kSepTile; k0 += kGK) {
+      for (int e = threadIdx.x; e < kGK * kSepTile; e += kBlock) {
+        const int c = e / kGK, kk = e % kGK, n = n0 + c, i = i0 + k0 + kk;
+        const float2 v = (n < N && i < W) ? ldg2(Ft + (int64_t)n * W + i) : make_float2(0.f, 0.f);
+        Bs[kk][c] = make_float2(v.x, -v.y);
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int kk = 0; kk < kGK; ++kk) {
+        float2 a[4], b[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a[r] = us[tr + 16 * r][k0 + kk];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tc + 16 * c];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) cmac(t[r][c], a[r], b[c]);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int n = n0 + tc + 16 * c;
+      float2 v = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = j0 + tr + 16 * r;
+        if (j < H && n < N) {
+          const float2 g = ldg2(Gt + (int64_t)j * N + n);
+          cmac(v, make_float2(g.x, -g.y), t[r][c]);
+        }
+      }
+      red[tr][tc + 16 * c] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kSepTile) {
+      const int n = n0 + threadIdx.x;
+      if (n < N) {
+        float2 s = red[0][threadIdx.x];
+        for (int k = 1; k < 16; ++k) {
+          s.x += red[k][threadIdx.x].x;
+          s.y += red[k][threadIdx.x].y;
+        }
+        store_dev(jb.partial + (int64_t)lb * N + n, s);
+      }
+    }
+    __syncthreads();
+  }
+  PassCtx a;
+  a.sp = jb.sp;
+  a.N = N;
+  a.W = W;
+  a.H = H;
+  a.ps = PixelSet{nullptr, nullptr, 0, W * H, W * H};
+  a.phi = nullptr;
+  a.tiles = d.plan.tiles;
+  a.group_size = d.plan.group_size;
+  a.ngroups = d.plan.ngroups;
+  a.lb = lb;
+  a.nb = d.plan.blocks;
+  a.partial = jb.partial;
+  a.gpart = jb.gpart;
+  a.counters = jb.counters;
+  a.inv_count = d.inv_count;
+  a.V = d.V;
+  a.status = jb.status;
+  a.update = d.update;
+  a.from_phi = 0;
+  pass_tail(a);
+}
+
 // -------------------------------------------------------------- metrics ---
 
 // FP64 separable factors of e^{-i phi_n}: eq. (2) splits into a part in x'
@@ -715,6 +935,35 @@ void launch_pass_batch(const JobDev* jobs, const PassDesc* descs, int ndesc, int
 }
 
 int backprop_blocks(int32_t count) { return ceil_div(count, kBlock); }
+
+int sep_table_blocks(int W, int H, int N) { return ceil_div((int64_t)N * (W + H), 256); }
+
+void launch_sep_tables(const JobDev* jobs, const JobSlice* slices, int nslices, int total_blocks,
+                       hipStream_t s) {
+  if (nslices <= 0 || total_blocks <= 0) return;
+  hipLaunchKernelGGL(k_sep_tables, dim3(total_blocks), dim3(256), 0, s, jobs, slices, nslices);
+}
+
+PassPlan plan_sep(int W, int H) {
+  PassPlan p;
+  p.tiles = ceil_div(W, kSepTile) * ceil_div(H, kSepTile);
+  p.blocks = p.tiles;
+  int gs = 1;
+  while (gs * gs < p.blocks) ++gs;
+  p.group_size = gs;
+  p.ngroups = ceil_div(p.blocks, gs);
+  return p;
+}
+
+void launch_sep_pass(const JobDev* jobs, const SepDesc* descs, int ndesc, int total_blocks,
+                     bool final, hipStream_t s) {
+  if (ndesc <= 0 || total_blocks <= 0) return;
+  if (final)
+    hipLaunchKernelGGL(k_sep_pass<true>, dim3(total_blocks), dim3(kBlock), 0, s, jobs, descs, ndesc);
+  else
+    hipLaunchKernelGGL(k_sep_pass<false>, dim3(total_blocks), dim3(kBlock), 0, s, jobs, descs,
+                       ndesc);
+}
 
 void launch_backprop_batch(const JobDev* jobs, const BackDesc* descs, int ndesc,
                            int total_blocks, hipStream_t s) {

@@ -70,6 +70,10 @@ struct JobDev {
   int32_t trace;       // V is [iterations][N] instead of [N]
   double2* V;
   int32_t* status;     // sticky status word of the caller's stream
+  // separable factors of the full-grid passes (see sep_tables):
+  float2* sepF;        // [N][W]  e^{i 2 pi fx_n(i)}
+  float2* sepB;        // [H][N]  A_n e^{i 2 pi (fy_n(j) + th_n)}
+  float2* sepG;        // [H][N]  e^{i 2 pi fy_n(j)}
 };
 
 // Pixel set of a pass: all pixels 0..count-1 (perm == idx == nullptr),
@@ -129,6 +133,34 @@ void launch_pass_batch(const JobDev* jobs, const PassDesc* descs, int ndesc, int
 void launch_backprop_batch(const JobDev* jobs, const BackDesc* descs, int ndesc,
                            int total_blocks, hipStream_t s);
 int backprop_blocks(int32_t count);
+
+// ---- separable full-grid passes ----
+// eq. (2) splits into a part in x' and a part in y': with doubled offsets,
+//   phi_n / 2pi = fx_n(i) + fy_n(j),  fx_n = cx Lx + cz Lx^2,  fy_n = cy Ly + cz Ly^2,
+// so e^{i phi_n(i,j)} = F_n(i) G_n(j).  A full-grid back-propagation is then
+// the complex product S = B F (B_n(j) = A_n e^{i th_n} G_n(j)) and the
+// full-grid forward sum is V_n = (1/M) sum_j conj(G_n(j)) sum_i u(j,i) conj(F_n(i)).
+constexpr int kSepTile = 64;  // output tile edge of the separable passes
+struct SepDesc {
+  int32_t block_begin;
+  int32_t job;
+  int32_t tiles_x;      // ceil(W / kSepTile)
+  int32_t tiles_y;
+  PassPlan plan;        // blocks = tiles_x * tiles_y, reduction groups
+  int32_t update;       // weight update after the sums (fused passes)
+  double inv_count;
+  double2* V;
+  float* out;           // final-phase variant: Phi output
+};
+// Tables F, B, G of each listed job from its current state (FP64 phases).
+int sep_table_blocks(int W, int H, int N);
+void launch_sep_tables(const JobDev* jobs, const JobSlice* slices, int nslices, int total_blocks,
+                       hipStream_t s);
+PassPlan plan_sep(int W, int H);
+// Fused full-grid pass (back-propagation, forward, reduction, update) or,
+// with final != 0, the full-grid hologram Phi = arg(B F).
+void launch_sep_pass(const JobDev* jobs, const SepDesc* descs, int ndesc, int total_blocks,
+                     bool final, hipStream_t s);
 
 // ---- metrics (FP64) ----
 struct SetupArgs {

@@ -114,6 +114,7 @@ hg_status make_spec(const hg_grid* g, const hg_optics* o, const hg_spots* s, int
   j.compression = compression;
   j.seed = seed;
   j.precision = flags & HG_PREC_MASK;
+  j.full_direct = (flags & HG_FULL_DIRECT) != 0;
   j.phi = phi;
   j.trace_host = trace_host;
   *out = j;
@@ -243,10 +244,16 @@ JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev
   j.phi = s.phi;
   j.trace = s.trace_host ? 1 : 0;
   j.status = status_dev;
+  L.separable = tp.separable_full && !s.full_direct;
   L.plan_all = plan_pass(j.M, tp.full_block_cap);
   L.plan_sub = j.compressed ? plan_pass(j.m, tp.subset_block_cap) : L.plan_all;
-  const int max_blocks = std::max(L.plan_all.blocks, L.plan_sub.blocks);
-  const int max_groups = std::max(L.plan_all.ngroups, L.plan_sub.ngroups);
+  L.plan_sep = plan_sep(j.W, j.H);
+  int max_blocks = std::max(L.plan_all.blocks, L.plan_sub.blocks);
+  int max_groups = std::max(L.plan_all.ngroups, L.plan_sub.ngroups);
+  if (L.separable) {
+    max_blocks = std::max(max_blocks, L.plan_sep.blocks);
+    max_groups = std::max(max_groups, L.plan_sep.ngroups);
+  }
   j.counters_len = max_groups + 1;
   size_t bytes = 0;
   auto take = [&](size_t n) {
@@ -265,6 +272,11 @@ JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev
   L.off_counters = take(sizeof(unsigned) * (size_t)j.counters_len);
   L.off_V = take(sizeof(double2) * (size_t)s.N *
                  (s.trace_host && s.iterations > 0 ? s.iterations : 1));
+  if (L.separable) {
+    L.off_sepF = take(sizeof(float2) * (size_t)s.N * s.W);
+    L.off_sepB = take(sizeof(float2) * (size_t)s.N * s.H);
+    L.off_sepG = take(sizeof(float2) * (size_t)s.N * s.H);
+  }
   L.bytes = align_up(bytes, 256);
   return L;
 }
@@ -284,6 +296,9 @@ JobDev bind_job(const JobLayout& L, const JobSpec& s, char* base, const double* 
   j.gpart = reinterpret_cast<double2*>(base + L.off_gpart);
   j.counters = reinterpret_cast<unsigned*>(base + L.off_counters);
   j.V = reinterpret_cast<double2*>(base + L.off_V);
+  j.sepF = L.separable ? reinterpret_cast<float2*>(base + L.off_sepF) : nullptr;
+  j.sepB = L.separable ? reinterpret_cast<float2*>(base + L.off_sepB) : nullptr;
+  j.sepG = L.separable ? reinterpret_cast<float2*>(base + L.off_sepG) : nullptr;
   return j;
 }
 
@@ -305,6 +320,105 @@ PassDesc iteration_desc(const JobDev& j, const JobLayout& L, int it, int index, 
   d.V = j.V + (j.trace ? (size_t)(it - 1) * j.N : 0);
   return d;
 }
+
+// ------------------------------------------------------------- launch sets --
+
+namespace {
+SepDesc sep_desc(const JobDev& j, const JobLayout& L, int index, int block_begin) {
+  SepDesc d;
+  d.block_begin = block_begin;
+  d.job = index;
+  d.tiles_x = (j.W + kSepTile - 1) / kSepTile;
+  d.tiles_y = (j.H + kSepTile - 1) / kSepTile;
+  d.plan = L.plan_sep;
+  d.update = 0;
+  d.inv_count = 1.0 / (double)j.M;
+  d.V = j.V;
+  d.out = nullptr;
+  return d;
+}
+}  // namespace
+
+void LaunchSet::add_iteration(const JobDev& j, const JobLayout& L, int it, int index) {
+  const bool sub = j.compressed && it < j.iterations;
+  if (!sub && L.separable) {
+    tabs.push_back(JobSlice{tab_blocks, index});
+    tab_blocks += sep_table_blocks(j.W, j.H, j.N);
+    SepDesc d = sep_desc(j, L, index, sep_blocks);
+    d.update = 1;
+    d.V = j.V + (j.trace ? (size_t)(it - 1) * j.N : 0);
+    sep.push_back(d);
+    sep_blocks += d.plan.blocks;
+    return;
+  }
+  const PassDesc d = iteration_desc(j, L, it, index, pass_blocks);
+  pass.push_back(d);
+  pass_blocks += d.plan.blocks;
+  units = std::max(units, pass_units_per_wave(j.N));
+}
+
+void LaunchSet::add_final(const JobDev& j, const JobLayout& L, int index) {
+  if (L.separable) {
+    tabs.push_back(JobSlice{tab_blocks, index});
+    tab_blocks += sep_table_blocks(j.W, j.H, j.N);
+    SepDesc d = sep_desc(j, L, index, sep_blocks);
+    d.out = j.phi;
+    sep.push_back(d);
+    sep_blocks += d.plan.blocks;
+    sep_final = true;
+    return;
+  }
+  BackDesc b;
+  b.block_begin = back_blocks;
+  b.job = index;
+  b.ps = all_pixels(j.M);
+  b.out = j.phi;
+  back.push_back(b);
+  back_blocks += backprop_blocks(j.M);
+}
+
+size_t LaunchSet::bytes() const {
+  return align_up(sizeof(PassDesc) * pass.size(), 256) + align_up(sizeof(SepDesc) * sep.size(), 256) +
+         align_up(sizeof(JobSlice) * tabs.size(), 256) + align_up(sizeof(BackDesc) * back.size(), 256);
+}
+
+size_t LaunchSet::stage(char* host, char* dev) {
+  size_t o = 0;
+  auto put = [&](const void* src, size_t n) {
+    const size_t at = o;
+    if (n) std::memcpy(host + at, src, n);
+    o = align_up(o + n, 256);
+    return dev + at;
+  };
+  d_pass = reinterpret_cast<const PassDesc*>(put(pass.data(), sizeof(PassDesc) * pass.size()));
+  d_sep = reinterpret_cast<const SepDesc*>(put(sep.data(), sizeof(SepDesc) * sep.size()));
+  d_tabs = reinterpret_cast<const JobSlice*>(put(tabs.data(), sizeof(JobSlice) * tabs.size()));
+  d_back = reinterpret_cast<const BackDesc*>(put(back.data(), sizeof(BackDesc) * back.size()));
+  return o;
+}
+
+void LaunchSet::launch(const JobDev* jobs, hipStream_t s, bool capture) const {
+  auto run = [&](const char* name, auto&& f) {
+    if (capture) f();
+    else timed(s, name, f);
+  };
+  if (!tabs.empty())
+    run("k_sep_tables", [&] { launch_sep_tables(jobs, d_tabs, (int)tabs.size(), tab_blocks, s); });
+  if (!sep.empty())
+    run(sep_final ? "k_sep_final" : "k_sep_pass",
+        [&] { launch_sep_pass(jobs, d_sep, (int)sep.size(), sep_blocks, sep_final, s); });
+  if (!pass.empty()) {
+    bool any_full = false, any_sub = false;
+    for (const PassDesc& d : pass) (d.ps.count == d.ps.M && !d.ps.perm ? any_full : any_sub) = true;
+    run(any_full && any_sub ? "k_pass_mixed" : any_sub ? "k_pass_subset" : "k_pass_full",
+        [&] { launch_pass_batch(jobs, d_pass, (int)pass.size(), pass_blocks, units, s); });
+  }
+  if (!back.empty())
+    run("k_backprop_phi",
+        [&] { launch_backprop_batch(jobs, d_back, (int)back.size(), back_blocks, s); });
+}
+
+// ------------------------------------------------------------------- batch --
 
 hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
                        int32_t* status_dev) {
@@ -340,73 +454,39 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
     jobs_[i] = bind_job(layouts_[i], specs[i], arena_.p + base_off[i],
                         reinterpret_cast<const double*>(arena_.p + raw_off[i]));
   // iteration rounds: round r runs iteration r + 1 of every job with I > r
-  pass_.clear();
-  round_first_.clear();
-  round_count_.clear();
-  round_blocks_.clear();
-  round_units_.clear();
-  round_kind_.clear();
-  for (int r = 0; r < max_rounds; ++r) {
-    const int first = (int)pass_.size();
-    int blocks = 0, units = 1;
-    bool any_sub = false, any_full = false;
-    for (int i = 0; i < count; ++i) {
-      const JobDev& j = jobs_[i];
-      if (r >= j.iterations) continue;
-      const PassDesc d = iteration_desc(j, layouts_[i], r + 1, i, blocks);
-      blocks += d.plan.blocks;
-      units = std::max(units, pass_units_per_wave(j.N));
-      (d.ps.count == j.M ? any_full : any_sub) = true;
-      pass_.push_back(d);
-    }
-    round_first_.push_back(first);
-    round_count_.push_back((int)pass_.size() - first);
-    round_blocks_.push_back(blocks);
-    round_units_.push_back(units);
-    round_kind_.push_back(any_sub && any_full ? kRoundMixed : any_sub ? kRoundSubset : kRoundFull);
-  }
-  back_.clear();
-  back_blocks_ = 0;
+  rounds_.assign(max_rounds, LaunchSet{});
+  for (int r = 0; r < max_rounds; ++r)
+    for (int i = 0; i < count; ++i)
+      if (r < jobs_[i].iterations) rounds_[r].add_iteration(jobs_[i], layouts_[i], r + 1, i);
+  final_ = LaunchSet{};
   perm_.clear();
   perm_blocks_ = 0;
   for (int i = 0; i < count; ++i) {
     const JobDev& j = jobs_[i];
-    if (j.phi) {
-      BackDesc b;
-      b.block_begin = back_blocks_;
-      b.job = i;
-      b.ps = all_pixels(j.M);
-      b.out = j.phi;
-      back_.push_back(b);
-      back_blocks_ += backprop_blocks(j.M);
-    }
+    if (j.phi) final_.add_final(j, layouts_[i], i);
     if (j.compressed) {
       perm_.push_back(JobSlice{perm_blocks_, i});
       perm_blocks_ += perm_blocks(j.M);
     }
   }
-  // descriptor tables: [JobDev][PassDesc][BackDesc][JobSlice]
-  size_t tb = 0;
-  const size_t t_jobs = tb;
-  tb = align_up(tb + sizeof(JobDev) * count, 256);
-  const size_t t_pass = tb;
-  tb = align_up(tb + sizeof(PassDesc) * pass_.size(), 256);
-  const size_t t_back = tb;
-  tb = align_up(tb + sizeof(BackDesc) * back_.size(), 256);
+  // descriptor tables: [JobDev][JobSlice perm][rounds...][final]
+  size_t tb = align_up(sizeof(JobDev) * count, 256);
   const size_t t_perm = tb;
   tb = align_up(tb + sizeof(JobSlice) * perm_.size(), 256);
+  const size_t t_sets = tb;
+  for (const LaunchSet& ls : rounds_) tb += ls.bytes();
+  tb += final_.bytes();
   table_bytes_ = tb;
   HG_TRY(table_.reserve(std::max<size_t>(tb, 256)));
-  jobs_dev_ = reinterpret_cast<JobDev*>(table_.p + t_jobs);
-  pass_dev_ = reinterpret_cast<PassDesc*>(table_.p + t_pass);
-  back_dev_ = reinterpret_cast<BackDesc*>(table_.p + t_back);
-  perm_dev_ = reinterpret_cast<JobSlice*>(table_.p + t_perm);
   HG_TRY(staging_.acquire(tb + host_spot_bytes_));
   std::memset(staging_.p, 0, tb);
-  std::memcpy(staging_.p + t_jobs, jobs_.data(), sizeof(JobDev) * count);
-  if (!pass_.empty()) std::memcpy(staging_.p + t_pass, pass_.data(), sizeof(PassDesc) * pass_.size());
-  if (!back_.empty()) std::memcpy(staging_.p + t_back, back_.data(), sizeof(BackDesc) * back_.size());
+  jobs_dev_ = reinterpret_cast<JobDev*>(table_.p);
+  perm_dev_ = reinterpret_cast<JobSlice*>(table_.p + t_perm);
+  std::memcpy(staging_.p, jobs_.data(), sizeof(JobDev) * count);
   if (!perm_.empty()) std::memcpy(staging_.p + t_perm, perm_.data(), sizeof(JobSlice) * perm_.size());
+  size_t o = t_sets;
+  for (LaunchSet& ls : rounds_) o += ls.stage(staging_.p + o, table_.p + o);
+  o += final_.stage(staging_.p + o, table_.p + o);
   for (int i = 0; i < count; ++i) {
     const JobSpec& s = specs[i];
     if (s.spots_on_device) continue;
@@ -439,21 +519,8 @@ hg_status Batch::enqueue_prologue(hipStream_t s, bool capture) {
 
 hg_status Batch::enqueue(hipStream_t s, bool capture) {
   HG_TRY(enqueue_prologue(s, capture));
-  auto run = [&](const char* name, auto&& launch) {
-    if (capture) launch();
-    else timed(s, name, launch);
-  };
-  static const char* kNames[] = {"k_pass_subset", "k_pass_full", "k_pass_mixed"};
-  for (size_t r = 0; r < round_first_.size(); ++r) {
-    run(kNames[round_kind_[r]], [&] {
-      launch_pass_batch(jobs_dev_, pass_dev_ + round_first_[r], round_count_[r], round_blocks_[r],
-                        round_units_[r], s);
-    });
-  }
-  if (!back_.empty())
-    run("k_backprop_phi", [&] {
-      launch_backprop_batch(jobs_dev_, back_dev_, (int)back_.size(), back_blocks_, s);
-    });
+  for (const LaunchSet& ls : rounds_) ls.launch(jobs_dev_, s, capture);
+  final_.launch(jobs_dev_, s, capture);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess)
     return set_error(HG_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
@@ -484,6 +551,12 @@ hg_status Batch::upload_custom(const void* bytes, size_t size, hipStream_t s, vo
   return HG_OK;
 }
 
+hg_status Batch::custom_device(size_t size, char** dev) {
+  HG_TRY(custom_.reserve(std::max<size_t>(size, 256)));
+  *dev = custom_.p;
+  return HG_OK;
+}
+
 void Batch::release() {
   staging_.release();
   custom_staging_.release();
@@ -491,8 +564,6 @@ void Batch::release() {
   table_.release();
   custom_.release();
   jobs_dev_ = nullptr;
-  pass_dev_ = nullptr;
-  back_dev_ = nullptr;
   perm_dev_ = nullptr;
 }
 

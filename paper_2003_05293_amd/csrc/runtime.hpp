@@ -73,6 +73,7 @@ struct JobSpec {
   double compression = -1.0;  // <= 0: plain WGS (no random order)
   uint64_t seed = 0;
   uint32_t precision = HG_PREC_FP32;
+  bool full_direct = false;   // full-grid passes with the per-pixel kernels
   float* phi = nullptr;       // output hologram (device)
   double* trace_host = nullptr;
 };
@@ -81,6 +82,7 @@ struct JobSpec {
 struct TuneParams {
   int32_t full_block_cap = kDefaultBlockCap;
   int32_t subset_block_cap = kDefaultBlockCap;
+  bool separable_full = true;  // full-grid passes as separable products
 };
 
 // Validation of the host-visible parts of a hologram description.
@@ -93,9 +95,10 @@ hg_status make_spec(const hg_grid* g, const hg_optics* o, const hg_spots* s, int
 // Device scratch of one job, laid out relative to the job's base address.
 struct JobLayout {
   JobDev dev;  // every field but the pointers
-  PassPlan plan_all, plan_sub;
+  PassPlan plan_all, plan_sub, plan_sep;
+  bool separable = false;
   size_t off_raw = 0, off_sp = 0, off_tab = 0, off_perm = 0, off_partial = 0, off_gpart = 0,
-         off_counters = 0, off_V = 0;
+         off_counters = 0, off_V = 0, off_sepF = 0, off_sepB = 0, off_sepG = 0;
   size_t bytes = 0;
   bool raw_inline = false;  // the job's own scratch holds a copy of its spot arrays
 };
@@ -108,6 +111,36 @@ JobDev bind_job(const JobLayout& L, const JobSpec& s, char* base, const double* 
 // Descriptor of iteration `it` (1-based) of job `index` in a launch.
 PassDesc iteration_desc(const JobDev& j, const JobLayout& L, int it, int index, int block_begin);
 PixelSet all_pixels(int32_t M);
+
+// The launches of one iteration round (or of the final phase) of a set of
+// jobs: compressed passes (k_pass_batch), separable full-grid passes (tables
+// then k_sep_pass) and direct full-grid final phases (k_backprop_batch).
+struct LaunchSet {
+  std::vector<PassDesc> pass;
+  int pass_blocks = 0, units = 1;
+  std::vector<SepDesc> sep;
+  int sep_blocks = 0;
+  bool sep_final = false;
+  std::vector<JobSlice> tabs;
+  int tab_blocks = 0;
+  std::vector<BackDesc> back;
+  int back_blocks = 0;
+  // device copies, set by stage()
+  const PassDesc* d_pass = nullptr;
+  const SepDesc* d_sep = nullptr;
+  const JobSlice* d_tabs = nullptr;
+  const BackDesc* d_back = nullptr;
+
+  void add_iteration(const JobDev& j, const JobLayout& L, int it, int index);
+  void add_final(const JobDev& j, const JobLayout& L, int index);
+  bool empty() const { return pass.empty() && sep.empty() && back.empty(); }
+  size_t bytes() const;
+  // Copies the descriptors into host staging at `host` and points the
+  // device copies at `dev` (same offsets); returns the bytes used.
+  size_t stage(char* host, char* dev);
+  // Launches (tables before the separable pass).  `capture`: no timing.
+  void launch(const JobDev* jobs, hipStream_t s, bool capture) const;
+};
 
 // Kernel timing (hg_timing_*).  While enabled, `timed` brackets a launch
 // with two events recorded on its stream; hg_timing_read drains them.
@@ -147,19 +180,20 @@ class Batch {
 
   int count() const { return (int)specs_.size(); }
   const JobDev& job(int i) const { return jobs_[i]; }
+  const JobLayout& layout(int i) const { return layouts_[i]; }
   const JobDev* jobs_device() const { return jobs_dev_; }
   // A descriptor area on the device for ad-hoc single launches.
   hg_status upload_custom(const void* bytes, size_t size, hipStream_t s, void** dev);
+  // Reserves the custom area and returns its device address.
+  hg_status custom_device(size_t size, char** dev);
   void release();
 
  private:
   std::vector<JobSpec> specs_;
   std::vector<JobDev> jobs_;
   std::vector<JobLayout> layouts_;
-  std::vector<PassDesc> pass_;          // every round's descriptors, concatenated
-  std::vector<int> round_first_, round_count_, round_blocks_, round_units_, round_kind_;
-  std::vector<BackDesc> back_;
-  int back_blocks_ = 0;
+  std::vector<LaunchSet> rounds_;        // one per iteration round
+  LaunchSet final_;                      // final phases
   std::vector<JobSlice> perm_;
   int perm_blocks_ = 0;
   bool perm_lds_ = true;
@@ -170,15 +204,11 @@ class Batch {
   DevBuf<char> table_;
   DevBuf<char> custom_;
   JobDev* jobs_dev_ = nullptr;
-  PassDesc* pass_dev_ = nullptr;
-  BackDesc* back_dev_ = nullptr;
   JobSlice* perm_dev_ = nullptr;
   size_t table_bytes_ = 0;
   Staging staging_;
   Staging custom_staging_;
 };
 
-// Round kinds for timing tags.
-enum RoundKind { kRoundSubset = 0, kRoundFull = 1, kRoundMixed = 2 };
 
 }  // namespace hg

@@ -127,15 +127,35 @@ def test_backward_vs_oracle(W, H, N, seed):
     assert st["rms"] < 1e-4 and st["p999"] < 2e-3
 
 
-def test_backward_all_pixels_layout():
+@pytest.mark.parametrize("direct", [False, True])
+def test_backward_all_pixels_layout(direct):
     g = Grid(97, 61)
     s = spot_cloud(8, 9, g)
     w = np.linspace(0.7, 1.3, 9)
     th = np.linspace(0, 6, 9)
-    say("backward all pixels 97x61")
-    phi = to_np(hg.backward(g, OPTICS, s, w, th))
+    say("backward all pixels 97x61 direct" if direct else "backward all pixels 97x61 separable")
+    phi = to_np(hg.backward(g, OPTICS, s, w, th, direct=direct))
     want = oracle.backward(g, OPTICS, s, w, th)
     assert err_stats(wrapped(phi, want))["max"] < 1e-3
+
+
+@pytest.mark.parametrize("W,H,N", [(1152, 1152, 100), (1920, 1152, 150), (130, 65, 3)])
+def test_backward_full_grid_separable(W, H, N):
+    """Full-grid back-propagation as the separable product: the FP64 tables
+    make the phases exact to FP32 rounding, so the error is far below the
+    per-pixel path's."""
+    g = Grid(W, H)
+    s = spot_cloud(W + N, N, g, z_half_mm=0.1)
+    rng = np.random.default_rng(N)
+    w = rng.uniform(0.5, 1.5, N)
+    th = rng.uniform(-math.pi, math.pi, N)
+    say("backward separable", W, H, N)
+    phi = to_np(hg.backward(g, OPTICS, s, w, th))
+    idx = np.sort(rng.choice(g.M, min(g.M, 60000), replace=False))
+    want = oracle.backward(g, OPTICS, s, w, th, idx)
+    st = err_stats(wrapped(phi[idx], want))
+    print("separable backward wrapped Phi error", W, H, N, st)
+    assert st["rms"] < 2e-5 and st["p999"] < 5e-4
 
 
 # ------------------------------------------------------------ forward ---
@@ -161,9 +181,12 @@ def test_forward_phi_held_fixed(W, H, N, seed, sub):
     assert np.max(np.abs(Vg - Vo)) <= REL_V * np.abs(Vo).mean() * 3
 
 
-@pytest.mark.parametrize("W,H,N,seed,sub", [(256, 256, 16, 0, None), (1152, 1152, 100, 3, 1 / 16),
-                                            (333, 129, 65, 9, 0.25), (64, 64, 1, 2, None)])
-def test_step_state_held_fixed(W, H, N, seed, sub):
+@pytest.mark.parametrize("W,H,N,seed,sub,direct", [
+    (256, 256, 16, 0, None, False), (256, 256, 16, 0, None, True), (1152, 1152, 100, 3, 1 / 16, False),
+    (1152, 1152, 100, 4, None, False), (1152, 1152, 100, 4, None, True),
+    (333, 129, 65, 9, 0.25, False), (333, 129, 65, 9, None, False), (64, 64, 1, 2, None, False),
+    (200, 70, 129, 5, None, False)])
+def test_step_state_held_fixed(W, H, N, seed, sub, direct):
     g = Grid(W, H)
     s = spot_cloud(seed, N, g)
     rng = np.random.default_rng(seed + 100)
@@ -171,11 +194,12 @@ def test_step_state_held_fixed(W, H, N, seed, sub):
     th = rng.uniform(0, 2 * math.pi, N)
     idx = None if sub is None else oracle.subset(g.M, seed, 2, sub)
     say("step", W, H, N, sub)
-    Vg = hg.step(g, OPTICS, s, w, th, idx=None if idx is None else to_dev(idx, "int32"))
+    Vg = hg.step(g, OPTICS, s, w, th, idx=None if idx is None else to_dev(idx, "int32"),
+                 direct=direct)
     p = np.arange(g.M) if idx is None else idx
     Vo = oracle.forward(g, OPTICS, s, oracle.backward(g, OPTICS, s, w, th, p), p)
     e = rel_mag_err(Vg, Vo)
-    print("step |V| rel err", W, H, N, sub, e)
+    print("step |V| rel err", W, H, N, sub, "direct" if direct else "", e)
     assert e <= REL_V
 
 
@@ -244,6 +268,18 @@ def _run_and_compare(g, s, I, c, seed, tag):
 def test_wgs_256_n16_i20():
     g = Grid(256, 256)
     _run_and_compare(g, spot_cloud(0, 16, g), 20, None, 0, "wgs")
+
+
+def test_wgs_separable_and_direct_agree():
+    g = Grid(320, 240)
+    s = spot_cloud(5, 40, g)
+    say("wgs separable vs direct")
+    a = hg.wgs(g, OPTICS, s, 10, 5)
+    b = hg.cswgs(g, OPTICS, s, 10, 1.0, 5, direct=True)  # c = 1: every pass over all pixels
+    eo, uo, _ = oracle.metrics(g, OPTICS, s, oracle.wgs(g, OPTICS, s, 10, 5))
+    for phi in (a, b):
+        e, u, _ = hg.metrics(g, OPTICS, s, phi)
+        assert abs(e - eo) < 1e-4 and abs(u - uo) < 1e-4
 
 
 @pytest.mark.parametrize("c", [1 / 16, 1 / 4, 1.0])
