@@ -43,6 +43,10 @@ CLOUDS = 10
 FLOPS_BACK = 10
 FLOPS_FWD = 14
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (256 CU, 2.4 GHz, packed FMA)
+# Launch tags of the library's kernel timing (hg_timing_read).
+KERNELS = ("k_setup", "k_perm", "k_sep_tables", "k_sep_pass", "k_sep_final", "k_pass_subset",
+           "k_pass_full", "k_pass_mixed", "k_backprop_phi", "k_mx_tables", "k_mx_subset",
+           "k_mx_full", "k_mx_final")
 
 
 def cpu_baseline(grid, optics, spots, seed):
@@ -83,6 +87,35 @@ def cpu_baseline(grid, optics, spots, seed):
                    f"scaled to 2 full back + 1 full forward + {ITER - 1} compressed iterations "
                    f"= {per_holo:.1f} s per hologram"),
     }
+
+
+def single_form(hg, grid, clouds, spots_dev, phis, stream, form, steps, warmup, gold):
+    """One hologram per call on one stream in the given precision, with its
+    e, u error against the stored FP64 oracle result of the seed-0 cloud."""
+    import torch
+    from workload import OPTICS
+    for k in range(warmup):
+        hg.cswgs_device(grid, OPTICS, spots_dev[k % CLOUDS], ITER, COMP, k % CLOUDS,
+                        phi=phis[k % CLOUDS], stream=stream, precision=form)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record(stream)
+    for k in range(steps):
+        hg.cswgs_device(grid, OPTICS, spots_dev[k % CLOUDS], ITER, COMP, k % CLOUDS,
+                        phi=phis[k % CLOUDS], stream=stream, precision=form)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    hg.cswgs_device(grid, OPTICS, spots_dev[0], ITER, COMP, 0, phi=phis[0], stream=stream,
+                    precision=form)
+    e, u, _ = hg.metrics(grid, OPTICS, clouds[0], phis[0])
+    out = {"holograms_per_s": round(1000.0 / ms, 3), "ms_per_hologram": round(ms, 5),
+           "how": "one hologram per call, back to back on one stream", "e": e, "u": u}
+    if gold is not None:
+        out.update({"e_abs_err": abs(e - gold["e"]), "u_abs_err": abs(u - gold["u"])})
+    print(f"[bench] {form}: {ms:.4f} ms per hologram, e {e:.6f} u {u:.6f}", file=sys.stderr,
+          flush=True)
+    return out
 
 
 def _time_batch(torch, batch, stream, runs):
@@ -163,7 +196,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--form", default="fp32", choices=["fp32"])
+    ap.add_argument("--form", default="fp32", choices=["fp32", "mixed"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch", type=int, default=32, help="holograms per batched launch")
@@ -219,16 +252,25 @@ def main():
     torch.cuda.synchronize()
     hg.timing_enable(False)
     kern = {}
-    for name in ("k_pass_subset", "k_pass_full", "k_backprop_phi"):
+    for name in KERNELS:
         ms, cnt = hg.timing_read(name)
-        kern[name] = {"total_ms": ms, "launches": cnt, "avg_us": 1000.0 * ms / max(cnt, 1)}
+        if cnt:
+            kern[name] = {"total_ms": ms, "launches": cnt, "avg_us": 1000.0 * ms / cnt}
     dominant = max(kern, key=lambda k: kern[k]["total_ms"])
     m = math.ceil(COMP * W * H)
-    pixels = {"k_pass_subset": m, "k_pass_full": W * H}
-    if dominant in pixels:
-        flops = pixels[dominant] * N * (FLOPS_BACK + FLOPS_FWD)
-    else:
-        flops = W * H * N * FLOPS_BACK
+    # (pixel, spot) pairs per launch and the steps each launch performs
+    pairs = {"k_pass_subset": (m, FLOPS_BACK + FLOPS_FWD),
+             "k_pass_full": (W * H, FLOPS_BACK + FLOPS_FWD),
+             "k_sep_pass": (W * H, FLOPS_BACK + FLOPS_FWD),
+             "k_sep_final": (W * H, FLOPS_BACK),
+             "k_backprop_phi": (W * H, FLOPS_BACK),
+             "k_mx_subset": (m, FLOPS_BACK + FLOPS_FWD),
+             "k_mx_full": (W * H, FLOPS_BACK + FLOPS_FWD),
+             "k_mx_final": (W * H, FLOPS_BACK)}
+    if dominant not in pairs:
+        raise RuntimeError(f"dominant kernel {dominant} has no algorithmic flop count")
+    px, fl = pairs[dominant]
+    flops = px * N * fl
     achieved = flops / (kern[dominant]["avg_us"] * 1e-6) / 1e12
     roofline = {
         "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
@@ -243,17 +285,23 @@ def main():
     # Accuracy of the seed-0 hologram against the stored FP64 oracle run.
     accuracy = None
     gold = os.path.join(ROOT, "tests", "golden", "cswgs_1152x1152_n100_i30_c16_seed0.json")
-    step(0)
-    e, u, _ = hg.metrics(grid, OPTICS, clouds[0], phis[0])
-    accuracy = {"e": e, "u": u}
+    gd = None
     if os.path.exists(gold):
         with open(gold) as f:
             gd = json.load(f)
+    step(0)
+    e, u, _ = hg.metrics(grid, OPTICS, clouds[0], phis[0])
+    accuracy = {"e": e, "u": u}
+    if gd is not None:
         accuracy.update({"e_oracle": gd["e"], "u_oracle": gd["u"],
                          "e_abs_err": abs(e - gd["e"]), "u_abs_err": abs(u - gd["u"])})
 
-    forms = {"fp32": {"holograms_per_s": round(value, 3), "ms_per_hologram": round(ms_per_step, 5),
-                      "how": "one hologram per call, back to back on one stream"}}
+    forms = {args.form: {"holograms_per_s": round(value, 3),
+                         "ms_per_hologram": round(ms_per_step, 5),
+                         "how": "one hologram per call, back to back on one stream"}}
+    other = "mixed" if args.form == "fp32" else "fp32"
+    forms[other] = single_form(hg, grid, clouds, spots_dev, phis, stream, other, args.steps,
+                               args.warmup, gd)
     if not args.no_batched:
         forms.update(batched_forms(hg, grid, OPTICS, args.steps, args.batch))
     if args.serve_seconds > 0:
