@@ -89,28 +89,51 @@ def cpu_baseline(grid, optics, spots, seed):
     }
 
 
-def single_form(hg, grid, clouds, spots_dev, phis, stream, form, steps, warmup, gold):
+def kernel_times(hg, run, count):
+    """Per-family kernel durations (HIP events on the launch stream) over
+    `count` calls of run(k)."""
+    import torch
+    hg.timing_reset()
+    hg.timing_enable(True)
+    for k in range(count):
+        run(k)
+    torch.cuda.synchronize()
+    hg.timing_enable(False)
+    kern = {}
+    for name in KERNELS:
+        ms, cnt = hg.timing_read(name)
+        if cnt:
+            kern[name] = {"total_ms": ms, "launches": cnt, "avg_us": 1000.0 * ms / cnt}
+    return kern
+
+
+def single_form(hg, grid, clouds, spots_dev, phis, stream, form, steps, warmup, gold, tune):
     """One hologram per call on one stream in the given precision, with its
     e, u error against the stored FP64 oracle result of the seed-0 cloud."""
     import torch
     from workload import OPTICS
     for k in range(warmup):
         hg.cswgs_device(grid, OPTICS, spots_dev[k % CLOUDS], ITER, COMP, k % CLOUDS,
-                        phi=phis[k % CLOUDS], stream=stream, precision=form)
+                        phi=phis[k % CLOUDS], stream=stream, precision=form, tune=tune)
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     a.record(stream)
     for k in range(steps):
         hg.cswgs_device(grid, OPTICS, spots_dev[k % CLOUDS], ITER, COMP, k % CLOUDS,
-                        phi=phis[k % CLOUDS], stream=stream, precision=form)
+                        phi=phis[k % CLOUDS], stream=stream, precision=form, tune=tune)
     b.record(stream)
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / steps
+    kern = kernel_times(hg, lambda k: hg.cswgs_device(
+        grid, OPTICS, spots_dev[k % CLOUDS], ITER, COMP, k % CLOUDS, phi=phis[k % CLOUDS],
+        stream=stream, precision=form, tune=tune), min(steps, 10))
     hg.cswgs_device(grid, OPTICS, spots_dev[0], ITER, COMP, 0, phi=phis[0], stream=stream,
-                    precision=form)
+                    precision=form, tune=tune)
     e, u, _ = hg.metrics(grid, OPTICS, clouds[0], phis[0])
     out = {"holograms_per_s": round(1000.0 / ms, 3), "ms_per_hologram": round(ms, 5),
-           "how": "one hologram per call, back to back on one stream", "e": e, "u": u}
+           "how": "one hologram per call, back to back on one stream", "e": e, "u": u,
+           "kernels": {k: {"avg_us": round(v["avg_us"], 3), "launches_per_hologram":
+                           v["launches"] / min(steps, 10)} for k, v in kern.items()}}
     if gold is not None:
         out.update({"e_abs_err": abs(e - gold["e"]), "u_abs_err": abs(u - gold["u"])})
     print(f"[bench] {form}: {ms:.4f} ms per hologram, e {e:.6f} u {u:.6f}", file=sys.stderr,
@@ -141,11 +164,14 @@ def batched_forms(hg, grid, optics, steps, bsize):
     out = {}
     jobs = [hg.DeviceJob.from_spots(grid, optics, spot_cloud(100 + k, N, grid), ITER, COMP,
                                     100 + k) for k in range(bsize)]
-    batch = hg.Batch(jobs, use_graph=True)
+    from paper_2003_05293_amd import autotune
+    tuned = autotune.tune_batch(jobs, reps=2, stream=stream)
+    batch = hg.Batch(jobs, tune=autotune.Table.as_tune(tuned), use_graph=True)
     runs = max(1, steps // bsize + 1)
     ms = _time_batch(torch, batch, stream, runs)
     out["fp32_batched"] = {"holograms_per_s": round(1000.0 * bsize / ms, 3),
                            "ms_per_batch": round(ms, 4), "batch": bsize, "runs": runs,
+                           "tune": autotune.Table.as_tune(tuned),
                            "how": f"{bsize} holograms of this workload per graph-captured batch"}
     print(f"[bench] batched x{bsize}: {ms:.3f} ms per batch", file=sys.stderr, flush=True)
     batch.close()
@@ -155,10 +181,12 @@ def batched_forms(hg, grid, optics, steps, bsize):
              for j in mixed]
     terms = sum((j.grid.M * 3 + 2 * (j.iterations - 1) * math.ceil(j.compression * j.grid.M))
                 * j.spots.n for j in mixed)
-    batch = hg.Batch(mjobs, use_graph=True)
+    tuned = autotune.tune_batch(mjobs, reps=2, stream=stream)
+    batch = hg.Batch(mjobs, tune=autotune.Table.as_tune(tuned), use_graph=True)
     ms = _time_batch(torch, batch, stream, 3)
     out["fp32_mixed64"] = {"holograms_per_s": round(64000.0 / ms, 3), "ms_per_batch": round(ms, 4),
                            "terms_per_s": round(terms / (ms * 1e-3), 1),
+                           "tune": autotune.Table.as_tune(tuned),
                            "how": "64 mixed holograms (sizes 512^2..1920x1152, N 8..200, I 30, "
                                   "c 1/16) per graph-captured batch"}
     print(f"[bench] mixed64: {ms:.3f} ms per batch", file=sys.stderr, flush=True)
@@ -220,10 +248,16 @@ def main():
     phis = [torch.empty(W * H, dtype=torch.float32, device="cuda") for _ in range(CLOUDS)]
     stream = torch.cuda.current_stream()
 
+    # launch geometry of the compressed passes, chosen by the autotuner
+    from paper_2003_05293_amd import autotune
+    tuned = autotune.tune_single(grid, OPTICS, clouds[0], ITER, COMP, precision="fp32", reps=5)
+    tune = autotune.Table.as_tune(tuned)
+    print(f"[bench] autotuned {tune} ({tuned['ms']:.4f} ms)", file=sys.stderr, flush=True)
+
     def step(k):
         s = k % CLOUDS
         hg.cswgs_device(grid, OPTICS, spots_dev[s], ITER, COMP, s, phi=phis[s], stream=stream,
-                        precision=args.form)
+                        precision=args.form, tune=tune)
 
     for k in range(args.warmup):
         step(k)
@@ -301,7 +335,7 @@ def main():
                          "how": "one hologram per call, back to back on one stream"}}
     other = "mixed" if args.form == "fp32" else "fp32"
     forms[other] = single_form(hg, grid, clouds, spots_dev, phis, stream, other, args.steps,
-                               args.warmup, gd)
+                               args.warmup, gd, tune)
     if not args.no_batched:
         forms.update(batched_forms(hg, grid, OPTICS, args.steps, args.batch))
     if args.serve_seconds > 0:
@@ -319,7 +353,8 @@ def main():
         "data": "synthetic", "wall_s": round(wall, 4),
         "config": {"workload": WORKLOAD, "W": W, "H": H, "N": N, "iterations": ITER,
                    "compression": COMP, "form": args.form, "clouds": CLOUDS,
-                   "spots": "resident in HBM"},
+                   "spots": "resident in HBM", "tune": tune,
+                   "tune_sweep_ms": {k: round(v, 4) for k, v in tuned["sweep_ms"].items()}},
         "roofline": roofline, "accuracy": accuracy, "forms": forms, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -110,6 +110,17 @@ typedef struct hg_spots {
 #define HG_FULL_DIRECT 0x200u
 
 /* Extended parameters of hg_cswgs_ex. */
+/* Launch geometry of the passes, 0 meaning the default: a pass runs on
+ * min(tiles, cap) blocks that take its tiles of pixels dynamically
+ * (full-grid and compressed passes have separate caps).  Partial sums are
+ * kept per tile, whichever block computes it, so the geometry never changes
+ * the results, only the speed.  Chosen per shape by the package's
+ * autotuner. */
+typedef struct hg_tune {
+  int32_t full_block_cap;
+  int32_t subset_block_cap;
+} hg_tune;
+
 typedef struct hg_params {
   int32_t iterations;    /* I >= 0                                          */
   double compression;    /* c in (0, 1]; 1 gives WGS                        */
@@ -117,6 +128,7 @@ typedef struct hg_params {
   uint32_t flags;        /* HG_PREC_*                                       */
   double *trace_V;       /* NULL, or host [iterations][N][2] doubles: the
                             spot field V^j (re, im) of every iteration j    */
+  hg_tune tune;          /* launch geometry (zeros: defaults)               */
 } hg_params;
 
 /* ---------------------------------------------------------------------- */
@@ -183,21 +195,11 @@ typedef struct hg_job {
   double *trace_V;
 } hg_job;
 
-/* Launch geometry of the passes, 0 meaning the default: a pass of P pixels
- * runs on min(ceil(P/64), cap) blocks (full-grid and compressed passes have
- * separate caps).  It fixes the summation order, so results are
- * bit-identical for equal caps and may differ in the last bits otherwise.
- * Chosen per shape by the package's autotuner. */
-typedef struct hg_tune {
-  int32_t full_block_cap;
-  int32_t subset_block_cap;
-} hg_tune;
-
 /* Runs `count` holograms together (paper section 2 for each; the paper
  * computes one hologram at a time): one launch per iteration round covers
  * every hologram still iterating, so the per-iteration reductions of one
  * hologram overlap the work of the others.  Each hologram's result is
- * bit-identical to computing it alone with the same tune.  tune may be
+ * bit-identical to computing it alone.  tune may be
  * NULL.  Asynchronous unless a job asks for a trace. */
 hg_status hg_cswgs_batch(int32_t count, const hg_job *jobs, const hg_tune *tune,
                          void *stream);

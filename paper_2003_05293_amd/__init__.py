@@ -81,7 +81,8 @@ class _EngineConfig(ctypes.Structure):
 
 class _Params(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("compression", ctypes.c_double),
-                ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("trace_V", _DP)]
+                ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("trace_V", _DP),
+                ("tune", _Tune)]
 
 
 def lib_path() -> str:
@@ -250,22 +251,24 @@ def wgs(grid, optics, spots, iterations: int, seed: int, phi=None, stream=None):
 
 
 def cswgs(grid, optics, spots, iterations: int, compression: float, seed: int, phi=None,
-          stream=None, precision: str = "fp32", trace: bool = False, direct: bool = False):
+          stream=None, precision: str = "fp32", trace: bool = False, direct: bool = False,
+          tune=None):
     """Compressed-sensing WGS hologram.  With trace=True returns (phi, V)
     where V[j-1] is the complex spot field of iteration j.  direct=True
-    computes the full-grid passes with the per-pixel kernels."""
+    computes the full-grid passes with the per-pixel kernels.  tune: launch
+    geometry {"full_block_cap", "subset_block_cap"} (see autotune)."""
     lib = load()
     phi = _new_phi(grid) if phi is None else phi
     sa = _SpotArgs(spots)
     flags = _flags(precision) | (FULL_DIRECT if direct else 0)
-    if precision == "fp32" and not trace and not direct:
+    if precision == "fp32" and not trace and not direct and tune is None:
         _check(lib.hg_cswgs(_grid(grid), _optics(optics), sa.struct, int(iterations),
                             float(compression), int(seed),
                             _dev_f32(phi, grid.W * grid.H, "phi"), _stream(stream)))
         return phi
     tr = np.zeros((max(int(iterations), 1), sa.n, 2)) if trace else None
     params = _Params(int(iterations), float(compression), int(seed), flags,
-                     tr.ctypes.data_as(_DP) if trace else None)
+                     tr.ctypes.data_as(_DP) if trace else None, _tune(tune) or _Tune(0, 0))
     _check(lib.hg_cswgs_ex(_grid(grid), _optics(optics), sa.struct, ctypes.byref(params),
                            _dev_f32(phi, grid.W * grid.H, "phi"), _stream(stream)))
     if trace:
@@ -355,7 +358,7 @@ def step(grid, optics, spots, w, theta, idx=None, precision: str = "fp32",
 
 
 def cswgs_device(grid, optics, spots_dev, iterations: int, compression: float, seed: int,
-                 phi=None, stream=None, precision: str = "fp32"):
+                 phi=None, stream=None, precision: str = "fp32", tune=None):
     """CS-WGS with the spot arrays already on the GPU: spots_dev is a float64
     GPU tensor of shape (4, N) holding x_mm, y_mm, z_mm, amp."""
     import torch
@@ -370,7 +373,7 @@ def cswgs_device(grid, optics, spots_dev, iterations: int, compression: float, s
     sp = _Spots(n, *ptrs)
     phi = _new_phi(grid) if phi is None else phi
     params = _Params(int(iterations), float(compression), int(seed),
-                     _flags(precision) | SPOTS_ON_DEVICE, None)
+                     _flags(precision) | SPOTS_ON_DEVICE, None, _tune(tune) or _Tune(0, 0))
     _check(lib.hg_cswgs_ex(_grid(grid), _optics(optics), sp, ctypes.byref(params),
                            _dev_f32(phi, grid.W * grid.H, "phi"), _stream(stream)))
     return phi

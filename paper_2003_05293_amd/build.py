@@ -19,7 +19,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhg.so")
-SOURCES = ["kernels.hip", "runtime.hip", "api.hip", "engine.hip"]
+SOURCES = ["kernels.hip", "kernels_mx.hip", "runtime.hip", "api.hip", "engine.hip"]
 ARCH = "gfx950"
 
 HIP_FLAGS = [
@@ -40,15 +40,18 @@ def build(verbose: bool = False) -> str:
     """Compile every source and link libhg.so; returns its path."""
     cc = hipcc()
     with tempfile.TemporaryDirectory(prefix="hg_build_") as tmp:
-        objs = []
+        objs, procs = [], []
         for src in SOURCES:
             obj = os.path.join(tmp, os.path.splitext(src)[0] + ".o")
             cmd = [cc, *HIP_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c",
                    os.path.join(CSRC, src), "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
-            subprocess.run(cmd, check=True)
+            procs.append((cmd, subprocess.Popen(cmd)))
             objs.append(obj)
+        for cmd, proc in procs:
+            if proc.wait() != 0:
+                raise subprocess.CalledProcessError(proc.returncode, cmd)
         out_tmp = os.path.join(tmp, "libhg.so")
         cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", out_tmp]
         if verbose:

@@ -92,8 +92,11 @@ hg_status check_launch() {
 
 hg_status validate_flags(uint32_t flags, uint32_t allowed_extra) {
   if (flags & ~(HG_PREC_MASK | allowed_extra)) return set_error(HG_EINVAL, "flags: unknown bits set");
-  if ((flags & HG_PREC_MASK) != HG_PREC_FP32)
-    return set_error(HG_EINVAL, "flags: only HG_PREC_FP32 is available in this build");
+  const uint32_t prec = flags & HG_PREC_MASK;
+  if (prec != HG_PREC_FP32 && prec != HG_PREC_MIXED)
+    return set_error(HG_EINVAL, "flags: precision must be HG_PREC_FP32 or HG_PREC_MIXED");
+  if (prec == HG_PREC_MIXED && (flags & HG_FULL_DIRECT))
+    return set_error(HG_EINVAL, "flags: HG_FULL_DIRECT applies to HG_PREC_FP32 only");
   return HG_OK;
 }
 
@@ -102,10 +105,17 @@ hg_status check_compression(double c) {
   return HG_OK;
 }
 
+hg::TuneParams tune_params(const hg_tune* t) {
+  hg::TuneParams tp;
+  if (t && t->full_block_cap > 0) tp.full_block_cap = t->full_block_cap;
+  if (t && t->subset_block_cap > 0) tp.subset_block_cap = t->subset_block_cap;
+  return tp;
+}
+
 // The shared schedule of RS (I = 0), WGS (c < 0) and CS-WGS: a batch of one.
 hg_status run_one(const hg_grid* g, const hg_optics* o, const hg_spots* s, int32_t iterations,
                   double c, uint64_t seed, uint32_t flags, float* phi, double* trace_host,
-                  void* stream) {
+                  void* stream, const hg::TuneParams& tp = hg::TuneParams{}) {
   hg::JobSpec spec;
   HG_TRY(hg::make_spec(g, o, s, iterations, c, seed, flags, phi, trace_host, &spec));
   if (!phi) return set_error(HG_EINVAL, "phi_dev must be non-NULL");
@@ -113,7 +123,7 @@ hg_status run_one(const hg_grid* g, const hg_optics* o, const hg_spots* s, int32
   HG_TRY(get_workspace(stream, &ws));
   std::lock_guard<std::mutex> lk(ws->mu);
   HG_TRY(ws->init_status());
-  HG_TRY(ws->batch.build(&spec, 1, hg::TuneParams{}, ws->status.p));
+  HG_TRY(ws->batch.build(&spec, 1, tp, ws->status.p));
   HG_TRY(ws->batch.enqueue(ws->stream));
   if (trace_host) {
     HG_TRY(ws->batch.fetch_traces(ws->stream));
@@ -137,6 +147,14 @@ hg_status check_state(const hg_spots* spots, const double* w, const double* thet
   return HG_OK;
 }
 
+// The mixed-precision passes work on the whole grid (or a window of the
+// random order), not on explicit pixel lists.
+hg_status check_mixed_set(uint32_t flags, const int32_t* idx_dev) {
+  if ((flags & HG_PREC_MASK) == HG_PREC_MIXED && idx_dev)
+    return set_error(HG_EINVAL, "HG_PREC_MIXED hooks take the whole grid: idx_dev must be NULL");
+  return HG_OK;
+}
+
 hg::PixelSet pixel_set(const int32_t* idx, int32_t m, int32_t M) {
   hg::PixelSet ps;
   ps.perm = nullptr;
@@ -157,7 +175,7 @@ hg_status set_state(Workspace* ws, int N, const double* w, const double* theta) 
   HG_HIP(hipMemcpyAsync(ws->raw.p, st, sizeof(double) * 2 * N, hipMemcpyHostToDevice,
                         ws->stream));
   HG_TRY(ws->staging.mark_copied(ws->stream));
-  hg::launch_set_state(N, ws->raw.p, ws->batch.job(0).sp, ws->stream);
+  hg::launch_set_state(N, ws->raw.p, ws->batch.job(0).sp, ws->batch.job(0).coef, ws->stream);
   return HG_OK;
 }
 
@@ -172,12 +190,14 @@ hg_status single_pass(Workspace* ws, const hg::PixelSet& ps, bool from_phi, doub
   d.plan = hg::plan_pass(ps.count, hg::kDefaultBlockCap);
   d.update = 0;
   d.from_phi = from_phi ? 1 : 0;
+  d.grab_slot = 0;
   d.inv_count = 1.0 / (double)ps.count;
   d.V = j.V;
   void* dev = nullptr;
   HG_TRY(ws->batch.upload_custom(&d, sizeof(d), ws->stream, &dev));
   hg::launch_pass_batch(ws->batch.jobs_device(), reinterpret_cast<const hg::PassDesc*>(dev), 1,
-                        d.plan.blocks, hg::pass_units_per_wave(j.N), ws->stream);
+                        d.plan.blocks, hg::pass_units_per_wave(j.N),
+                        from_phi ? 0 : hg::pass_e_width(j.N), ws->stream);
   HG_TRY(check_launch());
   HG_HIP(hipMemcpyAsync(V_out, j.V, sizeof(double2) * j.N, hipMemcpyDeviceToHost, ws->stream));
   HG_HIP(hipStreamSynchronize(ws->stream));
@@ -196,12 +216,6 @@ hg_status single_set(Workspace* ws, hg::LaunchSet& set) {
   return check_launch();
 }
 
-hg::TuneParams tune_params(const hg_tune* t) {
-  hg::TuneParams tp;
-  if (t && t->full_block_cap > 0) tp.full_block_cap = t->full_block_cap;
-  if (t && t->subset_block_cap > 0) tp.subset_block_cap = t->subset_block_cap;
-  return tp;
-}
 
 hg_status job_specs(int32_t count, const hg_job* jobs, const hg_tune* tune,
                     std::vector<hg::JobSpec>* out) {
@@ -264,8 +278,10 @@ hg_status hg_cswgs_ex(const hg_grid* grid, const hg_optics* optics, const hg_spo
   if (!params) return set_error(HG_EINVAL, "params must be non-NULL");
   HG_TRY(check_compression(params->compression));
   HG_TRY(validate_flags(params->flags, HG_SPOTS_ON_DEVICE | HG_FULL_DIRECT));
+  if (params->tune.full_block_cap < 0 || params->tune.subset_block_cap < 0)
+    return set_error(HG_EINVAL, "tune caps must be >= 0");
   return run_one(grid, optics, spots, params->iterations, params->compression, params->seed,
-                 params->flags, phi_dev, params->trace_V, stream);
+                 params->flags, phi_dev, params->trace_V, stream, tune_params(&params->tune));
 }
 
 hg_status hg_metrics(const hg_grid* grid, const hg_optics* optics, const hg_spots* spots,
@@ -377,7 +393,9 @@ hg_status hg_forward(const hg_grid* grid, const hg_optics* optics, const hg_spot
   hg::JobSpec spec;
   HG_TRY(hg::make_spec(grid, optics, spots, 0, -1.0, 0, flags, const_cast<float*>(phi_dev),
                        nullptr, &spec));
+  spec.hook = true;
   HG_TRY(check_set(grid, idx_dev, m));
+  HG_TRY(check_mixed_set(flags, idx_dev));
   if (!phi_dev || !V_out) return set_error(HG_EINVAL, "phi_dev and V_out must be non-NULL");
   Workspace* ws = nullptr;
   HG_TRY(get_workspace(stream, &ws));
@@ -385,6 +403,15 @@ hg_status hg_forward(const hg_grid* grid, const hg_optics* optics, const hg_spot
   HG_TRY(ws->init_status());
   HG_TRY(ws->batch.build(&spec, 1, hg::TuneParams{}, ws->status.p));
   HG_TRY(ws->batch.enqueue_prologue(ws->stream));
+  if (spec.precision == HG_PREC_MIXED) {
+    const hg::JobDev& j = ws->batch.job(0);
+    hg::LaunchSet set;
+    set.add_forward_mx(j, ws->batch.layout(0), 0);
+    HG_TRY(single_set(ws, set));
+    HG_HIP(hipMemcpyAsync(V_out, j.V, sizeof(double2) * j.N, hipMemcpyDeviceToHost, ws->stream));
+    HG_HIP(hipStreamSynchronize(ws->stream));
+    return ws->take_status();
+  }
   return single_pass(ws, pixel_set(idx_dev, m, grid->W * grid->H), true, V_out);
 }
 
@@ -395,8 +422,10 @@ hg_status hg_backward(const hg_grid* grid, const hg_optics* optics, const hg_spo
   hg::JobSpec spec;
   HG_TRY(hg::make_spec(grid, optics, spots, 0, -1.0, 0, flags, idx_dev ? nullptr : phi_dev,
                        nullptr, &spec));
+  spec.hook = true;
   HG_TRY(check_state(spots, w, theta));
   HG_TRY(check_set(grid, idx_dev, m));
+  HG_TRY(check_mixed_set(flags, idx_dev));
   if (!phi_dev) return set_error(HG_EINVAL, "phi_dev must be non-NULL");
   Workspace* ws = nullptr;
   HG_TRY(get_workspace(stream, &ws));
@@ -428,8 +457,10 @@ hg_status hg_step(const hg_grid* grid, const hg_optics* optics, const hg_spots* 
   HG_TRY(validate_flags(flags, HG_FULL_DIRECT));
   hg::JobSpec spec;
   HG_TRY(hg::make_spec(grid, optics, spots, 0, -1.0, 0, flags, nullptr, nullptr, &spec));
+  spec.hook = true;
   HG_TRY(check_state(spots, w, theta));
   HG_TRY(check_set(grid, idx_dev, m));
+  HG_TRY(check_mixed_set(flags, idx_dev));
   if (!V_out) return set_error(HG_EINVAL, "V_out must be non-NULL");
   Workspace* ws = nullptr;
   HG_TRY(get_workspace(stream, &ws));
@@ -445,7 +476,8 @@ hg_status hg_step(const hg_grid* grid, const hg_optics* optics, const hg_spots* 
     jj.iterations = 1;
     hg::LaunchSet set;
     set.add_iteration(jj, ws->batch.layout(0), 1, 0);
-    set.sep[0].update = 0;
+    if (!set.sep.empty()) set.sep[0].update = 0;
+    if (!set.mx.empty()) set.mx[0].update = 0;
     HG_TRY(single_set(ws, set));
     HG_HIP(hipMemcpyAsync(V_out, j.V, sizeof(double2) * j.N, hipMemcpyDeviceToHost, ws->stream));
     HG_HIP(hipStreamSynchronize(ws->stream));

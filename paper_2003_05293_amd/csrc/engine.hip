@@ -88,8 +88,11 @@ hg_status spec_from_job(const hg_job& j, hg::JobSpec* out) {
     return set_error(HG_EINVAL, "compression must be in (0, 1]");
   if (j.flags & ~(HG_PREC_MASK | HG_SPOTS_ON_DEVICE | HG_FULL_DIRECT))
     return set_error(HG_EINVAL, "flags: unknown bits set");
-  if ((j.flags & HG_PREC_MASK) != HG_PREC_FP32)
-    return set_error(HG_EINVAL, "flags: only HG_PREC_FP32 is available in this build");
+  const uint32_t prec = j.flags & HG_PREC_MASK;
+  if (prec != HG_PREC_FP32 && prec != HG_PREC_MIXED)
+    return set_error(HG_EINVAL, "flags: precision must be HG_PREC_FP32 or HG_PREC_MIXED");
+  if (prec == HG_PREC_MIXED && (j.flags & HG_FULL_DIRECT))
+    return set_error(HG_EINVAL, "flags: HG_FULL_DIRECT applies to HG_PREC_FP32 only");
   if (j.trace_V) return set_error(HG_EINVAL, "engine requests cannot ask for a trace");
   if (!j.phi_dev) return set_error(HG_EINVAL, "phi_dev must be non-NULL");
   return hg::make_spec(&j.grid, &j.optics, &j.spots, j.iterations, j.compression, j.seed,
@@ -233,13 +236,13 @@ hg_status hg_engine_step(hg_engine* e, void* stream, int32_t* pending_out) {
     fresh.push_back(free_slot);
   }
 
-  // step payload: [slot table][new jobs][pass descs][back descs][perm slices][spots]
+  // step payload: [slot table][new jobs][perm slices][mx table slices][iteration][final][spots]
   std::vector<hg::JobDev> table(e->max_slots, hg::JobDev{});
   for (int si = 0; si < e->max_slots; ++si)
     if (e->slots[si].used) table[si] = e->slots[si].dev;
   std::vector<hg::JobDev> newjobs;
-  std::vector<hg::JobSlice> perm;
-  int perm_blocks = 0, max_h = 0;
+  std::vector<hg::JobSlice> perm, mxtab;
+  int perm_blocks = 0, mxtab_blocks = 0, max_h = 0;
   bool perm_lds = true;
   for (int si : fresh) {
     const hg::JobDev& j = e->slots[si].dev;
@@ -248,6 +251,10 @@ hg_status hg_engine_step(hg_engine* e, void* stream, int32_t* pending_out) {
       perm_blocks += hg::perm_blocks(j.M);
       max_h = std::max(max_h, j.h);
       if (j.h > 11) perm_lds = false;
+    }
+    if (j.mixed) {
+      mxtab.push_back(hg::JobSlice{mxtab_blocks, (int32_t)newjobs.size()});
+      mxtab_blocks += hg::mx_table_blocks(j);
     }
     newjobs.push_back(j);
   }
@@ -275,6 +282,8 @@ hg_status hg_engine_step(hg_engine* e, void* stream, int32_t* pending_out) {
   o = align(o + sizeof(hg::JobDev) * newjobs.size());
   const size_t o_perm = o;
   o = align(o + sizeof(hg::JobSlice) * perm.size());
+  const size_t o_mxtab = o;
+  o = align(o + sizeof(hg::JobSlice) * mxtab.size());
   const size_t o_iter = o;
   o += iter.bytes();
   const size_t o_fin = o;
@@ -290,6 +299,7 @@ hg_status hg_engine_step(hg_engine* e, void* stream, int32_t* pending_out) {
   std::memcpy(st + o_table, table.data(), sizeof(hg::JobDev) * table.size());
   if (!newjobs.empty()) std::memcpy(st + o_new, newjobs.data(), sizeof(hg::JobDev) * newjobs.size());
   if (!perm.empty()) std::memcpy(st + o_perm, perm.data(), sizeof(hg::JobSlice) * perm.size());
+  if (!mxtab.empty()) std::memcpy(st + o_mxtab, mxtab.data(), sizeof(hg::JobSlice) * mxtab.size());
   iter.stage(st + o_iter, e->step_buf.p + o_iter);
   fin.stage(st + o_fin, e->step_buf.p + o_fin);
   HG_HIP(hipMemcpyAsync(e->step_buf.p, st, table_bytes, hipMemcpyHostToDevice, s));
@@ -312,6 +322,11 @@ hg_status hg_engine_step(hg_engine* e, void* stream, int32_t* pending_out) {
       hg::timed(s, "k_perm", [&] {
         hg::launch_perm_batch(new_dev, reinterpret_cast<const hg::JobSlice*>(e->step_buf.p + o_perm),
                               (int)perm.size(), perm_blocks, perm_lds, s);
+      });
+    if (mxtab_blocks)
+      hg::timed(s, "k_mx_tables", [&] {
+        hg::launch_mx_tables(new_dev, reinterpret_cast<const hg::JobSlice*>(e->step_buf.p + o_mxtab),
+                             (int)mxtab.size(), mxtab_blocks, s);
       });
   }
   iter.launch(slots_dev, s, false);

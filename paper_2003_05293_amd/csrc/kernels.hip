@@ -10,47 +10,13 @@
 // search over the descriptors' first-block offsets.
 #include <math.h>
 
+#include "device_common.hpp"
 #include "device_math.hpp"
 #include "kernels.hpp"
 
 namespace hg {
 
 namespace {
-
-__host__ __device__ inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
-
-// Address-space views of pointers read from the job tables.  Without them
-// the compiler sees generic pointers and issues flat loads.  Spot records
-// are read-only while a pass reads them (its weight update runs after every
-// block of the pass has finished reading), so they are read through the
-// constant address space: uniform indices then become scalar loads.
-#define HG_CONST __attribute__((address_space(4)))
-#define HG_GLOBAL __attribute__((address_space(1)))
-template <typename T>
-__device__ __forceinline__ const HG_CONST T* as_const(const T* p) {
-  return (const HG_CONST T*)p;
-}
-template <typename T>
-__device__ __forceinline__ const HG_GLOBAL T* as_global(const T* p) {
-  return (const HG_GLOBAL T*)p;
-}
-template <typename T>
-__device__ __forceinline__ HG_GLOBAL T* as_global_mut(T* p) {
-  return (HG_GLOBAL T*)p;
-}
-
-// Index of the descriptor whose block range holds `block` (descriptors are
-// sorted by block_begin, the first starts at 0).  Uniform across the block.
-template <typename D>
-__device__ __forceinline__ int find_desc(const D* __restrict__ d, int n, int block) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (d[mid].block_begin <= block) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
 
 __device__ __forceinline__ int32_t pixel_of(const PixelSet& ps, int32_t q) {
   if (ps.idx) return as_global(ps.idx)[q];
@@ -124,6 +90,9 @@ __global__ __launch_bounds__(256) void k_setup_batch(const JobDev* __restrict__ 
       r.w = 1.0f;
       r.pad = 0.0f;
       jb.sp[n] = r;
+      double sn, cn;
+      sincospi(2.0 * theta0_turns(jb.seed, (uint64_t)n), &sn, &cn);
+      jb.coef[n] = make_float2((float)(amp * cn), (float)(amp * sn));
     }
     for (int k = threadIdx.x; k < jb.counters_len; k += blockDim.x) jb.counters[k] = 0u;
   } else if (jb.compressed) {
@@ -134,7 +103,8 @@ __global__ __launch_bounds__(256) void k_setup_batch(const JobDev* __restrict__ 
   }
 }
 
-// pi(k) for every k < M of each compressed job.  With LDS, the Feistel
+// pi(k) for every k < M of each compressed job (and, for mixed-precision
+// jobs, the inverse: the rank of every pixel in the order).  With LDS, the Feistel
 // tables (h <= 11: 48 KB) are staged in LDS; otherwise read from memory.
 constexpr int kPermThreads = 512;
 constexpr int kPermLdsHalfBits = 11;
@@ -156,8 +126,11 @@ __global__ __launch_bounds__(kPermThreads) void k_perm_batch(const JobDev* __res
     __syncthreads();
     tab = tab_s;
   }
-  for (int32_t k = lb * kPermThreads + threadIdx.x; k < jb.M; k += nb * kPermThreads)
-    jb.perm[k] = (int32_t)permute((uint32_t)k, (uint32_t)jb.M, tab, jb.h);
+  for (int32_t k = lb * kPermThreads + threadIdx.x; k < jb.M; k += nb * kPermThreads) {
+    const uint32_t p = permute((uint32_t)k, (uint32_t)jb.M, tab, jb.h);
+    jb.perm[k] = (int32_t)p;
+    if (jb.rank) jb.rank[p] = (uint32_t)k;  // pixel p is the k-th of the random order
+  }
 }
 
 __global__ void k_theta0(uint64_t seed, int count, double* __restrict__ out) {
@@ -166,7 +139,8 @@ __global__ void k_theta0(uint64_t seed, int count, double* __restrict__ out) {
   out[n] = (2.0 * M_PI) * theta0_turns(seed, (uint64_t)n);
 }
 
-__global__ void k_set_state(int N, const double* __restrict__ wth, SpotRec* __restrict__ sp) {
+__global__ void k_set_state(int N, const double* __restrict__ wth, SpotRec* __restrict__ sp,
+                            float2* __restrict__ coef) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
   const double w = wth[n];
@@ -177,6 +151,10 @@ __global__ void k_set_state(int N, const double* __restrict__ wth, SpotRec* __re
   r.A = (float)(w * (double)r.a0);
   r.th = (float)t;
   sp[n] = r;
+  double sn, cn;
+  sincospi(2.0 * t, &sn, &cn);
+  const double A = w * (double)r.a0;
+  coef[n] = make_float2((float)(A * cn), (float)(A * sn));
 }
 
 __global__ void k_gather(PixelSet ps, int32_t* __restrict__ out) {
@@ -187,7 +165,11 @@ __global__ void k_gather(PixelSet ps, int32_t* __restrict__ out) {
 
 // ------------------------------------------------------------ iteration ---
 
-// One pass of one job over a pixel set, in tiles of kTile pixels:
+// One pass of one job over a pixel set, in tiles of kTile pixels.  The
+// pass's blocks take tiles dynamically: block b starts with tile b, then
+// takes tiles nb, nb + 1, ... in the order the blocks ask for them (one
+// counter per pass), so a block on a busy compute unit takes fewer tiles.
+// For each tile:
 //  phase 1  back-propagation (eq. 1) of the current state, the spot sum
 //           split over the block's waves (wave w adds spots
 //           [w N/4, (w+1) N/4) for all kTile pixels, lane = pixel, spot
@@ -196,15 +178,15 @@ __global__ void k_gather(PixelSet ps, int32_t* __restrict__ out) {
 //           or, for a forward test pass, u = e^{i Phi} of a stored hologram;
 //  phase 2  forward projection (eq. 3): lanes map to spots (groups of Lg
 //           lanes, R = 64/Lg replicas each taking every R-th pixel), waves
-//           to (spot chunk, pixel slice) units; each lane keeps its running
-//           sum across all tiles of the block;
-//  tail     the block's per-spot sums go to partial[block]; the last block
-//           of each group of blocks to finish adds its group's partials (in
-//           block order, FP64), and the last group to finish adds the group
-//           sums (in group order), divides by |Omega| and, when asked,
-//           applies the weight update of eqs. (4)-(6) in place.
-// Every sum is taken in an order fixed by the job's pass alone, so results
-// depend neither on scheduling nor on the other jobs of the batch.
+//           to (spot chunk, pixel slice) units;
+//  partial  the tile's per-spot sums go to partial[tile] (FP32);
+//  tail     the block that completes a group of tiles adds the group's
+//           partials (tile order, FP64); the block that completes the last
+//           group adds the group sums (group order), divides by |Omega|
+//           and, when asked, applies the weight update of eqs. (4)-(6).
+// A tile's sums do not depend on which block computed it, and every sum is
+// taken in an order fixed by the pass alone, so results depend neither on
+// scheduling nor on the other jobs of the batch.
 
 __device__ __forceinline__ void forward_term(float cx, float cy, float cz, const float4& a,
                                              float ui, float& vr, float& vi) {
@@ -236,52 +218,23 @@ __host__ __device__ inline LaneMap lane_map(int N) {
   return m;
 }
 
-// Cross-block hand-off of the pass sums.  The L2 caches of the XCDs are not
-// coherent with each other, and an agent-scope fence would write back and
-// invalidate the whole L2 of every block's XCD (measured: 4x slower pass).
-// Instead the partial sums are written and read with device-scope accesses
-// (coherent across XCDs, not left dirty in any L2), each writer waits until
-// its own writes have completed before the block's counter increment, and
-// the counters are device-scope read-modify-writes.  The block that sees the
-// last increment of a group therefore reads every partial of that group.
-__device__ __forceinline__ void store_dev(float2* p, float2 v) {
-  uint64_t bits;
-  __builtin_memcpy(&bits, &v, sizeof(bits));
-  __hip_atomic_store(as_global_mut(reinterpret_cast<uint64_t*>(p)), bits, __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ float2 load_dev(const float2* p) {
-  const uint64_t bits = __hip_atomic_load(as_global(reinterpret_cast<const uint64_t*>(p)),
-                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  float2 v;
-  __builtin_memcpy(&v, &bits, sizeof(v));
-  return v;
-}
-__device__ __forceinline__ void store_dev(double2* p, double2 v) {
-  HG_GLOBAL double* d = as_global_mut(reinterpret_cast<double*>(p));
-  __hip_atomic_store(d, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(d + 1, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double2 load_dev(const double2* p) {
-  const HG_GLOBAL double* d = as_global(reinterpret_cast<const double*>(p));
-  return make_double2(__hip_atomic_load(d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                      __hip_atomic_load(d + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-}
-
-// Sum over rows k = k0, k0 + step, ... < k1 of src[k * N + n], in that
-// order, in FP64.  Loads are issued kBatch at a time so that their latency
-// overlaps; out-of-range slots contribute exact zeros.
-constexpr int kBatch = 8;
-template <typename T>
-__device__ __forceinline__ double2 ordered_column_sum(const T* __restrict__ src, int N, int n,
-                                                      int k0, int k1, int step) {
+// Sum over rows k0 + s, k0 + s + S, ... < min(k1, row_end) of column n, in
+// that order, in FP64; kBatch loads are issued before any is used.  s is
+// the thread's slice; k0 and S are uniform across the block.  Rows past
+// row_end fall outside the buffer resource and load as zero.
+constexpr int kBatch = 10;
+__device__ __forceinline__ double2 column_sum(const ColumnSrc& src, int n, int s, int k0, int k1,
+                                              int S) {
   double re = 0.0, im = 0.0;
-  for (int k = k0; k < k1; k += step * kBatch) {
-    T v[kBatch];
+  const int step = S * src.N * (int)sizeof(float2);
+  int off = ((k0 + s) * src.N + n) * (int)sizeof(float2);
+  for (int k = k0; k < k1; k += S * kBatch, off += kBatch * step) {
+    float2 v[kBatch];
 #pragma unroll
     for (int b = 0; b < kBatch; ++b) {
-      const int kk = k + b * step;
-      v[b] = kk < k1 ? load_dev(src + (int64_t)kk * N + n) : T{};
+      const auto bits =
+          __builtin_amdgcn_raw_buffer_load_b64(src.rsrc, off + b * step, 0, kDeviceScope);
+      __builtin_memcpy(&v[b], &bits, sizeof(float2));
     }
 #pragma unroll
     for (int b = 0; b < kBatch; ++b) {
@@ -292,23 +245,15 @@ __device__ __forceinline__ double2 ordered_column_sum(const T* __restrict__ src,
   return make_double2(re, im);
 }
 
-// Returns true in the block that made the last of `expected` increments.
-__device__ __forceinline__ bool arrive_last(unsigned* counter, unsigned expected, int* flag) {
-  __builtin_amdgcn_s_waitcnt(0);  // this thread's device-scope writes are complete
-  __syncthreads();
-  if (threadIdx.x == 0) *flag = atomicAdd(counter, 1u) == expected - 1u;
-  __syncthreads();
-  return *flag != 0;
-}
-
 // Everything one (virtual) block of a pass needs, uniform across the block.
 struct PassCtx {
   SpotRec* sp;
+  float2* coef;
   int N, W, H;
   PixelSet ps;
   const float* phi;
-  int tiles, group_size, ngroups;
-  int lb, nb;  // this block within the pass, blocks of the pass
+  PassPlan plan;
+  int lb;  // this block within the pass
   float2* partial;
   double2* gpart;
   unsigned* counters;
@@ -318,50 +263,68 @@ struct PassCtx {
   int update, from_phi;
 };
 
-// Adds this block's partials into the group / global sums (see above).
-__device__ void pass_tail(const PassCtx& a) {
-  __shared__ int last;
-  __shared__ double mred[kBlock];
-  __shared__ double2 cred[kBlock];
-  const int N = a.N;
-  // thread = (spot lane c, slice s): Npad spot lanes, S slices
-  int Npad = 1;
-  while (Npad < N && Npad < kBlock) Npad <<= 1;
-  const int S = kBlock / Npad;
-  const int c = threadIdx.x % Npad, s = threadIdx.x / Npad;
+// Thread layout of the reductions: Npad spot lanes x S slices.
+struct RedLayout {
+  int Npad, S, c, s;
+};
+__device__ __forceinline__ RedLayout red_layout(int N) {
+  RedLayout r;
+  r.Npad = 1;
+  while (r.Npad < N && r.Npad < kBlock) r.Npad <<= 1;
+  r.S = kBlock / r.Npad;
+  r.c = threadIdx.x % r.Npad;
+  r.s = threadIdx.x / r.Npad;
+  return r;
+}
 
-  const int g = a.lb / a.group_size;
-  const int b0 = g * a.group_size;
-  const int b1 = min(b0 + a.group_size, a.nb);
-  if (!arrive_last(&a.counters[g], (unsigned)(b1 - b0), &last)) return;
-  for (int n0 = 0; n0 < N; n0 += Npad) {
-    const int n = n0 + c;
-    cred[threadIdx.x] = n < N ? ordered_column_sum(a.partial, N, n, b0 + s, b1, S)
-                              : make_double2(0.0, 0.0);
+// Group g of tiles is complete: add its tiles' partials (tile order, FP64),
+// store the group sums (FP32) and count the group.  Returns true in the
+// block that completes the last group.
+__device__ bool tail_group(const PassCtx& a, int g, double2* cred, int* flag) {
+  const int N = a.N;
+  const RedLayout L = red_layout(N);
+  const int t0 = g * a.plan.group_size;
+  const int t1 = min(t0 + a.plan.group_size, a.plan.tiles);
+  const ColumnSrc src = column_src(a.partial, t1, N);
+  float2* gsum = reinterpret_cast<float2*>(a.gpart);
+  for (int n0 = 0; n0 < N; n0 += L.Npad) {
+    const int n = n0 + L.c;
+    cred[threadIdx.x] = n < N ? column_sum(src, n, L.s, t0, t1, L.S) : make_double2(0.0, 0.0);
     __syncthreads();
-    if (s == 0 && n < N) {
-      double2 t = cred[c];
-      for (int k = 1; k < S; ++k) {
-        t.x += cred[k * Npad + c].x;
-        t.y += cred[k * Npad + c].y;
+    if (L.s == 0 && n < N) {
+      double2 t = cred[L.c];
+      for (int k = 1; k < L.S; ++k) {
+        t.x += cred[k * L.Npad + L.c].x;
+        t.y += cred[k * L.Npad + L.c].y;
       }
-      store_dev(a.gpart + (int64_t)g * N + n, t);
+      store_dev(gsum + (int64_t)g * N + n, make_float2((float)t.x, (float)t.y));
     }
     __syncthreads();
   }
-  if (!arrive_last(&a.counters[a.ngroups], (unsigned)a.ngroups, &last)) return;
-  // global sums, |V_n| and their total (thread (c, 0) owns spot n = n0 + c)
+  return arrive_last(&a.counters[a.plan.ngroups * kCounterStride], (unsigned)a.plan.ngroups, flag);
+}
+
+// Every group is complete: V_n = (group sums, group order) / |Omega|; the
+// counters are cleared for the next pass; with a.update, eqs. (4)-(6):
+// w_n <- w_n mean/|V_n|, theta_n <- arg V_n, A_n = a_n^0 w_n.
+__device__ void tail_final(const PassCtx& a, double2* cred, double* wsum) {
+  const int N = a.N;
+  const RedLayout L = red_layout(N);
+  // the spot records of the update travel with the group sums
+  SpotRec pre{};
+  if (a.update && L.s == 0 && L.c < N) pre = a.sp[L.c];
+  const ColumnSrc src = column_src(reinterpret_cast<const float2*>(a.gpart), a.plan.ngroups, N);
   double magsum = 0.0;
-  for (int n0 = 0; n0 < N; n0 += Npad) {
-    const int n = n0 + c;
-    cred[threadIdx.x] = n < N ? ordered_column_sum(a.gpart, N, n, s, a.ngroups, S)
+  for (int n0 = 0; n0 < N; n0 += L.Npad) {
+    const int n = n0 + L.c;
+    cred[threadIdx.x] = n < N ? column_sum(src, n, L.s, 0, a.plan.ngroups, L.S)
                               : make_double2(0.0, 0.0);
     __syncthreads();
-    if (s == 0 && n < N) {
-      double2 t = cred[c];
-      for (int k = 1; k < S; ++k) {
-        t.x += cred[k * Npad + c].x;
-        t.y += cred[k * Npad + c].y;
+    if (L.s == 0 && n < N) {
+      double2 t = cred[L.c];
+      for (int k = 1; k < L.S; ++k) {
+        t.x += cred[k * L.Npad + L.c].x;
+        t.y += cred[k * L.Npad + L.c].y;
       }
       t.x *= a.inv_count;
       t.y *= a.inv_count;
@@ -371,21 +334,20 @@ __device__ void pass_tail(const PassCtx& a) {
     __syncthreads();
   }
   // the counters are ready for the next pass (kernel end orders these writes)
-  for (int k = threadIdx.x; k <= a.ngroups; k += kBlock) a.counters[k] = 0u;
+  for (int k = threadIdx.x; k <= a.plan.ngroups; k += kBlock) a.counters[k * kCounterStride] = 0u;
   if (!a.update) return;
-  mred[threadIdx.x] = magsum;
+  // sum of |V_n| in a fixed order: within each wave, then the waves in order
+  for (int off = 32; off > 0; off >>= 1) magsum += __shfl_xor(magsum, off);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = magsum;
   __syncthreads();
-  for (int stride = kBlock / 2; stride > 0; stride >>= 1) {
-    if (threadIdx.x < stride) mred[threadIdx.x] += mred[threadIdx.x + stride];
-    __syncthreads();
-  }
-  const double mean = mred[0] / (double)N;
-  if (s != 0) return;
-  // eqs. (4)-(6): w_n <- w_n mean/|V_n|, theta_n <- arg V_n, A_n = a_n^0 w_n.
-  for (int n = c; n < N; n += Npad) {
+  double total = wsum[0];
+  for (int w = 1; w < kWaves; ++w) total += wsum[w];
+  const double mean = total / (double)N;
+  if (L.s != 0) return;
+  for (int n = L.c; n < N; n += L.Npad) {
     const double2 v = a.V[n];  // written above by this same thread
     const double mag = sqrt(v.x * v.x + v.y * v.y);
-    SpotRec r = a.sp[n];
+    SpotRec r = n == L.c ? pre : a.sp[n];
     const double w = (double)r.w * (mean / mag);
     if (!(mag > 0.0) || !isfinite(w)) {
       a.status[0] = 4;  // HG_ENUMERIC
@@ -393,28 +355,58 @@ __device__ void pass_tail(const PassCtx& a) {
     }
     r.w = (float)w;
     r.A = (float)(w * (double)r.a0);
-    r.th = (float)(atan2(v.y, v.x) / (2.0 * M_PI));
+    // theta is kept in FP32 turns: the FP32 arctangent of the FP64 sum
+    // (rounded to FP32) is within a few FP32 ulps of the rounded FP64 one
+    r.th = atan2f((float)v.y, (float)v.x) * 0.15915494309189535f;
     a.sp[n] = r;
+    // C_n = A_n e^{i theta_n} = A_n V_n / |V_n|
+    const double Am = w * (double)r.a0 / mag;
+    a.coef[n] = make_float2((float)(Am * v.x), (float)(Am * v.y));
   }
 }
 
+// Counts the partials of `count` tiles listed in done[] into their groups
+// (the block's own partial stores are complete first); the groups this
+// block completes are appended to owned[].
+constexpr int kDoneList = 256;  // = kBlock: one counting thread per tile
+constexpr int kMaxGroups = 128;
+__device__ void count_tiles(const PassCtx& a, const int* done, int count, int* owned,
+                            int* nowned) {
+  __builtin_amdgcn_s_waitcnt(0);  // this thread's partial stores are complete
+  __syncthreads();
+  if ((int)threadIdx.x < count) {
+    const int g = done[threadIdx.x] / a.plan.group_size;
+    const int size = min(a.plan.group_size, a.plan.tiles - g * a.plan.group_size);
+    if (atomicAdd(&a.counters[g * kCounterStride], 1u) == (unsigned)size - 1u) owned[atomicAdd(nowned, 1)] = g;
+  }
+  __syncthreads();
+}
+
 template <int MAXU>
-__device__ void pass_block(const PassCtx& a, float2 (*sw)[kTile], float4* px, float* pui,
-                           float2 (*red)[64]) {
+__device__ void pass_block(const PassCtx& a, unsigned* grab) {
+  __shared__ float2 sw[kWaves][kTile];
+  __shared__ float4 px[kTile];
+  __shared__ float pui[kTile];
+  __shared__ float2 red[kWaves * MAXU][64];
+  __shared__ int done[kDoneList];
+  __shared__ int owned[kMaxGroups];
+  __shared__ int ndone, nowned, next_tile, flag;
+  __shared__ double2 cred[kBlock];
+  __shared__ double wsum[kWaves];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int N = a.N;
   const LaneMap lm = lane_map(N);
   const int g = lane % lm.Lg, r = lane / lm.Lg;
   const SpotRec* __restrict__ sp = a.sp;
+  if (threadIdx.x == 0) ndone = nowned = 0;
 
-  float cx[MAXU], cy[MAXU], cz[MAXU], vr[MAXU], vi[MAXU];
+  float cx[MAXU], cy[MAXU], cz[MAXU];
 #pragma unroll
   for (int k = 0; k < MAXU; ++k) {
     const int u = wave + k * kWaves;
     const int n = (u / lm.S) * lm.Lg + g;
     cx[k] = cy[k] = cz[k] = 0.f;
-    vr[k] = vi[k] = 0.f;
     if (u < lm.U && n < N) {
       const HG_GLOBAL SpotRec* rec = as_global(sp + n);
       cx[k] = rec->cx;
@@ -424,115 +416,277 @@ __device__ void pass_block(const PassCtx& a, float2 (*sw)[kTile], float4* px, fl
   }
   const int n_lo = (wave * N) / kWaves, n_hi = ((wave + 1) * N) / kWaves;
 
-  for (int tile = a.lb; tile < a.tiles; tile += a.nb) {
-    const int32_t q = tile * kTile + lane;
-    const bool valid = q < a.ps.count;
-    if (a.from_phi) {
-      if (wave == 0) {
-        float4 rec = make_float4(0.f, 0.f, 0.f, 0.f);
-        float ui = 0.f;
-        if (valid) {
-          const int32_t p = pixel_of(a.ps, q);
-          const PixCoord c = pixel_coord(p, a.W, a.H);
-          float sn, cs;
-          sincos_turns(as_global(a.phi)[p] * 0.15915494309189535f, sn, cs);
-          rec = make_float4(c.Lx, c.Ly, c.Q, cs);
-          ui = sn;
-        }
-        px[lane] = rec;
-        pui[lane] = ui;
-      }
-      __syncthreads();
-    } else {
-      PixCoord c{0.f, 0.f, 0.f};
-      if (valid) c = pixel_coord(pixel_of(a.ps, q), a.W, a.H);
-      sw[wave][lane] = backprop_field(sp, n_lo, n_hi, c);
-      __syncthreads();
-      if (wave == 0) {
-        float4 rec = make_float4(0.f, 0.f, 0.f, 0.f);
-        float ui = 0.f;
-        if (valid) {
-          float2 S = sw[0][lane];
+  // with fewer blocks than tiles, blocks ask for their next tile while they
+  // work on the current one (after its back-propagation, whose memory reads
+  // would otherwise wait for the counter's answer)
+  const bool dynamic = a.plan.blocks < a.plan.tiles;
+  int tile = a.lb;
+  while (tile < a.plan.tiles) {
+    unsigned ticket = 0u;
+    float vr[MAXU], vi[MAXU];
 #pragma unroll
-          for (int w = 1; w < kWaves; ++w) {
-            S.x += sw[w][lane].x;
-            S.y += sw[w][lane].y;
+    for (int k = 0; k < MAXU; ++k) vr[k] = vi[k] = 0.f;
+    for (int st = 0; st < a.plan.sub; ++st) {
+      const int32_t q = (tile * a.plan.sub + st) * kTile + lane;
+      const bool valid = q < a.ps.count;
+      if (a.from_phi) {
+        if (wave == 0) {
+          float4 rec = make_float4(0.f, 0.f, 0.f, 0.f);
+          float ui = 0.f;
+          if (valid) {
+            const int32_t p = pixel_of(a.ps, q);
+            const PixCoord c = pixel_coord(p, a.W, a.H);
+            float sn, cs;
+            sincos_turns(as_global(a.phi)[p] * 0.15915494309189535f, sn, cs);
+            rec = make_float4(c.Lx, c.Ly, c.Q, cs);
+            ui = sn;
           }
-          const float m2 = S.x * S.x + S.y * S.y;
-          float ur = 1.f;
-          if (m2 > 0.f) {
-            const float inv = rsqrtf(m2);
-            ur = S.x * inv;
-            ui = S.y * inv;
-          }
-          rec = make_float4(c.Lx, c.Ly, c.Q, ur);
+          px[lane] = rec;
+          pui[lane] = ui;
         }
-        px[lane] = rec;
-        pui[lane] = ui;
+        __syncthreads();
+      } else {
+        const int32_t p = valid ? pixel_of(a.ps, q) : 0;
+        if (dynamic && st == a.plan.sub - 1 && threadIdx.x == 0)
+          ticket = atomicAdd(grab, p >= 0 ? 1u : 1u);
+        PixCoord c{0.f, 0.f, 0.f};
+        if (valid) c = pixel_coord(p, a.W, a.H);
+        sw[wave][lane] = backprop_field(sp, n_lo, n_hi, c);
+        __syncthreads();
+        if (wave == 0) {
+          float4 rec = make_float4(0.f, 0.f, 0.f, 0.f);
+          float ui = 0.f;
+          if (valid) {
+            float2 S = sw[0][lane];
+#pragma unroll
+            for (int w = 1; w < kWaves; ++w) {
+              S.x += sw[w][lane].x;
+              S.y += sw[w][lane].y;
+            }
+            const float m2 = S.x * S.x + S.y * S.y;
+            float ur = 1.f;
+            if (m2 > 0.f) {
+              const float inv = rsqrtf(m2);
+              ur = S.x * inv;
+              ui = S.y * inv;
+            }
+            rec = make_float4(c.Lx, c.Ly, c.Q, ur);
+          }
+          px[lane] = rec;
+          pui[lane] = ui;
+        }
+        __syncthreads();
+      }
+      if (a.from_phi && dynamic && st == a.plan.sub - 1 && threadIdx.x == 0)
+        ticket = atomicAdd(grab, 1u);
+#pragma unroll
+      for (int k = 0; k < MAXU; ++k) {
+        const int u = wave + k * kWaves;
+        if (u < lm.U) {
+          const int sl = u % lm.S;
+          const int j0 = (sl * kTile) / lm.S + r, j1 = ((sl + 1) * kTile) / lm.S;
+          for (int j = j0; j < j1; j += lm.R)
+            forward_term(cx[k], cy[k], cz[k], px[j], pui[j], vr[k], vi[k]);
+        }
       }
       __syncthreads();
     }
+    // tile partials: spot n = c*Lg + g of chunk c sums units (c, s) over
+    // slices s and replicas r, in that order.
 #pragma unroll
     for (int k = 0; k < MAXU; ++k) {
       const int u = wave + k * kWaves;
-      if (u < lm.U) {
-        const int sl = u % lm.S;
-        const int j0 = (sl * kTile) / lm.S + r, j1 = ((sl + 1) * kTile) / lm.S;
-        for (int j = j0; j < j1; j += lm.R)
-          forward_term(cx[k], cy[k], cz[k], px[j], pui[j], vr[k], vi[k]);
-      }
+      if (u < lm.U) red[u][lane] = make_float2(vr[k], vi[k]);
     }
     __syncthreads();
+    for (int idx = threadIdx.x; idx < lm.nch * lm.Lg; idx += kBlock) {
+      const int ch = idx / lm.Lg, gg = idx % lm.Lg;
+      const int n = ch * lm.Lg + gg;
+      if (n >= N) continue;
+      float2 acc = make_float2(0.f, 0.f);
+      for (int sl = 0; sl < lm.S; ++sl)
+        for (int rr = 0; rr < lm.R; ++rr) {
+          const float2 v = red[ch * lm.S + sl][rr * lm.Lg + gg];
+          acc.x += v.x;
+          acc.y += v.y;
+        }
+      store_dev(a.partial + (int64_t)tile * N + n, acc);
+    }
+    if (threadIdx.x == 0) {
+      done[ndone++] = tile;
+      next_tile = dynamic ? a.plan.blocks + (int)ticket : a.plan.tiles;
+    }
+    __syncthreads();
+    tile = next_tile;
+    if (ndone == kDoneList) {
+      count_tiles(a, done, ndone, owned, &nowned);
+      if (threadIdx.x == 0) ndone = 0;
+      __syncthreads();
+    }
   }
-  // block partials: spot n = c*Lg + g of chunk c sums units (c, s) over
-  // slices s and replicas r, in that order.
+  count_tiles(a, done, ndone, owned, &nowned);
+  for (int i = 0; i < nowned; ++i)
+    if (tail_group(a, owned[i], cred, &flag)) tail_final(a, cred, wsum);
+}
+
+}  // namespace
+
+__host__ __device__ int pass_e_width(int N) {
+  const int per_wave = (N + kWaves - 1) / kWaves;
+  return per_wave <= 8 ? 8 : per_wave <= 16 ? 16 : per_wave <= 25 ? 25 : 0;
+}
+
+namespace {
+
+// Sum of x over the 64 lanes of the wave, left in lane 63: an inclusive
+// scan within each row of 16 lanes (row shifts 1, 2, 4, 8), then the row
+// totals carried across rows (row broadcasts of lanes 15 and 31).  Fixed
+// order, so the result does not depend on scheduling.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_shift(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL,
+                                                               ROWMASK, 0xf, ROWMASK == 0xf));
+}
+__device__ __forceinline__ float wave_sum_lane63(float x) {
+  x += dpp_shift<0x111, 0xf>(x);  // row_shr:1
+  x += dpp_shift<0x112, 0xf>(x);  // row_shr:2
+  x += dpp_shift<0x114, 0xf>(x);  // row_shr:4
+  x += dpp_shift<0x118, 0xf>(x);  // row_shr:8
+  x += dpp_shift<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+  x += dpp_shift<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
+// The pass with one complex exponential per (pixel, spot) pair, for
+// N <= 4 MAXE (MAXE <= 25: the exponentials stay in registers at six waves
+// per SIMD).  Lane = pixel, wave w = spots [w N/4, (w+1) N/4):
+//  phase 1  E_n(p) = e^{i 2 pi (cx Lx + cy Ly + cz Q)} (eq. 2 without theta)
+//           kept in registers, and the wave's share of eq. (1),
+//           sum_n C_n E_n(p) with C_n = A_n e^{i theta_n};
+//  u        every wave adds the four shares in wave order and normalises
+//           (all waves obtain the same u for their lane's pixel);
+//  phase 2  the forward terms u conj(E_n(p)) of eq. (3), added over the
+//           wave's 64 pixels with a fixed lane reduction.
+// Partials, tiles, tile order and the tail are those of pass_block.
+template <int MAXE>
+__device__ void pass_block_e(const PassCtx& a, unsigned* grab) {
+  __shared__ float2 sw[kWaves][kTile];
+  __shared__ float2 rede[kWaves][MAXE];
+  __shared__ int done[kDoneList];
+  __shared__ int owned[kMaxGroups];
+  __shared__ int ndone, nowned, next_tile, flag;
+  __shared__ double2 cred[kBlock];
+  __shared__ double wsum[kWaves];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int N = a.N;
+  const int n_lo = (wave * N) / kWaves, n_hi = ((wave + 1) * N) / kWaves;
+  const int cnt = n_hi - n_lo;
+  const HG_CONST SpotRec* sp = as_const(a.sp) + n_lo;
+  const HG_CONST float2* cf = as_const(a.coef) + n_lo;
+  if (threadIdx.x == 0) ndone = nowned = 0;
+  const bool dynamic = a.plan.blocks < a.plan.tiles;
+  int tile = a.lb;
+  while (tile < a.plan.tiles) {
+    unsigned ticket = 0u;
+    for (int st = 0; st < a.plan.sub; ++st) {
+      const int32_t q = (tile * a.plan.sub + st) * kTile + lane;
+      const bool valid = q < a.ps.count;
+      const int32_t p = valid ? pixel_of(a.ps, q) : 0;
+      // the next tile is asked for once the pixel index has arrived (the
+      // counter's answer is first needed after phase 1)
+      if (dynamic && st == a.plan.sub - 1 && threadIdx.x == 0) ticket = atomicAdd(grab, p >= 0 ? 1u : 1u);
+      PixCoord c{0.f, 0.f, 0.f};
+      if (valid) c = pixel_coord(p, a.W, a.H);
+      float er[MAXE], ei[MAXE];
+      float Sr = 0.f, Si = 0.f;
 #pragma unroll
-  for (int k = 0; k < MAXU; ++k) {
-    const int u = wave + k * kWaves;
-    if (u < lm.U) red[u][lane] = make_float2(vr[k], vi[k]);
-  }
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < lm.nch * lm.Lg; idx += kBlock) {
-    const int ch = idx / lm.Lg, gg = idx % lm.Lg;
-    const int n = ch * lm.Lg + gg;
-    if (n >= N) continue;
-    float2 acc = make_float2(0.f, 0.f);
-    for (int sl = 0; sl < lm.S; ++sl)
-      for (int rr = 0; rr < lm.R; ++rr) {
-        const float2 v = red[ch * lm.S + sl][rr * lm.Lg + gg];
-        acc.x += v.x;
-        acc.y += v.y;
+      for (int k = 0; k < MAXE; ++k) {
+        er[k] = ei[k] = 0.f;
+        if (k < cnt) {
+          const float t = fmaf(sp[k].cx, c.Lx, fmaf(sp[k].cy, c.Ly, sp[k].cz * c.Q));
+          sincos_turns(t, ei[k], er[k]);
+          const float Cr = cf[k].x, Ci = cf[k].y;
+          Sr = fmaf(Cr, er[k], fmaf(-Ci, ei[k], Sr));
+          Si = fmaf(Cr, ei[k], fmaf(Ci, er[k], Si));
+        }
       }
-    store_dev(a.partial + (int64_t)a.lb * N + n, acc);
+      sw[wave][lane] = make_float2(Sr, Si);
+      __syncthreads();
+      float2 S = sw[0][lane];
+#pragma unroll
+      for (int w = 1; w < kWaves; ++w) {
+        S.x += sw[w][lane].x;
+        S.y += sw[w][lane].y;
+      }
+      float ur = 0.f, ui = 0.f;
+      if (valid) {
+        const float m2 = S.x * S.x + S.y * S.y;
+        ur = 1.f;
+        if (m2 > 0.f) {
+          const float inv = rsqrtf(m2);
+          ur = S.x * inv;
+          ui = S.y * inv;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < MAXE; ++k) {
+        if (k < cnt) {
+          // u conj(E_n)
+          const float pr = wave_sum_lane63(fmaf(ur, er[k], ui * ei[k]));
+          const float pi = wave_sum_lane63(fmaf(ui, er[k], -ur * ei[k]));
+          if (lane == 63) {
+            if (st == 0) {
+              rede[wave][k] = make_float2(pr, pi);
+            } else {
+              rede[wave][k].x += pr;
+              rede[wave][k].y += pi;
+            }
+          }
+        }
+      }
+      __syncthreads();  // sw is rewritten by the next sub-tile
+    }
+    // the tile's partials: spot n_lo + lane of each wave
+    if (lane < cnt) store_dev(a.partial + (int64_t)tile * N + n_lo + lane, rede[wave][lane]);
+    if (threadIdx.x == 0) {
+      done[ndone++] = tile;
+      next_tile = dynamic ? a.plan.blocks + (int)ticket : a.plan.tiles;
+    }
+    __syncthreads();
+    tile = next_tile;
+    if (ndone == kDoneList) {
+      count_tiles(a, done, ndone, owned, &nowned);
+      if (threadIdx.x == 0) ndone = 0;
+      __syncthreads();
+    }
   }
-  pass_tail(a);
+  count_tiles(a, done, ndone, owned, &nowned);
+  for (int i = 0; i < nowned; ++i)
+    if (tail_group(a, owned[i], cred, &flag)) tail_final(a, cred, wsum);
 }
 
 // Batched pass launch: blocks [descs[i].block_begin, descs[i+1].block_begin)
 // work on pass i.
-template <int MAXU>
-__global__ __launch_bounds__(kBlock) void k_pass_batch(const JobDev* __restrict__ jobs,
+// Occupancy target: six waves per SIMD (all blocks of a 1152^2 compressed
+// pass resident) except for the widest register forms.
+template <int MAXU, int MAXE>
+__global__ __launch_bounds__(kBlock, MAXU > 4 ? 4 : 6) void k_pass_batch(const JobDev* __restrict__ jobs,
                                                        const PassDesc* __restrict__ descs,
                                                        int ndesc) {
-  __shared__ float2 sw[kWaves][kTile];
-  __shared__ float4 px[kTile];
-  __shared__ float pui[kTile];
-  __shared__ float2 red[kWaves * MAXU][64];
   const int di = find_desc(descs, ndesc, blockIdx.x);
   const PassDesc& d = descs[di];
   const JobDev& jb = jobs[d.job];
   PassCtx a;
   a.sp = jb.sp;
+  a.coef = jb.coef;
   a.N = jb.N;
   a.W = jb.W;
   a.H = jb.H;
   a.ps = d.ps;
   a.phi = jb.phi;
-  a.tiles = d.plan.tiles;
-  a.group_size = d.plan.group_size;
-  a.ngroups = d.plan.ngroups;
+  a.plan = d.plan;
   a.lb = blockIdx.x - d.block_begin;
-  a.nb = d.plan.blocks;
   a.partial = jb.partial;
   a.gpart = jb.gpart;
   a.counters = jb.counters;
@@ -541,7 +695,15 @@ __global__ __launch_bounds__(kBlock) void k_pass_batch(const JobDev* __restrict_
   a.status = jb.status;
   a.update = d.update;
   a.from_phi = d.from_phi;
-  pass_block<MAXU>(a, sw, px, pui, red);
+  // the form depends on the job alone (its N, and whether it back-propagates),
+  // so a hologram gives the same bits alone and in any batch
+  if constexpr (MAXE > 0) {
+    if (!d.from_phi && pass_e_width(jb.N) != 0) {
+      pass_block_e<MAXE>(a, jb.grab + d.grab_slot);
+      return;
+    }
+  }
+  pass_block<MAXU>(a, jb.grab + d.grab_slot);
 }
 
 // Final hologram on a pixel set: Phi = atan2(Im S, Re S), written to out[q].
@@ -757,16 +919,14 @@ __global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ 
   }
   PassCtx a;
   a.sp = jb.sp;
+  a.coef = jb.coef;
   a.N = N;
   a.W = W;
   a.H = H;
   a.ps = PixelSet{nullptr, nullptr, 0, W * H, W * H};
   a.phi = nullptr;
-  a.tiles = d.plan.tiles;
-  a.group_size = d.plan.group_size;
-  a.ngroups = d.plan.ngroups;
+  a.plan = d.plan;
   a.lb = lb;
-  a.nb = d.plan.blocks;
   a.partial = jb.partial;
   a.gpart = jb.gpart;
   a.counters = jb.counters;
@@ -775,7 +935,15 @@ __global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ 
   a.status = jb.status;
   a.update = d.update;
   a.from_phi = 0;
-  pass_tail(a);
+  // one tile per block: count it, then the group and final sums
+  __shared__ int flag;
+  __shared__ double2 cred[kBlock];
+  __shared__ double wsum[kWaves];
+  const int g = lb / d.plan.group_size;
+  const int size = min(d.plan.group_size, d.plan.tiles - g * d.plan.group_size);
+  if (arrive_last(&jb.counters[g * kCounterStride], (unsigned)size, &flag) &&
+      tail_group(a, g, cred, &flag))
+    tail_final(a, cred, wsum);
 }
 
 // -------------------------------------------------------------- metrics ---
@@ -870,14 +1038,16 @@ __global__ void k_metric_reduce(const double2* __restrict__ partial, int nblk, i
 
 PassPlan plan_pass(int32_t count, int32_t block_cap) {
   PassPlan p;
-  p.tiles = ceil_div(count, kTile);
-  if (p.tiles < 1) p.tiles = 1;
+  int64_t units = ceil_div(count, kTile);  // kTile-pixel sub-tiles
+  if (units < 1) units = 1;
+  p.sub = ceil_div(units, kMaxTiles);
+  p.tiles = ceil_div(units, p.sub);
   p.blocks = p.tiles < block_cap ? p.tiles : block_cap;
   if (p.blocks < 1) p.blocks = 1;
   int gs = 1;
-  while (gs * gs < p.blocks) ++gs;
+  while (gs * gs < p.tiles) ++gs;
   p.group_size = gs;
-  p.ngroups = ceil_div(p.blocks, gs);
+  p.ngroups = ceil_div(p.tiles, gs);
   return p;
 }
 
@@ -911,8 +1081,8 @@ void launch_theta0(uint64_t seed, int count, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_theta0, dim3(ceil_div(count, 256)), dim3(256), 0, s, seed, count, out);
 }
 
-void launch_set_state(int N, const double* wth, SpotRec* sp, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_state, dim3(ceil_div(N, 256)), dim3(256), 0, s, N, wth, sp);
+void launch_set_state(int N, const double* wth, SpotRec* sp, float2* coef, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_state, dim3(ceil_div(N, 256)), dim3(256), 0, s, N, wth, sp, coef);
 }
 
 void launch_gather(const PixelSet& ps, int32_t* out, hipStream_t s) {
@@ -925,13 +1095,24 @@ int pass_units_per_wave(int N) {
   return ceil_div(lm.U, kWaves);
 }
 
-void launch_pass_batch(const JobDev* jobs, const PassDesc* descs, int ndesc, int total_blocks,
-                       int max_units, hipStream_t s) {
-  if (ndesc <= 0 || total_blocks <= 0) return;
+template <int MAXU>
+void launch_pass_u(const JobDev* jobs, const PassDesc* descs, int ndesc, int total_blocks,
+                   int e_width, hipStream_t s) {
   const dim3 grid(total_blocks), block(kBlock);
-  if (max_units <= 1) hipLaunchKernelGGL(k_pass_batch<1>, grid, block, 0, s, jobs, descs, ndesc);
-  else if (max_units <= 4) hipLaunchKernelGGL(k_pass_batch<4>, grid, block, 0, s, jobs, descs, ndesc);
-  else hipLaunchKernelGGL(k_pass_batch<16>, grid, block, 0, s, jobs, descs, ndesc);
+  switch (e_width) {
+    case 8: hipLaunchKernelGGL((k_pass_batch<MAXU, 8>), grid, block, 0, s, jobs, descs, ndesc); break;
+    case 16: hipLaunchKernelGGL((k_pass_batch<MAXU, 16>), grid, block, 0, s, jobs, descs, ndesc); break;
+    case 25: hipLaunchKernelGGL((k_pass_batch<MAXU, 25>), grid, block, 0, s, jobs, descs, ndesc); break;
+    default: hipLaunchKernelGGL((k_pass_batch<MAXU, 0>), grid, block, 0, s, jobs, descs, ndesc);
+  }
+}
+
+void launch_pass_batch(const JobDev* jobs, const PassDesc* descs, int ndesc, int total_blocks,
+                       int max_units, int e_width, hipStream_t s) {
+  if (ndesc <= 0 || total_blocks <= 0) return;
+  if (max_units <= 1) launch_pass_u<1>(jobs, descs, ndesc, total_blocks, e_width, s);
+  else if (max_units <= 4) launch_pass_u<4>(jobs, descs, ndesc, total_blocks, e_width, s);
+  else launch_pass_u<16>(jobs, descs, ndesc, total_blocks, e_width, s);
 }
 
 int backprop_blocks(int32_t count) { return ceil_div(count, kBlock); }
@@ -947,6 +1128,7 @@ void launch_sep_tables(const JobDev* jobs, const JobSlice* slices, int nslices, 
 PassPlan plan_sep(int W, int H) {
   PassPlan p;
   p.tiles = ceil_div(W, kSepTile) * ceil_div(H, kSepTile);
+  p.sub = 1;
   p.blocks = p.tiles;
   int gs = 1;
   while (gs * gs < p.blocks) ++gs;

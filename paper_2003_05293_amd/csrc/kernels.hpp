@@ -34,18 +34,24 @@ struct SpotPtrs {
 };
 
 constexpr int kBlock = 256;          // threads per block of the pixel kernels
+// Counters of the cross-block hand-off sit one 128-byte line apart, so that
+// the arrivals of different groups do not contend for one line.
+constexpr int kCounterStride = 32;
 constexpr int kWaves = kBlock / 64;  // wave64s per block
 constexpr int kTile = 64;            // pixels per tile of a pass
 constexpr int kFeistelRoundsHost = 6;  // rounds of the pixel permutation
 
 // Launch geometry of one pass over `count` pixels.
 struct PassPlan {
-  int32_t tiles;       // ceil(count / kTile)
-  int32_t blocks;      // blocks of this pass; block b handles tiles b, b + blocks, ...
-  int32_t group_size;  // blocks per first-level reduction group
+  int32_t tiles;       // tiles of `sub` x kTile pixels; one partial-sum row per tile
+  int32_t sub;         // kTile-pixel sub-tiles per tile (tiles <= kMaxTiles)
+  int32_t blocks;      // blocks of this pass (they take the tiles dynamically)
+  int32_t group_size;  // tiles per first-level reduction group
   int32_t ngroups;
 };
-// One tile per block up to `block_cap` blocks, groups of ceil(sqrt(blocks)).
+constexpr int32_t kMaxTiles = 8192;
+// Tiles of one kTile sub-tile while there are at most kMaxTiles of them;
+// min(tiles, block_cap) blocks; groups of ceil(sqrt(tiles)) tiles.
 PassPlan plan_pass(int32_t count, int32_t block_cap);
 constexpr int32_t kDefaultBlockCap = 4096;
 
@@ -60,13 +66,15 @@ struct JobDev {
   double pitch_mm, lambda_mm, focal_mm;
   SpotPtrs in;         // spot inputs (device)
   SpotRec* sp;         // [N] iteration state
+  float2* coef;        // [N] C_n = A_n e^{i 2 pi th_n}, kept with the state
   uint32_t* tab;       // [6 << h] Feistel tables (compressed only)
   int32_t* perm;       // [M] random pixel order (compressed only)
   float* phi;          // [H][W] output hologram (or input of a forward test pass)
-  float2* partial;     // [max pass blocks][N]
+  float2* partial;     // [max pass tiles][N]
   double2* gpart;      // [max pass groups][N]
-  unsigned* counters;  // [max pass groups + 1]
-  int32_t counters_len;
+  unsigned* counters;  // [max pass groups + 1] group and pass counters, kCounterStride apart
+  unsigned* grab;      // [iterations + 2] tile counters of the passes (PassDesc::grab_slot)
+  int32_t counters_len;  // counters and grab, zeroed by the setup
   int32_t trace;       // V is [iterations][N] instead of [N]
   double2* V;
   int32_t* status;     // sticky status word of the caller's stream
@@ -74,6 +82,18 @@ struct JobDev {
   float2* sepF;        // [N][W]  e^{i 2 pi fx_n(i)}
   float2* sepB;        // [H][N]  A_n e^{i 2 pi (fy_n(j) + th_n)}
   float2* sepG;        // [H][N]  e^{i 2 pi fy_n(j)}
+  // mixed-precision passes (see MxDesc): FP16 / FP32 factor tables in the
+  // lane order of the matrix-core operands, and the rank of every pixel in
+  // the random order (compressed jobs)
+  int32_t mixed;
+  int32_t mx_steps;    // Np / 16 with Np = N rounded up to 16
+  int32_t mx_cblocks;  // Wp / 16 with Wp = W rounded up to kMxTile
+  int32_t mx_rblocks;  // Hp / 16
+  uint4* mxFc;         // [Wp/16][Np/16][64] x 4 half2   (back-propagation operand)
+  uint4* mxFn;         // [Np/16][Wp/16][64] x 4 half2   (forward operand)
+  float4* mxGa;        // [Hp/16][Np/16][64] x 4 float2  (rows by lane)
+  float4* mxGv;        // [Hp/16][Np/16][64] x 4 float2  (spots by lane)
+  uint32_t* rank;      // [M] position of each pixel in the random order
 };
 
 // Pixel set of a pass: all pixels 0..count-1 (perm == idx == nullptr),
@@ -94,6 +114,7 @@ struct PassDesc {
   PassPlan plan;
   int32_t update;       // apply eqs. (4)-(6) after the sums
   int32_t from_phi;     // forward of job.phi instead of back-propagation
+  int32_t grab_slot;    // tile counter of this pass: job.grab[grab_slot]
   double inv_count;
   double2* V;           // spot fields of this pass, [N]
 };
@@ -122,14 +143,20 @@ int perm_blocks(int32_t M);
 void launch_perm_batch(const JobDev* jobs, const JobSlice* slices, int nslices, int total_blocks,
                        bool lds, hipStream_t s);
 void launch_theta0(uint64_t seed, int count, double* out, hipStream_t s);
-void launch_set_state(int N, const double* wth, SpotRec* sp, hipStream_t s);
+void launch_set_state(int N, const double* wth, SpotRec* sp, float2* coef, hipStream_t s);
 void launch_gather(const PixelSet& ps, int32_t* out, hipStream_t s);
 
 // ---- iteration ----
 // Units of phase-2 work per wave for N spots (selects the kernel variant).
 int pass_units_per_wave(int N);
+// Register width of the shared-exponential form for N spots (0: N too large
+// for it; the two-phase form is used).
+__host__ __device__ int pass_e_width(int N);
+// Passes of jobs with pass_e_width(N) > 0 (and not from a stored Phi) use
+// the shared-exponential form; e_width is the largest width they need,
+// max_units the largest two-phase unit count of the others.
 void launch_pass_batch(const JobDev* jobs, const PassDesc* descs, int ndesc, int total_blocks,
-                       int max_units, hipStream_t s);
+                       int max_units, int e_width, hipStream_t s);
 void launch_backprop_batch(const JobDev* jobs, const BackDesc* descs, int ndesc,
                            int total_blocks, hipStream_t s);
 int backprop_blocks(int32_t count);
@@ -161,6 +188,40 @@ PassPlan plan_sep(int W, int H);
 // with final != 0, the full-grid hologram Phi = arg(B F).
 void launch_sep_pass(const JobDev* jobs, const SepDesc* descs, int ndesc, int total_blocks,
                      bool final, hipStream_t s);
+
+// ---- mixed-precision passes (FP16 matrix cores, FP32 sums) ----
+// A pass is the separable recast above on the matrix cores: per output tile
+// of kMxTile x kMxTile pixels (wave w: rows 16w..16w+15), S = B F with FP16
+// operands and FP32 accumulation (K = 2 Np: real and imaginary parts
+// interleaved), u = S / |S| where the pixel is in the pass's pixel set
+// (else 0), T = u conj(F)^T the same way, and the tile's partial
+// V_n = sum_j conj(G_n(j)) T[j][n].  A compressed pass is the same product
+// over all pixels with u = 0 outside the window: pixel p is in window
+// [start, start + count) of the random order when (rank[p] - start) mod M
+// < count.  Partials are added across tiles with compensated FP32 sums.
+constexpr int kMxTile = 64;
+enum MxMode : int32_t { kMxIterate = 0, kMxFinal = 1, kMxFromPhi = 2 };
+struct MxDesc {
+  int32_t block_begin;
+  int32_t job;
+  int32_t tiles_x, tiles_y;
+  PassPlan plan;
+  int64_t start;        // window of the random order (count < M), else unused
+  int32_t count;        // pixels in the set (M: all pixels)
+  int32_t update;       // weight update after the sums
+  float inv_count;
+  double2* V;           // [N] spot fields of the pass (FP32 values widened)
+  float* out;           // final hologram (kMxFinal)
+};
+PassPlan plan_mx(int W, int H);
+// FP16 / FP32 tables from FP64 phases (spot inputs only: they do not change
+// during the iterations).
+int mx_table_blocks(const JobDev& j);
+void launch_mx_tables(const JobDev* jobs, const JobSlice* slices, int nslices, int total_blocks,
+                      hipStream_t s);
+// mode: MxMode; max_steps: largest Np / 16 among the descriptors.
+void launch_mx_pass(const JobDev* jobs, const MxDesc* descs, int ndesc, int total_blocks,
+                    int mode, int max_steps, hipStream_t s);
 
 // ---- metrics (FP64) ----
 struct SetupArgs {

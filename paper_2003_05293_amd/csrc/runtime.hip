@@ -244,17 +244,38 @@ JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev
   j.phi = s.phi;
   j.trace = s.trace_host ? 1 : 0;
   j.status = status_dev;
-  L.separable = tp.separable_full && !s.full_direct;
+  j.mixed = s.precision == HG_PREC_MIXED ? 1 : 0;
+  L.separable = !j.mixed && tp.separable_full && !s.full_direct;
   L.plan_all = plan_pass(j.M, tp.full_block_cap);
   L.plan_sub = j.compressed ? plan_pass(j.m, tp.subset_block_cap) : L.plan_all;
   L.plan_sep = plan_sep(j.W, j.H);
-  int max_blocks = std::max(L.plan_all.blocks, L.plan_sub.blocks);
-  int max_groups = std::max(L.plan_all.ngroups, L.plan_sub.ngroups);
+  L.plan_mx = plan_mx(j.W, j.H);
+  // partial-sum rows: one per tile of the largest pass the job can run
+  int max_rows = 0, max_groups = 0;
+  if (j.mixed) {
+    max_rows = L.plan_mx.tiles;
+    max_groups = L.plan_mx.ngroups;
+    j.mx_steps = (s.N + 15) / 16;
+    j.mx_cblocks = (s.W + kMxTile - 1) / kMxTile * (kMxTile / 16);
+    j.mx_rblocks = (s.H + kMxTile - 1) / kMxTile * (kMxTile / 16);
+  } else {
+    // direct full-grid passes: without the separable form, and for the
+    // single-pass entry points
+    if (!L.separable || s.hook) {
+      max_rows = L.plan_all.tiles;
+      max_groups = L.plan_all.ngroups;
+    }
+    if (j.compressed) {
+      max_rows = std::max(max_rows, L.plan_sub.tiles);
+      max_groups = std::max(max_groups, L.plan_sub.ngroups);
+    }
+  }
   if (L.separable) {
-    max_blocks = std::max(max_blocks, L.plan_sep.blocks);
+    max_rows = std::max(max_rows, L.plan_sep.tiles);
     max_groups = std::max(max_groups, L.plan_sep.ngroups);
   }
-  j.counters_len = max_groups + 1;
+  L.grab_offset = (max_groups + 1) * kCounterStride;
+  j.counters_len = L.grab_offset + (s.iterations + 2);
   size_t bytes = 0;
   auto take = [&](size_t n) {
     bytes = align_up(bytes, 256);
@@ -265,9 +286,18 @@ JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev
   L.raw_inline = raw_inline && !s.spots_on_device;
   L.off_raw = L.raw_inline ? take(sizeof(double) * 4 * (size_t)s.N) : 0;
   L.off_sp = take(sizeof(SpotRec) * (size_t)s.N);
+  L.off_coef = take(sizeof(float2) * (size_t)s.N);
   L.off_tab = j.compressed ? take(sizeof(uint32_t) * ((size_t)kFeistelRoundsHost << j.h)) : 0;
   L.off_perm = j.compressed ? take(sizeof(int32_t) * (size_t)j.M) : 0;
-  L.off_partial = take(sizeof(float2) * (size_t)max_blocks * s.N);
+  if (j.mixed) {
+    const size_t ops = (size_t)j.mx_steps * 64;  // operand groups per 16-row/column block
+    L.off_mxFc = take(16 * ops * j.mx_cblocks);
+    L.off_mxFn = take(16 * ops * j.mx_cblocks);
+    L.off_mxGa = take(32 * ops * j.mx_rblocks);
+    L.off_mxGv = take(32 * ops * j.mx_rblocks);
+    L.off_rank = j.compressed ? take(sizeof(uint32_t) * (size_t)j.M) : 0;
+  }
+  L.off_partial = take(sizeof(float2) * (size_t)max_rows * s.N);
   L.off_gpart = take(sizeof(double2) * (size_t)max_groups * s.N);
   L.off_counters = take(sizeof(unsigned) * (size_t)j.counters_len);
   L.off_V = take(sizeof(double2) * (size_t)s.N *
@@ -290,15 +320,24 @@ JobDev bind_job(const JobLayout& L, const JobSpec& s, char* base, const double* 
     j.in = SpotPtrs{r, r + s.N, r + 2 * s.N, r + 3 * s.N};
   }
   j.sp = reinterpret_cast<SpotRec*>(base + L.off_sp);
+  j.coef = reinterpret_cast<float2*>(base + L.off_coef);
   j.tab = j.compressed ? reinterpret_cast<uint32_t*>(base + L.off_tab) : nullptr;
   j.perm = j.compressed ? reinterpret_cast<int32_t*>(base + L.off_perm) : nullptr;
   j.partial = reinterpret_cast<float2*>(base + L.off_partial);
   j.gpart = reinterpret_cast<double2*>(base + L.off_gpart);
   j.counters = reinterpret_cast<unsigned*>(base + L.off_counters);
+  j.grab = j.counters + L.grab_offset;
   j.V = reinterpret_cast<double2*>(base + L.off_V);
   j.sepF = L.separable ? reinterpret_cast<float2*>(base + L.off_sepF) : nullptr;
   j.sepB = L.separable ? reinterpret_cast<float2*>(base + L.off_sepB) : nullptr;
   j.sepG = L.separable ? reinterpret_cast<float2*>(base + L.off_sepG) : nullptr;
+  if (j.mixed) {
+    j.mxFc = reinterpret_cast<uint4*>(base + L.off_mxFc);
+    j.mxFn = reinterpret_cast<uint4*>(base + L.off_mxFn);
+    j.mxGa = reinterpret_cast<float4*>(base + L.off_mxGa);
+    j.mxGv = reinterpret_cast<float4*>(base + L.off_mxGv);
+    j.rank = j.compressed ? reinterpret_cast<uint32_t*>(base + L.off_rank) : nullptr;
+  }
   return j;
 }
 
@@ -316,6 +355,7 @@ PassDesc iteration_desc(const JobDev& j, const JobLayout& L, int it, int index, 
   d.plan = sub ? L.plan_sub : L.plan_all;
   d.update = 1;
   d.from_phi = 0;
+  d.grab_slot = it;
   d.inv_count = 1.0 / (double)d.ps.count;
   d.V = j.V + (j.trace ? (size_t)(it - 1) * j.N : 0);
   return d;
@@ -339,8 +379,48 @@ SepDesc sep_desc(const JobDev& j, const JobLayout& L, int index, int block_begin
 }
 }  // namespace
 
+namespace {
+MxDesc mx_desc(const JobDev& j, const JobLayout& L, int index, int block_begin) {
+  MxDesc d;
+  d.block_begin = block_begin;
+  d.job = index;
+  d.tiles_x = (j.W + kMxTile - 1) / kMxTile;
+  d.tiles_y = (j.H + kMxTile - 1) / kMxTile;
+  d.plan = L.plan_mx;
+  d.start = 0;
+  d.count = j.M;
+  d.update = 0;
+  d.inv_count = 1.0f / (float)j.M;
+  d.V = j.V;
+  d.out = nullptr;
+  return d;
+}
+}  // namespace
+
+void LaunchSet::add_forward_mx(const JobDev& j, const JobLayout& L, int index) {
+  mx.push_back(mx_desc(j, L, index, mx_blocks));
+  mx_blocks += L.plan_mx.blocks;
+  mx_steps = std::max(mx_steps, j.mx_steps);
+  mx_mode = kMxFromPhi;
+}
+
 void LaunchSet::add_iteration(const JobDev& j, const JobLayout& L, int it, int index) {
   const bool sub = j.compressed && it < j.iterations;
+  if (j.mixed) {
+    MxDesc d = mx_desc(j, L, index, mx_blocks);
+    if (sub) {
+      d.start = (int64_t)(it - 1) * j.m % j.M;
+      d.count = j.m;
+      d.inv_count = 1.0f / (float)j.m;
+    }
+    (sub ? mx_sub : mx_full) += 1;
+    d.update = 1;
+    d.V = j.V + (j.trace ? (size_t)(it - 1) * j.N : 0);
+    mx.push_back(d);
+    mx_blocks += d.plan.blocks;
+    mx_steps = std::max(mx_steps, j.mx_steps);
+    return;
+  }
   if (!sub && L.separable) {
     tabs.push_back(JobSlice{tab_blocks, index});
     tab_blocks += sep_table_blocks(j.W, j.H, j.N);
@@ -354,10 +434,21 @@ void LaunchSet::add_iteration(const JobDev& j, const JobLayout& L, int it, int i
   const PassDesc d = iteration_desc(j, L, it, index, pass_blocks);
   pass.push_back(d);
   pass_blocks += d.plan.blocks;
-  units = std::max(units, pass_units_per_wave(j.N));
+  const int ew = pass_e_width(j.N);
+  if (ew > 0) e_width = std::max(e_width, ew);
+  else units = std::max(units, pass_units_per_wave(j.N));
 }
 
 void LaunchSet::add_final(const JobDev& j, const JobLayout& L, int index) {
+  if (j.mixed) {
+    MxDesc d = mx_desc(j, L, index, mx_blocks);
+    d.out = j.phi;
+    mx.push_back(d);
+    mx_blocks += d.plan.blocks;
+    mx_steps = std::max(mx_steps, j.mx_steps);
+    mx_mode = kMxFinal;
+    return;
+  }
   if (L.separable) {
     tabs.push_back(JobSlice{tab_blocks, index});
     tab_blocks += sep_table_blocks(j.W, j.H, j.N);
@@ -379,7 +470,8 @@ void LaunchSet::add_final(const JobDev& j, const JobLayout& L, int index) {
 
 size_t LaunchSet::bytes() const {
   return align_up(sizeof(PassDesc) * pass.size(), 256) + align_up(sizeof(SepDesc) * sep.size(), 256) +
-         align_up(sizeof(JobSlice) * tabs.size(), 256) + align_up(sizeof(BackDesc) * back.size(), 256);
+         align_up(sizeof(JobSlice) * tabs.size(), 256) + align_up(sizeof(BackDesc) * back.size(), 256) +
+         align_up(sizeof(MxDesc) * mx.size(), 256);
 }
 
 size_t LaunchSet::stage(char* host, char* dev) {
@@ -394,6 +486,7 @@ size_t LaunchSet::stage(char* host, char* dev) {
   d_sep = reinterpret_cast<const SepDesc*>(put(sep.data(), sizeof(SepDesc) * sep.size()));
   d_tabs = reinterpret_cast<const JobSlice*>(put(tabs.data(), sizeof(JobSlice) * tabs.size()));
   d_back = reinterpret_cast<const BackDesc*>(put(back.data(), sizeof(BackDesc) * back.size()));
+  d_mx = reinterpret_cast<const MxDesc*>(put(mx.data(), sizeof(MxDesc) * mx.size()));
   return o;
 }
 
@@ -411,11 +504,20 @@ void LaunchSet::launch(const JobDev* jobs, hipStream_t s, bool capture) const {
     bool any_full = false, any_sub = false;
     for (const PassDesc& d : pass) (d.ps.count == d.ps.M && !d.ps.perm ? any_full : any_sub) = true;
     run(any_full && any_sub ? "k_pass_mixed" : any_sub ? "k_pass_subset" : "k_pass_full",
-        [&] { launch_pass_batch(jobs, d_pass, (int)pass.size(), pass_blocks, units, s); });
+        [&] { launch_pass_batch(jobs, d_pass, (int)pass.size(), pass_blocks, units, e_width, s); });
   }
   if (!back.empty())
     run("k_backprop_phi",
         [&] { launch_backprop_batch(jobs, d_back, (int)back.size(), back_blocks, s); });
+  if (!mx.empty()) {
+    const char* name = "k_mx_forward";
+    if (mx_mode == kMxFinal) {
+      name = "k_mx_final";
+    } else if (mx_mode == kMxIterate) {
+      name = mx_full && mx_sub ? "k_mx_mixed" : mx_sub ? "k_mx_subset" : "k_mx_full";
+    }
+    run(name, [&] { launch_mx_pass(jobs, d_mx, (int)mx.size(), mx_blocks, mx_mode, mx_steps, s); });
+  }
 }
 
 // ------------------------------------------------------------------- batch --
@@ -461,6 +563,8 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
   final_ = LaunchSet{};
   perm_.clear();
   perm_blocks_ = 0;
+  mxtab_.clear();
+  mxtab_blocks_ = 0;
   for (int i = 0; i < count; ++i) {
     const JobDev& j = jobs_[i];
     if (j.phi) final_.add_final(j, layouts_[i], i);
@@ -468,11 +572,17 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
       perm_.push_back(JobSlice{perm_blocks_, i});
       perm_blocks_ += perm_blocks(j.M);
     }
+    if (j.mixed) {
+      mxtab_.push_back(JobSlice{mxtab_blocks_, i});
+      mxtab_blocks_ += mx_table_blocks(j);
+    }
   }
-  // descriptor tables: [JobDev][JobSlice perm][rounds...][final]
+  // descriptor tables: [JobDev][JobSlice perm][JobSlice mx tables][rounds...][final]
   size_t tb = align_up(sizeof(JobDev) * count, 256);
   const size_t t_perm = tb;
   tb = align_up(tb + sizeof(JobSlice) * perm_.size(), 256);
+  const size_t t_mxtab = tb;
+  tb = align_up(tb + sizeof(JobSlice) * mxtab_.size(), 256);
   const size_t t_sets = tb;
   for (const LaunchSet& ls : rounds_) tb += ls.bytes();
   tb += final_.bytes();
@@ -484,6 +594,9 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
   perm_dev_ = reinterpret_cast<JobSlice*>(table_.p + t_perm);
   std::memcpy(staging_.p, jobs_.data(), sizeof(JobDev) * count);
   if (!perm_.empty()) std::memcpy(staging_.p + t_perm, perm_.data(), sizeof(JobSlice) * perm_.size());
+  mxtab_dev_ = reinterpret_cast<JobSlice*>(table_.p + t_mxtab);
+  if (!mxtab_.empty())
+    std::memcpy(staging_.p + t_mxtab, mxtab_.data(), sizeof(JobSlice) * mxtab_.size());
   size_t o = t_sets;
   for (LaunchSet& ls : rounds_) o += ls.stage(staging_.p + o, table_.p + o);
   o += final_.stage(staging_.p + o, table_.p + o);
@@ -513,6 +626,10 @@ hg_status Batch::enqueue_prologue(hipStream_t s, bool capture) {
   if (perm_blocks_ > 0)
     run("k_perm", [&] {
       launch_perm_batch(jobs_dev_, perm_dev_, (int)perm_.size(), perm_blocks_, perm_lds_, s);
+    });
+  if (mxtab_blocks_ > 0)
+    run("k_mx_tables", [&] {
+      launch_mx_tables(jobs_dev_, mxtab_dev_, (int)mxtab_.size(), mxtab_blocks_, s);
     });
   return HG_OK;
 }
@@ -565,6 +682,7 @@ void Batch::release() {
   custom_.release();
   jobs_dev_ = nullptr;
   perm_dev_ = nullptr;
+  mxtab_dev_ = nullptr;
 }
 
 }  // namespace hg

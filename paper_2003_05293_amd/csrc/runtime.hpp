@@ -74,6 +74,7 @@ struct JobSpec {
   uint64_t seed = 0;
   uint32_t precision = HG_PREC_FP32;
   bool full_direct = false;   // full-grid passes with the per-pixel kernels
+  bool hook = false;          // single-pass entry point (any pixel set up to W*H)
   float* phi = nullptr;       // output hologram (device)
   double* trace_host = nullptr;
 };
@@ -95,12 +96,14 @@ hg_status make_spec(const hg_grid* g, const hg_optics* o, const hg_spots* s, int
 // Device scratch of one job, laid out relative to the job's base address.
 struct JobLayout {
   JobDev dev;  // every field but the pointers
-  PassPlan plan_all, plan_sub, plan_sep;
+  PassPlan plan_all, plan_sub, plan_sep, plan_mx;
   bool separable = false;
-  size_t off_raw = 0, off_sp = 0, off_tab = 0, off_perm = 0, off_partial = 0, off_gpart = 0,
-         off_counters = 0, off_V = 0, off_sepF = 0, off_sepB = 0, off_sepG = 0;
+  size_t off_raw = 0, off_sp = 0, off_coef = 0, off_tab = 0, off_perm = 0, off_partial = 0, off_gpart = 0,
+         off_counters = 0, off_V = 0, off_sepF = 0, off_sepB = 0, off_sepG = 0, off_mxFc = 0,
+         off_mxFn = 0, off_mxGa = 0, off_mxGv = 0, off_rank = 0;
   size_t bytes = 0;
   bool raw_inline = false;  // the job's own scratch holds a copy of its spot arrays
+  int grab_offset = 0;      // the pass tile counters follow the group counters
 };
 // raw_inline: reserve room for the 4N input doubles of host-resident spots.
 JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev,
@@ -114,10 +117,12 @@ PixelSet all_pixels(int32_t M);
 
 // The launches of one iteration round (or of the final phase) of a set of
 // jobs: compressed passes (k_pass_batch), separable full-grid passes (tables
-// then k_sep_pass) and direct full-grid final phases (k_backprop_batch).
+// then k_sep_pass), direct full-grid final phases (k_backprop_batch) and the
+// passes of mixed-precision jobs (k_mx_pass).
 struct LaunchSet {
   std::vector<PassDesc> pass;
   int pass_blocks = 0, units = 1;
+  int e_width = 0;  // widest shared-exponential form among the passes (0: none)
   std::vector<SepDesc> sep;
   int sep_blocks = 0;
   bool sep_final = false;
@@ -125,15 +130,22 @@ struct LaunchSet {
   int tab_blocks = 0;
   std::vector<BackDesc> back;
   int back_blocks = 0;
+  std::vector<MxDesc> mx;
+  int mx_blocks = 0, mx_steps = 0, mx_sub = 0, mx_full = 0;
+  int mx_mode = kMxIterate;
   // device copies, set by stage()
   const PassDesc* d_pass = nullptr;
   const SepDesc* d_sep = nullptr;
   const JobSlice* d_tabs = nullptr;
   const BackDesc* d_back = nullptr;
+  const MxDesc* d_mx = nullptr;
 
   void add_iteration(const JobDev& j, const JobLayout& L, int it, int index);
   void add_final(const JobDev& j, const JobLayout& L, int index);
-  bool empty() const { return pass.empty() && sep.empty() && back.empty(); }
+  // Forward projection of the job's stored hologram (mixed precision, all
+  // pixels, no update).
+  void add_forward_mx(const JobDev& j, const JobLayout& L, int index);
+  bool empty() const { return pass.empty() && sep.empty() && back.empty() && mx.empty(); }
   size_t bytes() const;
   // Copies the descriptors into host staging at `host` and points the
   // device copies at `dev` (same offsets); returns the bytes used.
@@ -196,6 +208,9 @@ class Batch {
   LaunchSet final_;                      // final phases
   std::vector<JobSlice> perm_;
   int perm_blocks_ = 0;
+  std::vector<JobSlice> mxtab_;          // factor tables of the mixed-precision jobs
+  int mxtab_blocks_ = 0;
+  JobSlice* mxtab_dev_ = nullptr;
   bool perm_lds_ = true;
   int max_h_ = 0;
   size_t host_spot_bytes_ = 0;

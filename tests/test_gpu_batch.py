@@ -162,3 +162,41 @@ def test_mixed_batch_against_stored_oracle():
                                                 j.compression, j.seed))
         eg, ug, _ = hg.metrics(j.grid, OPTICS, j.spots, d.phi)
         assert abs(eg - eo) <= 1e-3 and abs(ug - uo) <= 1e-3
+
+
+def test_launch_geometry_does_not_change_results():
+    """Partial sums are kept per tile of pixels whichever block computes the
+    tile, so the block caps (the autotuner's parameters) leave every result
+    bit-identical, also when blocks take several tiles each."""
+    import torch
+    g = Grid(1152, 1152)
+    s = spot_cloud(3, 100, g)
+    say("geometry invariance 1152 N=100")
+    ref = hg.cswgs(g, OPTICS, s, 10, 1 / 16, 3).clone()
+    for cap in (1, 64, 300, 1024, 4096):
+        out = hg.cswgs(g, OPTICS, s, 10, 1 / 16, 3,
+                       tune={"subset_block_cap": cap, "full_block_cap": cap})
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), cap
+    g2 = Grid(300, 170)
+    s2 = spot_cloud(4, 37, g2)
+    ref2 = hg.cswgs(g2, OPTICS, s2, 6, 0.25, 4, direct=True).clone()
+    for cap in (7, 100, 4096):
+        out = hg.cswgs(g2, OPTICS, s2, 6, 0.25, 4, direct=True,
+                       tune={"subset_block_cap": cap, "full_block_cap": cap})
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref2), cap
+
+
+def test_autotuner_picks_a_measured_candidate(tmp_path):
+    from paper_2003_05293_amd import autotune
+    g = Grid(512, 512)
+    s = spot_cloud(5, 60, g)
+    say("autotune 512 N=60")
+    table = autotune.Table(str(tmp_path / "tune.json"))
+    t = table.single(g, OPTICS, s, 8, 1 / 16, reps=2, subset_caps=(64, 256, 1024))
+    entry = table.entries[autotune.single_key(g, 60, 8, 1 / 16, "fp32")]
+    assert t["subset_block_cap"] in (64, 256, 1024)
+    assert entry["ms"] == min(entry["sweep_ms"].values())
+    again = autotune.Table(str(tmp_path / "tune.json"))
+    assert again.single(g, OPTICS, s, 8, 1 / 16) == t  # cached, not re-timed
