@@ -230,7 +230,24 @@ def main():
     ap.add_argument("--batch", type=int, default=32, help="holograms per batched launch")
     ap.add_argument("--serve-seconds", type=float, default=30.0,
                     help="length of the served Poisson stream (0: skip)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="default launch parameters instead of the autotuned ones")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device three times (counter calibration) "
+                         "and exit")
     args = ap.parse_args()
+    if args.calibrate_copy > 0:
+        import torch
+        n = args.calibrate_copy << 18  # float32 elements
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_read_per_copy": 4 * n,
+                          "calibrate_copy_bytes_written_per_copy": 4 * n, "copies": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the hologram "
               "path has no multi-GPU form in this build", file=sys.stderr)
@@ -250,9 +267,13 @@ def main():
 
     # launch geometry of the compressed passes, chosen by the autotuner
     from paper_2003_05293_amd import autotune
-    tuned = autotune.tune_single(grid, OPTICS, clouds[0], ITER, COMP, precision="fp32", reps=5)
+    if args.no_autotune:
+        tuned = {"full_block_cap": 0, "subset_block_cap": 0, "pass_form": 0, "ms": None,
+                 "sweep_ms": {}}
+    else:
+        tuned = autotune.tune_single(grid, OPTICS, clouds[0], ITER, COMP, precision="fp32", reps=5)
     tune = autotune.Table.as_tune(tuned)
-    print(f"[bench] autotuned {tune} ({tuned['ms']:.4f} ms)", file=sys.stderr, flush=True)
+    print(f"[bench] launch parameters {tune} ({tuned['ms']} ms)", file=sys.stderr, flush=True)
 
     def step(k):
         s = k % CLOUDS

@@ -110,15 +110,20 @@ typedef struct hg_spots {
 #define HG_FULL_DIRECT 0x200u
 
 /* Extended parameters of hg_cswgs_ex. */
-/* Launch geometry of the passes, 0 meaning the default: a pass runs on
- * min(tiles, cap) blocks that take its tiles of pixels dynamically
- * (full-grid and compressed passes have separate caps).  Partial sums are
- * kept per tile, whichever block computes it, so the geometry never changes
- * the results, only the speed.  Chosen per shape by the package's
- * autotuner. */
+/* Launch parameters of the passes, 0 meaning the default.
+ * Block caps: a pass runs on min(tiles, cap) blocks that take its tiles of
+ * pixels dynamically (full-grid and compressed passes have separate caps).
+ * Partial sums are kept per tile, whichever block computes it, so the caps
+ * never change the results, only the speed.
+ * pass_form (FP32 per-pixel passes): 0 = two sincos per (pixel, spot) pair,
+ * one per propagation direction; 1 = one complex exponential per pair, kept
+ * in registers between the directions (jobs with N <= 100; others use 0).
+ * The form changes the rounding of the sums (both stay within the same
+ * accuracy bars).  Chosen per shape by the package's autotuner. */
 typedef struct hg_tune {
   int32_t full_block_cap;
   int32_t subset_block_cap;
+  int32_t pass_form;
 } hg_tune;
 
 typedef struct hg_params {

@@ -1,9 +1,11 @@
-"""Autotuner of the pass launch geometry (hg_tune).
+"""Autotuner of the pass launch parameters (hg_tune).
 
 A pass runs on min(tiles, cap) blocks that take its tiles of pixels
 dynamically; the caps of the compressed and of the full-grid per-pixel
-passes are the tunable launch parameters.  Partial sums are kept per tile,
-so the geometry never changes the results, only the speed.
+passes, and the form of the compressed pass (two sincos per pixel-spot
+pair, or one shared complex exponential), are the tunable parameters.
+Partial sums are kept per tile, so the caps never change the results; the
+form changes the rounding only.
 
 For a workload -- one hologram shape, or a whole batch of jobs -- the tuner
 times every candidate on the GPU (HIP events on the launch stream, after a
@@ -23,6 +25,7 @@ from typing import Dict, Iterable, List, Optional
 
 SUBSET_CAPS = (256, 512, 768, 1024, 1536, 2048, 4096)
 FULL_CAPS = (1024, 2048, 4096)
+PASS_FORMS = (0, 1)
 
 
 def _hg():
@@ -56,9 +59,10 @@ def _time(run, reps: int, stream) -> float:
     return a.elapsed_time(b) / reps
 
 
-def _candidates(subset_caps: Iterable[int], full_caps: Iterable[int]) -> List[Dict[str, int]]:
-    return [{"full_block_cap": int(f), "subset_block_cap": int(s)}
-            for f in full_caps for s in subset_caps]
+def _candidates(subset_caps: Iterable[int], full_caps: Iterable[int],
+                forms: Iterable[int] = PASS_FORMS) -> List[Dict[str, int]]:
+    return [{"full_block_cap": int(f), "subset_block_cap": int(s), "pass_form": int(p)}
+            for p in forms for f in full_caps for s in subset_caps]
 
 
 def _best(sweep: Dict[str, float], cands: List[Dict[str, int]]) -> dict:
@@ -70,12 +74,12 @@ def _best(sweep: Dict[str, float], cands: List[Dict[str, int]]) -> dict:
 
 
 def _label(c: Dict[str, int]) -> str:
-    return f"full={c['full_block_cap']},subset={c['subset_block_cap']}"
+    return f"full={c['full_block_cap']},subset={c['subset_block_cap']},form={c['pass_form']}"
 
 
 def tune_single(grid, optics, spots, iterations: int, compression: float, seed: int = 0,
                 precision: str = "fp32", reps: int = 5, subset_caps=SUBSET_CAPS,
-                full_caps=(0,), stream=None) -> dict:
+                full_caps=(0,), forms=PASS_FORMS, stream=None) -> dict:
     """Fastest geometry for one hologram at a time of this shape."""
     import numpy as np
     import torch
@@ -85,7 +89,7 @@ def tune_single(grid, optics, spots, iterations: int, compression: float, seed: 
                                  np.asarray(spots.z_mm), np.asarray(spots.amp)]),
                        dtype=torch.float64, device="cuda")
     phi = torch.empty(grid.W * grid.H, dtype=torch.float32, device="cuda")
-    cands = _candidates(subset_caps, full_caps)
+    cands = _candidates(subset_caps, full_caps, forms)
     sweep = {}
     for c in cands:
         sweep[_label(c)] = _time(lambda: hg.cswgs_device(
@@ -94,13 +98,13 @@ def tune_single(grid, optics, spots, iterations: int, compression: float, seed: 
     return _best(sweep, cands)
 
 
-def tune_batch(jobs, reps: int = 3, subset_caps=SUBSET_CAPS, full_caps=(0,), stream=None,
-               use_graph: bool = True) -> dict:
+def tune_batch(jobs, reps: int = 3, subset_caps=SUBSET_CAPS, full_caps=(0,), forms=PASS_FORMS,
+               stream=None, use_graph: bool = True) -> dict:
     """Fastest geometry for a batch of DeviceJob run together."""
     import torch
     hg = _hg()
     stream = stream or torch.cuda.current_stream()
-    cands = _candidates(subset_caps, full_caps)
+    cands = _candidates(subset_caps, full_caps, forms)
     sweep = {}
     for c in cands:
         batch = hg.Batch(jobs, tune=c, use_graph=use_graph)
@@ -132,7 +136,8 @@ class Table:
     @staticmethod
     def as_tune(entry: dict) -> Dict[str, int]:
         return {"full_block_cap": int(entry["full_block_cap"]),
-                "subset_block_cap": int(entry["subset_block_cap"])}
+                "subset_block_cap": int(entry["subset_block_cap"]),
+                "pass_form": int(entry.get("pass_form", 0))}
 
     def single(self, grid, optics, spots, iterations: int, compression: float,
                precision: str = "fp32", **kw) -> Dict[str, int]:

@@ -19,7 +19,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhg.so")
-SOURCES = ["kernels.hip", "kernels_mx.hip", "runtime.hip", "api.hip", "engine.hip"]
+SOURCES = ["kernels.hip", "kernels_mx.hip", "kernels_sep.hip", "runtime.hip", "api.hip", "engine.hip"]
 ARCH = "gfx950"
 
 HIP_FLAGS = [

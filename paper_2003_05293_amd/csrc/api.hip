@@ -109,6 +109,7 @@ hg::TuneParams tune_params(const hg_tune* t) {
   hg::TuneParams tp;
   if (t && t->full_block_cap > 0) tp.full_block_cap = t->full_block_cap;
   if (t && t->subset_block_cap > 0) tp.subset_block_cap = t->subset_block_cap;
+  if (t) tp.pass_form = t->pass_form;
   return tp;
 }
 
@@ -197,7 +198,7 @@ hg_status single_pass(Workspace* ws, const hg::PixelSet& ps, bool from_phi, doub
   HG_TRY(ws->batch.upload_custom(&d, sizeof(d), ws->stream, &dev));
   hg::launch_pass_batch(ws->batch.jobs_device(), reinterpret_cast<const hg::PassDesc*>(dev), 1,
                         d.plan.blocks, hg::pass_units_per_wave(j.N),
-                        from_phi ? 0 : hg::pass_e_width(j.N), ws->stream);
+                        from_phi || !j.shared_e ? 0 : hg::pass_e_width(j.N), ws->stream);
   HG_TRY(check_launch());
   HG_HIP(hipMemcpyAsync(V_out, j.V, sizeof(double2) * j.N, hipMemcpyDeviceToHost, ws->stream));
   HG_HIP(hipStreamSynchronize(ws->stream));
@@ -220,8 +221,9 @@ hg_status single_set(Workspace* ws, hg::LaunchSet& set) {
 hg_status job_specs(int32_t count, const hg_job* jobs, const hg_tune* tune,
                     std::vector<hg::JobSpec>* out) {
   if (count < 1 || !jobs) return set_error(HG_EINVAL, "count must be >= 1 and jobs non-NULL");
-  if (tune && (tune->full_block_cap < 0 || tune->subset_block_cap < 0))
-    return set_error(HG_EINVAL, "tune caps must be >= 0");
+  if (tune && (tune->full_block_cap < 0 || tune->subset_block_cap < 0 || tune->pass_form < 0 ||
+               tune->pass_form > 1))
+    return set_error(HG_EINVAL, "tune caps must be >= 0 and pass_form 0 or 1");
   out->resize(count);
   for (int32_t i = 0; i < count; ++i) {
     const hg_job& j = jobs[i];
@@ -278,8 +280,9 @@ hg_status hg_cswgs_ex(const hg_grid* grid, const hg_optics* optics, const hg_spo
   if (!params) return set_error(HG_EINVAL, "params must be non-NULL");
   HG_TRY(check_compression(params->compression));
   HG_TRY(validate_flags(params->flags, HG_SPOTS_ON_DEVICE | HG_FULL_DIRECT));
-  if (params->tune.full_block_cap < 0 || params->tune.subset_block_cap < 0)
-    return set_error(HG_EINVAL, "tune caps must be >= 0");
+  if (params->tune.full_block_cap < 0 || params->tune.subset_block_cap < 0 ||
+      params->tune.pass_form < 0 || params->tune.pass_form > 1)
+    return set_error(HG_EINVAL, "tune caps must be >= 0 and pass_form 0 or 1");
   return run_one(grid, optics, spots, params->iterations, params->compression, params->seed,
                  params->flags, phi_dev, params->trace_V, stream, tune_params(&params->tune));
 }

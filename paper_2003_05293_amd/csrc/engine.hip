@@ -155,14 +155,16 @@ hg_status hg_engine_create(const hg_engine_config* cfg, hg_engine** out) {
     return set_error(HG_EINVAL, "max_slots must be in [1, 4096]");
   if (cfg->mem_budget_bytes < (size_t)(1 << 20))
     return set_error(HG_EINVAL, "mem_budget_bytes must be at least 1 MiB");
-  if (cfg->tune.full_block_cap < 0 || cfg->tune.subset_block_cap < 0)
-    return set_error(HG_EINVAL, "tune caps must be >= 0");
+  if (cfg->tune.full_block_cap < 0 || cfg->tune.subset_block_cap < 0 ||
+      cfg->tune.pass_form < 0 || cfg->tune.pass_form > 1)
+    return set_error(HG_EINVAL, "tune caps must be >= 0 and pass_form 0 or 1");
   auto e = std::make_unique<hg_engine>();
   HG_HIP(hipGetDevice(&e->device));
   e->budget = cfg->mem_budget_bytes;
   e->max_slots = cfg->max_slots;
   if (cfg->tune.full_block_cap > 0) e->tp.full_block_cap = cfg->tune.full_block_cap;
   if (cfg->tune.subset_block_cap > 0) e->tp.subset_block_cap = cfg->tune.subset_block_cap;
+  e->tp.pass_form = cfg->tune.pass_form;
   HG_TRY(e->pool.reserve(e->budget));
   e->alloc.reset(e->budget);
   HG_TRY(e->status.reserve(1));
@@ -236,13 +238,14 @@ hg_status hg_engine_step(hg_engine* e, void* stream, int32_t* pending_out) {
     fresh.push_back(free_slot);
   }
 
-  // step payload: [slot table][new jobs][perm slices][mx table slices][iteration][final][spots]
+  // step payload: [slot table][new jobs][perm slices][mx table slices][sep table slices]
+  // [iteration][final][spots]
   std::vector<hg::JobDev> table(e->max_slots, hg::JobDev{});
   for (int si = 0; si < e->max_slots; ++si)
     if (e->slots[si].used) table[si] = e->slots[si].dev;
   std::vector<hg::JobDev> newjobs;
-  std::vector<hg::JobSlice> perm, mxtab;
-  int perm_blocks = 0, mxtab_blocks = 0, max_h = 0;
+  std::vector<hg::JobSlice> perm, mxtab, septab;
+  int perm_blocks = 0, mxtab_blocks = 0, septab_blocks = 0, max_h = 0;
   bool perm_lds = true;
   for (int si : fresh) {
     const hg::JobDev& j = e->slots[si].dev;
@@ -255,6 +258,10 @@ hg_status hg_engine_step(hg_engine* e, void* stream, int32_t* pending_out) {
     if (j.mixed) {
       mxtab.push_back(hg::JobSlice{mxtab_blocks, (int32_t)newjobs.size()});
       mxtab_blocks += hg::mx_table_blocks(j);
+    }
+    if (e->slots[si].layout.separable) {
+      septab.push_back(hg::JobSlice{septab_blocks, (int32_t)newjobs.size()});
+      septab_blocks += hg::sep_table_blocks(j);
     }
     newjobs.push_back(j);
   }
@@ -284,6 +291,8 @@ hg_status hg_engine_step(hg_engine* e, void* stream, int32_t* pending_out) {
   o = align(o + sizeof(hg::JobSlice) * perm.size());
   const size_t o_mxtab = o;
   o = align(o + sizeof(hg::JobSlice) * mxtab.size());
+  const size_t o_septab = o;
+  o = align(o + sizeof(hg::JobSlice) * septab.size());
   const size_t o_iter = o;
   o += iter.bytes();
   const size_t o_fin = o;
@@ -300,6 +309,8 @@ hg_status hg_engine_step(hg_engine* e, void* stream, int32_t* pending_out) {
   if (!newjobs.empty()) std::memcpy(st + o_new, newjobs.data(), sizeof(hg::JobDev) * newjobs.size());
   if (!perm.empty()) std::memcpy(st + o_perm, perm.data(), sizeof(hg::JobSlice) * perm.size());
   if (!mxtab.empty()) std::memcpy(st + o_mxtab, mxtab.data(), sizeof(hg::JobSlice) * mxtab.size());
+  if (!septab.empty())
+    std::memcpy(st + o_septab, septab.data(), sizeof(hg::JobSlice) * septab.size());
   iter.stage(st + o_iter, e->step_buf.p + o_iter);
   fin.stage(st + o_fin, e->step_buf.p + o_fin);
   HG_HIP(hipMemcpyAsync(e->step_buf.p, st, table_bytes, hipMemcpyHostToDevice, s));
@@ -327,6 +338,12 @@ hg_status hg_engine_step(hg_engine* e, void* stream, int32_t* pending_out) {
       hg::timed(s, "k_mx_tables", [&] {
         hg::launch_mx_tables(new_dev, reinterpret_cast<const hg::JobSlice*>(e->step_buf.p + o_mxtab),
                              (int)mxtab.size(), mxtab_blocks, s);
+      });
+    if (septab_blocks)
+      hg::timed(s, "k_sep_tables", [&] {
+        hg::launch_sep_tables(new_dev,
+                              reinterpret_cast<const hg::JobSlice*>(e->step_buf.p + o_septab),
+                              (int)septab.size(), septab_blocks, s);
       });
   }
   iter.launch(slots_dev, s, false);

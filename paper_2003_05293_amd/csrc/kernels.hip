@@ -13,6 +13,7 @@
 #include "device_common.hpp"
 #include "device_math.hpp"
 #include "kernels.hpp"
+#include "pass_tail.hpp"
 
 namespace hg {
 
@@ -95,6 +96,12 @@ __global__ __launch_bounds__(256) void k_setup_batch(const JobDev* __restrict__ 
       jb.coef[n] = make_float2((float)(amp * cn), (float)(amp * sn));
     }
     for (int k = threadIdx.x; k < jb.counters_len; k += blockDim.x) jb.counters[k] = 0u;
+  }
+  // the exact sums start at zero (every block of the job takes a share)
+  for (int64_t k = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; k < jb.acc_len;
+       k += (int64_t)gridDim.y * blockDim.x)
+    jb.acc[k] = 0ull;
+  if (blockIdx.y == 0) {
   } else if (jb.compressed) {
     const int total = kFeistelRounds << jb.h;
     const int stride = (gridDim.y - 1) * blockDim.x;
@@ -126,10 +133,34 @@ __global__ __launch_bounds__(kPermThreads) void k_perm_batch(const JobDev* __res
     __syncthreads();
     tab = tab_s;
   }
-  for (int32_t k = lb * kPermThreads + threadIdx.x; k < jb.M; k += nb * kPermThreads) {
-    const uint32_t p = permute((uint32_t)k, (uint32_t)jb.M, tab, jb.h);
-    jb.perm[k] = (int32_t)p;
-    if (jb.rank) jb.rank[p] = (uint32_t)k;  // pixel p is the k-th of the random order
+  // The kPermPerThread walks of a thread advance in lock step, so that their
+  // table reads overlap instead of forming one long dependent chain.
+  const uint32_t M = (uint32_t)jb.M;
+  const int64_t k0 = (int64_t)lb * kPermThreads + threadIdx.x, dk = (int64_t)nb * kPermThreads;
+  uint32_t y[kPermPerThread];
+#pragma unroll
+  for (int i = 0; i < kPermPerThread; ++i) {
+    const int64_t k = k0 + i * dk;
+    y[i] = k < M ? feistel((uint32_t)k, tab, jb.h) : 0u;  // 0: nothing to walk
+  }
+  const uint32_t cap = 1u << (2 * jb.h < 32 ? 2 * jb.h : 31);
+  for (uint32_t step = 0; step < cap; ++step) {
+    bool more = false;
+#pragma unroll
+    for (int i = 0; i < kPermPerThread; ++i) more |= y[i] >= M;
+    if (!more) break;
+#pragma unroll
+    for (int i = 0; i < kPermPerThread; ++i) {
+      const uint32_t z = feistel(y[i], tab, jb.h);
+      y[i] = y[i] >= M ? z : y[i];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kPermPerThread; ++i) {
+    const int64_t k = k0 + i * dk;
+    if (k >= M) continue;
+    jb.perm[k] = (int32_t)y[i];
+    if (jb.rank) jb.rank[y[i]] = (uint32_t)k;  // pixel y is the k-th of the random order
   }
 }
 
@@ -218,170 +249,6 @@ __host__ __device__ inline LaneMap lane_map(int N) {
   return m;
 }
 
-// Sum over rows k0 + s, k0 + s + S, ... < min(k1, row_end) of column n, in
-// that order, in FP64; kBatch loads are issued before any is used.  s is
-// the thread's slice; k0 and S are uniform across the block.  Rows past
-// row_end fall outside the buffer resource and load as zero.
-constexpr int kBatch = 10;
-__device__ __forceinline__ double2 column_sum(const ColumnSrc& src, int n, int s, int k0, int k1,
-                                              int S) {
-  double re = 0.0, im = 0.0;
-  const int step = S * src.N * (int)sizeof(float2);
-  int off = ((k0 + s) * src.N + n) * (int)sizeof(float2);
-  for (int k = k0; k < k1; k += S * kBatch, off += kBatch * step) {
-    float2 v[kBatch];
-#pragma unroll
-    for (int b = 0; b < kBatch; ++b) {
-      const auto bits =
-          __builtin_amdgcn_raw_buffer_load_b64(src.rsrc, off + b * step, 0, kDeviceScope);
-      __builtin_memcpy(&v[b], &bits, sizeof(float2));
-    }
-#pragma unroll
-    for (int b = 0; b < kBatch; ++b) {
-      re += (double)v[b].x;
-      im += (double)v[b].y;
-    }
-  }
-  return make_double2(re, im);
-}
-
-// Everything one (virtual) block of a pass needs, uniform across the block.
-struct PassCtx {
-  SpotRec* sp;
-  float2* coef;
-  int N, W, H;
-  PixelSet ps;
-  const float* phi;
-  PassPlan plan;
-  int lb;  // this block within the pass
-  float2* partial;
-  double2* gpart;
-  unsigned* counters;
-  double inv_count;
-  double2* V;
-  int32_t* status;
-  int update, from_phi;
-};
-
-// Thread layout of the reductions: Npad spot lanes x S slices.
-struct RedLayout {
-  int Npad, S, c, s;
-};
-__device__ __forceinline__ RedLayout red_layout(int N) {
-  RedLayout r;
-  r.Npad = 1;
-  while (r.Npad < N && r.Npad < kBlock) r.Npad <<= 1;
-  r.S = kBlock / r.Npad;
-  r.c = threadIdx.x % r.Npad;
-  r.s = threadIdx.x / r.Npad;
-  return r;
-}
-
-// Group g of tiles is complete: add its tiles' partials (tile order, FP64),
-// store the group sums (FP32) and count the group.  Returns true in the
-// block that completes the last group.
-__device__ bool tail_group(const PassCtx& a, int g, double2* cred, int* flag) {
-  const int N = a.N;
-  const RedLayout L = red_layout(N);
-  const int t0 = g * a.plan.group_size;
-  const int t1 = min(t0 + a.plan.group_size, a.plan.tiles);
-  const ColumnSrc src = column_src(a.partial, t1, N);
-  float2* gsum = reinterpret_cast<float2*>(a.gpart);
-  for (int n0 = 0; n0 < N; n0 += L.Npad) {
-    const int n = n0 + L.c;
-    cred[threadIdx.x] = n < N ? column_sum(src, n, L.s, t0, t1, L.S) : make_double2(0.0, 0.0);
-    __syncthreads();
-    if (L.s == 0 && n < N) {
-      double2 t = cred[L.c];
-      for (int k = 1; k < L.S; ++k) {
-        t.x += cred[k * L.Npad + L.c].x;
-        t.y += cred[k * L.Npad + L.c].y;
-      }
-      store_dev(gsum + (int64_t)g * N + n, make_float2((float)t.x, (float)t.y));
-    }
-    __syncthreads();
-  }
-  return arrive_last(&a.counters[a.plan.ngroups * kCounterStride], (unsigned)a.plan.ngroups, flag);
-}
-
-// Every group is complete: V_n = (group sums, group order) / |Omega|; the
-// counters are cleared for the next pass; with a.update, eqs. (4)-(6):
-// w_n <- w_n mean/|V_n|, theta_n <- arg V_n, A_n = a_n^0 w_n.
-__device__ void tail_final(const PassCtx& a, double2* cred, double* wsum) {
-  const int N = a.N;
-  const RedLayout L = red_layout(N);
-  // the spot records of the update travel with the group sums
-  SpotRec pre{};
-  if (a.update && L.s == 0 && L.c < N) pre = a.sp[L.c];
-  const ColumnSrc src = column_src(reinterpret_cast<const float2*>(a.gpart), a.plan.ngroups, N);
-  double magsum = 0.0;
-  for (int n0 = 0; n0 < N; n0 += L.Npad) {
-    const int n = n0 + L.c;
-    cred[threadIdx.x] = n < N ? column_sum(src, n, L.s, 0, a.plan.ngroups, L.S)
-                              : make_double2(0.0, 0.0);
-    __syncthreads();
-    if (L.s == 0 && n < N) {
-      double2 t = cred[L.c];
-      for (int k = 1; k < L.S; ++k) {
-        t.x += cred[k * L.Npad + L.c].x;
-        t.y += cred[k * L.Npad + L.c].y;
-      }
-      t.x *= a.inv_count;
-      t.y *= a.inv_count;
-      a.V[n] = t;
-      magsum += sqrt(t.x * t.x + t.y * t.y);
-    }
-    __syncthreads();
-  }
-  // the counters are ready for the next pass (kernel end orders these writes)
-  for (int k = threadIdx.x; k <= a.plan.ngroups; k += kBlock) a.counters[k * kCounterStride] = 0u;
-  if (!a.update) return;
-  // sum of |V_n| in a fixed order: within each wave, then the waves in order
-  for (int off = 32; off > 0; off >>= 1) magsum += __shfl_xor(magsum, off);
-  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = magsum;
-  __syncthreads();
-  double total = wsum[0];
-  for (int w = 1; w < kWaves; ++w) total += wsum[w];
-  const double mean = total / (double)N;
-  if (L.s != 0) return;
-  for (int n = L.c; n < N; n += L.Npad) {
-    const double2 v = a.V[n];  // written above by this same thread
-    const double mag = sqrt(v.x * v.x + v.y * v.y);
-    SpotRec r = n == L.c ? pre : a.sp[n];
-    const double w = (double)r.w * (mean / mag);
-    if (!(mag > 0.0) || !isfinite(w)) {
-      a.status[0] = 4;  // HG_ENUMERIC
-      continue;
-    }
-    r.w = (float)w;
-    r.A = (float)(w * (double)r.a0);
-    // theta is kept in FP32 turns: the FP32 arctangent of the FP64 sum
-    // (rounded to FP32) is within a few FP32 ulps of the rounded FP64 one
-    r.th = atan2f((float)v.y, (float)v.x) * 0.15915494309189535f;
-    a.sp[n] = r;
-    // C_n = A_n e^{i theta_n} = A_n V_n / |V_n|
-    const double Am = w * (double)r.a0 / mag;
-    a.coef[n] = make_float2((float)(Am * v.x), (float)(Am * v.y));
-  }
-}
-
-// Counts the partials of `count` tiles listed in done[] into their groups
-// (the block's own partial stores are complete first); the groups this
-// block completes are appended to owned[].
-constexpr int kDoneList = 256;  // = kBlock: one counting thread per tile
-constexpr int kMaxGroups = 128;
-__device__ void count_tiles(const PassCtx& a, const int* done, int count, int* owned,
-                            int* nowned) {
-  __builtin_amdgcn_s_waitcnt(0);  // this thread's partial stores are complete
-  __syncthreads();
-  if ((int)threadIdx.x < count) {
-    const int g = done[threadIdx.x] / a.plan.group_size;
-    const int size = min(a.plan.group_size, a.plan.tiles - g * a.plan.group_size);
-    if (atomicAdd(&a.counters[g * kCounterStride], 1u) == (unsigned)size - 1u) owned[atomicAdd(nowned, 1)] = g;
-  }
-  __syncthreads();
-}
-
 template <int MAXU>
 __device__ void pass_block(const PassCtx& a, unsigned* grab) {
   __shared__ float2 sw[kWaves][kTile];
@@ -391,7 +258,6 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab) {
   __shared__ int done[kDoneList];
   __shared__ int owned[kMaxGroups];
   __shared__ int ndone, nowned, next_tile, flag;
-  __shared__ double2 cred[kBlock];
   __shared__ double wsum[kWaves];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -510,7 +376,7 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab) {
           acc.x += v.x;
           acc.y += v.y;
         }
-      store_dev(a.partial + (int64_t)tile * N + n, acc);
+      acc_add(a.acc, N, a.plan.shift, 1 + tile / a.plan.group_size, n, acc);
     }
     if (threadIdx.x == 0) {
       done[ndone++] = tile;
@@ -526,7 +392,7 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab) {
   }
   count_tiles(a, done, ndone, owned, &nowned);
   for (int i = 0; i < nowned; ++i)
-    if (tail_group(a, owned[i], cred, &flag)) tail_final(a, cred, wsum);
+    if (tail_group(a, owned[i], &flag)) tail_final(a, wsum);
 }
 
 }  // namespace
@@ -575,7 +441,6 @@ __device__ void pass_block_e(const PassCtx& a, unsigned* grab) {
   __shared__ int done[kDoneList];
   __shared__ int owned[kMaxGroups];
   __shared__ int ndone, nowned, next_tile, flag;
-  __shared__ double2 cred[kBlock];
   __shared__ double wsum[kWaves];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -648,7 +513,8 @@ __device__ void pass_block_e(const PassCtx& a, unsigned* grab) {
       __syncthreads();  // sw is rewritten by the next sub-tile
     }
     // the tile's partials: spot n_lo + lane of each wave
-    if (lane < cnt) store_dev(a.partial + (int64_t)tile * N + n_lo + lane, rede[wave][lane]);
+    if (lane < cnt)
+      acc_add(a.acc, N, a.plan.shift, 1 + tile / a.plan.group_size, n_lo + lane, rede[wave][lane]);
     if (threadIdx.x == 0) {
       done[ndone++] = tile;
       next_tile = dynamic ? a.plan.blocks + (int)ticket : a.plan.tiles;
@@ -663,15 +529,16 @@ __device__ void pass_block_e(const PassCtx& a, unsigned* grab) {
   }
   count_tiles(a, done, ndone, owned, &nowned);
   for (int i = 0; i < nowned; ++i)
-    if (tail_group(a, owned[i], cred, &flag)) tail_final(a, cred, wsum);
+    if (tail_group(a, owned[i], &flag)) tail_final(a, wsum);
 }
 
 // Batched pass launch: blocks [descs[i].block_begin, descs[i+1].block_begin)
 // work on pass i.
-// Occupancy target: six waves per SIMD (all blocks of a 1152^2 compressed
-// pass resident) except for the widest register forms.
+// Occupancy target (waves per SIMD): eight for the two-sincos form (all
+// blocks of a 1152^2 compressed pass resident with room to spare), six when
+// 25 exponentials per lane stay in registers, two for the widest spot maps.
 template <int MAXU, int MAXE>
-__global__ __launch_bounds__(kBlock, MAXU > 4 ? 4 : 6) void k_pass_batch(const JobDev* __restrict__ jobs,
+__global__ __launch_bounds__(kBlock, MAXU > 4 ? 2 : (MAXE > 16 ? 6 : 8)) void k_pass_batch(const JobDev* __restrict__ jobs,
                                                        const PassDesc* __restrict__ descs,
                                                        int ndesc) {
   const int di = find_desc(descs, ndesc, blockIdx.x);
@@ -689,6 +556,7 @@ __global__ __launch_bounds__(kBlock, MAXU > 4 ? 4 : 6) void k_pass_batch(const J
   a.lb = blockIdx.x - d.block_begin;
   a.partial = jb.partial;
   a.gpart = jb.gpart;
+  a.acc = jb.acc;
   a.counters = jb.counters;
   a.inv_count = d.inv_count;
   a.V = d.V;
@@ -698,7 +566,7 @@ __global__ __launch_bounds__(kBlock, MAXU > 4 ? 4 : 6) void k_pass_batch(const J
   // the form depends on the job alone (its N, and whether it back-propagates),
   // so a hologram gives the same bits alone and in any batch
   if constexpr (MAXE > 0) {
-    if (!d.from_phi && pass_e_width(jb.N) != 0) {
+    if (jb.shared_e && !d.from_phi) {
       pass_block_e<MAXE>(a, jb.grab + d.grab_slot);
       return;
     }
@@ -718,232 +586,6 @@ __global__ __launch_bounds__(kBlock) void k_backprop_batch(const JobDev* __restr
   const PixCoord c = pixel_coord(pixel_of(d.ps, q), jb.W, jb.H);
   const float2 S = backprop_field(jb.sp, 0, jb.N, c);
   as_global_mut(d.out)[q] = atan2f(S.y, S.x);
-}
-
-// ------------------------------------------------- separable full passes ---
-
-// Separable factors of eq. (2) for the full-grid passes, from FP64 phases:
-//   F[n][i] = e^{i 2 pi fx_n(i)},  G[j][n] = e^{i 2 pi fy_n(j)},
-//   B[j][n] = A_n e^{i 2 pi (fy_n(j) + th_n)}   (current state A, th).
-__global__ __launch_bounds__(256) void k_sep_tables(const JobDev* __restrict__ jobs,
-                                                    const JobSlice* __restrict__ slices,
-                                                    int nslices) {
-  const int si = find_desc(slices, nslices, blockIdx.x);
-  const JobDev& jb = jobs[slices[si].job];
-  const int lb = blockIdx.x - slices[si].block_begin;
-  const int W = jb.W, H = jb.H, N = jb.N;
-  const int nb = ceil_div((int64_t)N * (W + H), 256);
-  const int64_t nF = (int64_t)N * W, total = nF + (int64_t)H * N;
-  const double lf = jb.lambda_mm * jb.focal_mm;
-  const double lf2 = lf * jb.focal_mm;
-  const double kxy = jb.pitch_mm / (2.0 * lf), kz = jb.pitch_mm * jb.pitch_mm / (4.0 * lf2);
-  for (int64_t k = (int64_t)lb * 256 + threadIdx.x; k < total; k += (int64_t)nb * 256) {
-    if (k < nF) {
-      const int n = (int)(k / W), i = (int)(k % W);
-      const double L = (double)(2 * i - (W - 1));
-      double t = jb.in.x[n] * kxy * L + jb.in.z[n] * kz * L * L;
-      t -= rint(t);
-      double s, c;
-      sincospi(2.0 * t, &s, &c);
-      jb.sepF[k] = make_float2((float)c, (float)s);
-    } else {
-      const int64_t kk = k - nF;
-      const int j = (int)(kk / N), n = (int)(kk % N);
-      const double L = (double)(2 * j - (H - 1));
-      double t = jb.in.y[n] * kxy * L + jb.in.z[n] * kz * L * L;
-      t -= rint(t);
-      double s, c;
-      sincospi(2.0 * t, &s, &c);
-      jb.sepG[kk] = make_float2((float)c, (float)s);
-      double tb = t + (double)jb.sp[n].th;
-      tb -= rint(tb);
-      sincospi(2.0 * tb, &s, &c);
-      const double A = (double)jb.sp[n].A;
-      jb.sepB[kk] = make_float2((float)(A * c), (float)(A * s));
-    }
-  }
-}
-
-constexpr int kGK = 16;  // K chunk of the separable products
-
-// float2 load through a global-address-space view (two adjacent floats).
-__device__ __forceinline__ float2 ldg2(const float2* p) {
-  const HG_GLOBAL float* f = as_global(reinterpret_cast<const float*>(p));
-  return make_float2(f[0], f[1]);
-}
-
-__device__ __forceinline__ void cmac(float2& acc, const float2& a, const float2& b) {
-  acc.x = fmaf(a.x, b.x, fmaf(-a.y, b.y, acc.x));
-  acc.y = fmaf(a.x, b.y, fmaf(a.y, b.x, acc.y));
-}
-
-// One 64 x 64 output tile (rows j, columns i) per block.  Thread (tr, tc)
-// of the 16 x 16 thread grid owns rows tr + 16 r and columns tc + 16 c
-// (r, c < 4), so LDS reads of a column group are conflict-free.
-//  phase A  S = B F over the N spots (FP32, K chunks of 16 in LDS);
-//  FINAL    Phi = atan2(S) is written and the block ends;
-//  else     u = S / |S| goes to LDS; phase B forms, per chunk of 64 spots,
-//           T[j][n] = sum_i u(j,i) conj(F_n(i)) over the tile's columns and
-//           the block's partial V_n = sum_j conj(G_n(j)) T[j][n] (rows in
-//           fixed order), which the pass tail reduces and applies.
-template <bool FINAL>
-__global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ jobs,
-                                                     const SepDesc* __restrict__ descs,
-                                                     int ndesc) {
-  __shared__ float2 As[kSepTile][kGK + 1];
-  __shared__ float2 Bs[kGK][kSepTile];
-  __shared__ float2 us[FINAL ? 1 : kSepTile][kSepTile + 1];
-  __shared__ float2 red[16][kSepTile];
-  const int di = find_desc(descs, ndesc, blockIdx.x);
-  const SepDesc& d = descs[di];
-  const JobDev& jb = jobs[d.job];
-  const int W = jb.W, H = jb.H, N = jb.N;
-  const int lb = blockIdx.x - d.block_begin;
-  const int j0 = (lb / d.tiles_x) * kSepTile, i0 = (lb % d.tiles_x) * kSepTile;
-  const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;
-  const float2* Bt = jb.sepB;
-  const float2* Ft = jb.sepF;
-
-  float2 acc[4][4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[r][c] = make_float2(0.f, 0.f);
-  for (int k0 = 0; k0 < N; k0 += kGK) {
-    for (int e = threadIdx.x; e < kSepTile * kGK; e += kBlock) {
-      const int r = e / kGK, kk = e % kGK, j = j0 + r, n = k0 + kk;
-      As[r][kk] = (j < H && n < N) ? ldg2(Bt + (int64_t)j * N + n) : make_float2(0.f, 0.f);
-    }
-    for (int e = threadIdx.x; e < kGK * kSepTile; e += kBlock) {
-      const int kk = e / kSepTile, c = e % kSepTile, n = k0 + kk, i = i0 + c;
-      Bs[kk][c] = (n < N && i < W) ? ldg2(Ft + (int64_t)n * W + i) : make_float2(0.f, 0.f);
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < kGK; ++kk) {
-      float2 a[4], b[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) a[r] = As[tr + 16 * r][kk];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tc + 16 * c];
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) cmac(acc[r][c], a[r], b[c]);
-    }
-    __syncthreads();
-  }
-  if (FINAL) {
-    HG_GLOBAL float* out = as_global_mut(d.out);
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int j = j0 + tr + 16 * r, i = i0 + tc + 16 * c;
-        if (j < H && i < W) out[(int64_t)j * W + i] = atan2f(acc[r][c].y, acc[r][c].x);
-      }
-    return;
-  }
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int j = j0 + tr + 16 * r, i = i0 + tc + 16 * c;
-      float2 u = make_float2(0.f, 0.f);
-      if (j < H && i < W) {
-        const float m2 = acc[r][c].x * acc[r][c].x + acc[r][c].y * acc[r][c].y;
-        u = make_float2(1.f, 0.f);
-        if (m2 > 0.f) {
-          const float inv = rsqrtf(m2);
-          u = make_float2(acc[r][c].x * inv, acc[r][c].y * inv);
-        }
-      }
-      us[tr + 16 * r][tc + 16 * c] = u;
-    }
-  __syncthreads();
-  const float2* Gt = jb.sepG;
-  for (int n0 = 0; n0 < N; n0 += kSepTile) {
-    float2 t[4][4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) t[r][c] = make_float2(0.f, 0.f);
-    for (int k0 = 0; k0 < kSepTile; k0 += kGK) {
-      for (int e = threadIdx.x; e < kGK * kSepTile; e += kBlock) {
-        const int c = e / kGK, kk = e % kGK, n = n0 + c, i = i0 + k0 + kk;
-        const float2 v = (n < N && i < W) ? ldg2(Ft + (int64_t)n * W + i) : make_float2(0.f, 0.f);
-        Bs[kk][c] = make_float2(v.x, -v.y);
-      }
-      __syncthreads();
-#pragma unroll 4
-      for (int kk = 0; kk < kGK; ++kk) {
-        float2 a[4], b[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) a[r] = us[tr + 16 * r][k0 + kk];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) b[c] = Bs[kk][tc + 16 * c];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-#pragma unroll
-          for (int c = 0; c < 4; ++c) cmac(t[r][c], a[r], b[c]);
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int n = n0 + tc + 16 * c;
-      float2 v = make_float2(0.f, 0.f);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int j = j0 + tr + 16 * r;
-        if (j < H && n < N) {
-          const float2 g = ldg2(Gt + (int64_t)j * N + n);
-          cmac(v, make_float2(g.x, -g.y), t[r][c]);
-        }
-      }
-      red[tr][tc + 16 * c] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x < kSepTile) {
-      const int n = n0 + threadIdx.x;
-      if (n < N) {
-        float2 s = red[0][threadIdx.x];
-        for (int k = 1; k < 16; ++k) {
-          s.x += red[k][threadIdx.x].x;
-          s.y += red[k][threadIdx.x].y;
-        }
-        store_dev(jb.partial + (int64_t)lb * N + n, s);
-      }
-    }
-    __syncthreads();
-  }
-  PassCtx a;
-  a.sp = jb.sp;
-  a.coef = jb.coef;
-  a.N = N;
-  a.W = W;
-  a.H = H;
-  a.ps = PixelSet{nullptr, nullptr, 0, W * H, W * H};
-  a.phi = nullptr;
-  a.plan = d.plan;
-  a.lb = lb;
-  a.partial = jb.partial;
-  a.gpart = jb.gpart;
-  a.counters = jb.counters;
-  a.inv_count = d.inv_count;
-  a.V = d.V;
-  a.status = jb.status;
-  a.update = d.update;
-  a.from_phi = 0;
-  // one tile per block: count it, then the group and final sums
-  __shared__ int flag;
-  __shared__ double2 cred[kBlock];
-  __shared__ double wsum[kWaves];
-  const int g = lb / d.plan.group_size;
-  const int size = min(d.plan.group_size, d.plan.tiles - g * d.plan.group_size);
-  if (arrive_last(&jb.counters[g * kCounterStride], (unsigned)size, &flag) &&
-      tail_group(a, g, cred, &flag))
-    tail_final(a, cred, wsum);
 }
 
 // -------------------------------------------------------------- metrics ---
@@ -1036,6 +678,12 @@ __global__ void k_metric_reduce(const double2* __restrict__ partial, int nblk, i
 
 // ------------------------------------------------------------ launchers ---
 
+int sum_shift(int64_t pixels) {
+  int b = 0;  // ceil(log2(pixels))
+  while ((int64_t(1) << b) < pixels) ++b;
+  return 62 - b;
+}
+
 PassPlan plan_pass(int32_t count, int32_t block_cap) {
   PassPlan p;
   int64_t units = ceil_div(count, kTile);  // kTile-pixel sub-tiles
@@ -1048,6 +696,7 @@ PassPlan plan_pass(int32_t count, int32_t block_cap) {
   while (gs * gs < p.tiles) ++gs;
   p.group_size = gs;
   p.ngroups = ceil_div(p.tiles, gs);
+  p.shift = sum_shift(count);
   return p;
 }
 
@@ -1117,35 +766,6 @@ void launch_pass_batch(const JobDev* jobs, const PassDesc* descs, int ndesc, int
 
 int backprop_blocks(int32_t count) { return ceil_div(count, kBlock); }
 
-int sep_table_blocks(int W, int H, int N) { return ceil_div((int64_t)N * (W + H), 256); }
-
-void launch_sep_tables(const JobDev* jobs, const JobSlice* slices, int nslices, int total_blocks,
-                       hipStream_t s) {
-  if (nslices <= 0 || total_blocks <= 0) return;
-  hipLaunchKernelGGL(k_sep_tables, dim3(total_blocks), dim3(256), 0, s, jobs, slices, nslices);
-}
-
-PassPlan plan_sep(int W, int H) {
-  PassPlan p;
-  p.tiles = ceil_div(W, kSepTile) * ceil_div(H, kSepTile);
-  p.sub = 1;
-  p.blocks = p.tiles;
-  int gs = 1;
-  while (gs * gs < p.blocks) ++gs;
-  p.group_size = gs;
-  p.ngroups = ceil_div(p.blocks, gs);
-  return p;
-}
-
-void launch_sep_pass(const JobDev* jobs, const SepDesc* descs, int ndesc, int total_blocks,
-                     bool final, hipStream_t s) {
-  if (ndesc <= 0 || total_blocks <= 0) return;
-  if (final)
-    hipLaunchKernelGGL(k_sep_pass<true>, dim3(total_blocks), dim3(kBlock), 0, s, jobs, descs, ndesc);
-  else
-    hipLaunchKernelGGL(k_sep_pass<false>, dim3(total_blocks), dim3(kBlock), 0, s, jobs, descs,
-                       ndesc);
-}
 
 void launch_backprop_batch(const JobDev* jobs, const BackDesc* descs, int ndesc,
                            int total_blocks, hipStream_t s) {

@@ -43,13 +43,17 @@ constexpr int kFeistelRoundsHost = 6;  // rounds of the pixel permutation
 
 // Launch geometry of one pass over `count` pixels.
 struct PassPlan {
-  int32_t tiles;       // tiles of `sub` x kTile pixels; one partial-sum row per tile
+  int32_t tiles;       // tiles of `sub` x kTile pixels
   int32_t sub;         // kTile-pixel sub-tiles per tile (tiles <= kMaxTiles)
   int32_t blocks;      // blocks of this pass (they take the tiles dynamically)
   int32_t group_size;  // tiles per first-level reduction group
   int32_t ngroups;
+  int32_t shift;       // fixed-point scale 2^shift of the exact sums (|sum| <= pixels)
 };
 constexpr int32_t kMaxTiles = 8192;
+// Fixed-point scale of the exact sums of a pass over `pixels` pixels: every
+// term has magnitude <= 1, so |sum| * 2^shift <= 2^62.
+int sum_shift(int64_t pixels);
 // Tiles of one kTile sub-tile while there are at most kMaxTiles of them;
 // min(tiles, block_cap) blocks; groups of ceil(sqrt(tiles)) tiles.
 PassPlan plan_pass(int32_t count, int32_t block_cap);
@@ -70,25 +74,32 @@ struct JobDev {
   uint32_t* tab;       // [6 << h] Feistel tables (compressed only)
   int32_t* perm;       // [M] random pixel order (compressed only)
   float* phi;          // [H][W] output hologram (or input of a forward test pass)
-  float2* partial;     // [max pass tiles][N]
-  double2* gpart;      // [max pass groups][N]
+  float2* partial;     // [max pass tiles][N] (mixed-precision passes)
+  double2* gpart;      // [max pass groups][N] (mixed-precision passes)
+  // exact fixed-point sums of the FP32 passes: row 0 the pass total, row
+  // 1 + g group g; (re, im) two's-complement pairs per spot, zero between passes
+  unsigned long long* acc;  // [max pass groups + 1][N][2]
+  int64_t acc_len;
   unsigned* counters;  // [max pass groups + 1] group and pass counters, kCounterStride apart
   unsigned* grab;      // [iterations + 2] tile counters of the passes (PassDesc::grab_slot)
   int32_t counters_len;  // counters and grab, zeroed by the setup
   int32_t trace;       // V is [iterations][N] instead of [N]
   double2* V;
   int32_t* status;     // sticky status word of the caller's stream
-  // separable factors of the full-grid passes (see sep_tables):
-  float2* sepF;        // [N][W]  e^{i 2 pi fx_n(i)}
-  float2* sepB;        // [H][N]  A_n e^{i 2 pi (fy_n(j) + th_n)}
-  float2* sepG;        // [H][N]  e^{i 2 pi fy_n(j)}
-  // mixed-precision passes (see MxDesc): FP16 / FP32 factor tables in the
-  // lane order of the matrix-core operands, and the rank of every pixel in
-  // the random order (compressed jobs)
+  // factor tables of the full-grid passes in the lane order of the matrix-
+  // core operands (see SepDesc and MxDesc); dimensions shared by both forms
   int32_t mixed;
+  int32_t shared_e;    // compressed passes in the shared-exponential form
   int32_t mx_steps;    // Np / 16 with Np = N rounded up to 16
-  int32_t mx_cblocks;  // Wp / 16 with Wp = W rounded up to kMxTile
+  int32_t mx_cblocks;  // Wp / 16 with Wp = W rounded up to 64
   int32_t mx_rblocks;  // Hp / 16
+  // FP32 separable passes (FP32 jobs)
+  float* sepFc;        // [Wp/16][Np/2][64]   back-propagation B operand
+  float* sepFn;        // [Np/16][Wp/2][64]   forward B operand
+  float2* sepGa;       // [Hp/16][Np/2][64]   G by row, per lane
+  float4* sepGv;       // [Hp/16][Np/16][64] x 2 float4: G for the V sums
+  // mixed-precision passes: FP16 / FP32 tables and the rank of every pixel
+  // in the random order (compressed jobs)
   uint4* mxFc;         // [Wp/16][Np/16][64] x 4 half2   (back-propagation operand)
   uint4* mxFn;         // [Np/16][Wp/16][64] x 4 half2   (forward operand)
   float4* mxGa;        // [Hp/16][Np/16][64] x 4 float2  (rows by lane)
@@ -165,7 +176,7 @@ int backprop_blocks(int32_t count);
 // eq. (2) splits into a part in x' and a part in y': with doubled offsets,
 //   phi_n / 2pi = fx_n(i) + fy_n(j),  fx_n = cx Lx + cz Lx^2,  fy_n = cy Ly + cz Ly^2,
 // so e^{i phi_n(i,j)} = F_n(i) G_n(j).  A full-grid back-propagation is then
-// the complex product S = B F (B_n(j) = A_n e^{i th_n} G_n(j)) and the
+// the complex product S = B F (B_n(j) = C_n G_n(j), C_n = A_n e^{i th_n}) and the
 // full-grid forward sum is V_n = (1/M) sum_j conj(G_n(j)) sum_i u(j,i) conj(F_n(i)).
 constexpr int kSepTile = 64;  // output tile edge of the separable passes
 struct SepDesc {
@@ -179,15 +190,17 @@ struct SepDesc {
   double2* V;
   float* out;           // final-phase variant: Phi output
 };
-// Tables F, B, G of each listed job from its current state (FP64 phases).
-int sep_table_blocks(int W, int H, int N);
+// Factor tables of each listed job from its spot inputs (FP64 phases; they
+// do not change during the iterations).
+int sep_table_blocks(const JobDev& j);
 void launch_sep_tables(const JobDev* jobs, const JobSlice* slices, int nslices, int total_blocks,
                        hipStream_t s);
 PassPlan plan_sep(int W, int H);
-// Fused full-grid pass (back-propagation, forward, reduction, update) or,
-// with final != 0, the full-grid hologram Phi = arg(B F).
+// Fused full-grid pass (back-propagation S = B F and forward T = U conj(F)^T
+// on the FP32 matrix cores, exact sums, update) or, with final != 0, the
+// full-grid hologram Phi = arg(B F).  max_steps: largest Np / 16.
 void launch_sep_pass(const JobDev* jobs, const SepDesc* descs, int ndesc, int total_blocks,
-                     bool final, hipStream_t s);
+                     bool final, int max_steps, hipStream_t s);
 
 // ---- mixed-precision passes (FP16 matrix cores, FP32 sums) ----
 // A pass is the separable recast above on the matrix cores: per output tile

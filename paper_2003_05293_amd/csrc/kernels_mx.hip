@@ -454,6 +454,7 @@ PassPlan plan_mx(int W, int H) {
   PassPlan p;
   p.tiles = ceil_div(W, kMxTile) * ceil_div(H, kMxTile);
   p.sub = 1;
+  p.shift = 0;  // the mixed passes use compensated FP32 sums
   p.blocks = p.tiles;
   int gs = 1;
   while (gs * gs < p.blocks) ++gs;

@@ -1,0 +1,329 @@
+// Full-grid FP32 passes as separable products on the gfx950 matrix cores.
+//
+// With doubled pixel offsets the phase of eq. (2) splits into a part in the
+// column and a part in the row: e^{i phi_n(i,j)} = F_n(i) G_n(j).  The
+// back-propagated field of eq. (1) over the whole grid is then the complex
+// matrix product S = B F with B_n(j) = C_n G_n(j), C_n = A_n e^{i theta_n},
+// and the forward sums of eq. (3) over all pixels are
+//   V_n = (1/M) sum_j conj(G_n(j)) T[j][n],  T = U conj(F)^T,  U = e^{i Phi}.
+// Both products run as v_mfma_f32_16x16x4_f32 (FP32 operands and sums): a
+// complex product is a real one with K = 2 Np, the real and imaginary parts
+// of each spot (or pixel column) interleaved along K.  The factor tables are
+// evaluated once per hologram in FP64 (the spots do not move), so the
+// phases are exact to FP32 rounding; C_n comes from the state.
+#include <math.h>
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+#include "pass_tail.hpp"
+
+namespace hg {
+
+namespace {
+
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+// Operand layouts of v_mfma_f32_16x16x4_f32 (lane l, r < 4):
+//   A[l % 16][l / 16],  B[l / 16][l % 16],  D[4 (l / 16) + r][l % 16].
+// K-step s of a spot contraction covers spots 2s and 2s + 1; lane group
+// g = l / 16 holds part g % 2 (0 real, 1 imaginary) of spot 2 s + g / 2.
+// The tables hold, per 16-column (or 16-row) block and K-step, the 64
+// lanes' operands contiguously: one coalesced load per operand.
+__device__ __forceinline__ f4_t mfma4(float a, float b, const f4_t& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ int64_t op_index(int blk, int step, int steps, int lane) {
+  return ((int64_t)blk * steps + step) * 64 + lane;
+}
+
+// Factor tables from FP64 phases (zero outside the grid and beyond N):
+//   Fc  back-propagation B operand: part of F_n(col), col 16 cb + l%16,
+//       spot n = 2 s + g/2 of K-step s;
+//   Ga  G_n(row) for row 16 rb + l%16, spot 2 s + g/2 (forms the A operand);
+//   Fn  forward B operand: part of F_n(col), spot 16 sb + l%16, column
+//       2 cp + g/2 of column pair cp;
+//   Gv  G_n(row) for spot 16 sb + l%16 and rows 16 rb + 4 g + r (V sums).
+__global__ __launch_bounds__(256) void k_sep_tables(const JobDev* __restrict__ jobs,
+                                                    const JobSlice* __restrict__ slices,
+                                                    int nslices) {
+  const int si = find_desc(slices, nslices, blockIdx.x);
+  const JobDev& jb = jobs[slices[si].job];
+  const int lb = blockIdx.x - slices[si].block_begin;
+  const int W = jb.W, H = jb.H, N = jb.N;
+  const int S16 = jb.mx_steps, Np = 16 * S16, KS = Np / 2;
+  const int CB = jb.mx_cblocks, RB = jb.mx_rblocks, CP = 8 * CB;
+  const int64_t nF = (int64_t)(16 * CB) * Np, total = nF + (int64_t)(16 * RB) * Np;
+  const int nb = ceil_div(total, 256);
+  const double lf = jb.lambda_mm * jb.focal_mm;
+  const double lf2 = lf * jb.focal_mm;
+  const double kxy = jb.pitch_mm / (2.0 * lf), kz = jb.pitch_mm * jb.pitch_mm / (4.0 * lf2);
+  for (int64_t k = (int64_t)lb * 256 + threadIdx.x; k < total; k += (int64_t)nb * 256) {
+    if (k < nF) {
+      const int col = (int)(k / Np), n = (int)(k % Np);
+      float fr = 0.f, fi = 0.f;
+      if (col < W && n < N) {
+        const double L = (double)(2 * col - (W - 1));
+        double t = jb.in.x[n] * kxy * L + jb.in.z[n] * kz * L * L;
+        t -= rint(t);
+        double s, c;
+        sincospi(2.0 * t, &s, &c);
+        fr = (float)c;
+        fi = (float)s;
+      }
+      const int lgc = (n & 1) << 1, lgn = (col & 1) << 1;
+      for (int p = 0; p < 2; ++p) {
+        const float v = p ? fi : fr;
+        jb.sepFc[op_index(col >> 4, n >> 1, KS, (col & 15) + 16 * (lgc + p))] = v;
+        jb.sepFn[op_index(n >> 4, col >> 1, CP, (n & 15) + 16 * (lgn + p))] = v;
+      }
+    } else {
+      const int64_t kk = k - nF;
+      const int row = (int)(kk / Np), n = (int)(kk % Np);
+      float2 g = make_float2(0.f, 0.f);
+      if (row < H && n < N) {
+        const double L = (double)(2 * row - (H - 1));
+        double t = jb.in.y[n] * kxy * L + jb.in.z[n] * kz * L * L;
+        t -= rint(t);
+        double s, c;
+        sincospi(2.0 * t, &s, &c);
+        g = make_float2((float)c, (float)s);
+      }
+      const int lga = (n & 1) << 1;
+      for (int p = 0; p < 2; ++p)
+        jb.sepGa[op_index(row >> 4, n >> 1, KS, (row & 15) + 16 * (lga + p))] = g;
+      float2* Gv = reinterpret_cast<float2*>(jb.sepGv);
+      Gv[op_index(row >> 4, n >> 4, S16, (n & 15) + 16 * ((row & 15) >> 2)) * 4 + (row & 3)] = g;
+    }
+  }
+}
+
+constexpr int kSepSteps = 8;  // K-steps of the back-propagation product per load group
+constexpr int kSepCols = 8;   // column pairs of the forward product per load group
+
+// One kSepTile x kSepTile tile per block; wave w owns rows 16 w .. 16 w + 15
+// of the tile.  FINAL: write Phi = atan2(S) and stop; otherwise u = S / |S|,
+// T and the tile's partial V, added into the exact sums of its group.
+template <bool FINAL>
+__global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ jobs,
+                                                     const SepDesc* __restrict__ descs,
+                                                     int ndesc) {
+  extern __shared__ float2 cs[];                      // [Np] C_n = A_n e^{i theta_n}
+  __shared__ float2 us[kWaves][16][kSepTile + 1];     // u of each wave's rows
+  __shared__ float2 red[kWaves][64];
+  __shared__ int flag;
+  __shared__ double wsum[kWaves];
+  const int di = find_desc(descs, ndesc, blockIdx.x);
+  const SepDesc& d = descs[di];
+  const JobDev& jb = jobs[d.job];
+  const int W = jb.W, H = jb.H, N = jb.N, S16 = jb.mx_steps, KS = 8 * S16;
+  const int CP = 8 * jb.mx_cblocks;
+  const int lb = blockIdx.x - d.block_begin;
+  const int tx = lb % d.tiles_x, ty = lb / d.tiles_x;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4, part = lg & 1;
+  const int rb = 4 * ty + wave;
+  const int row0 = 16 * rb, col0 = kSepTile * tx;
+
+  for (int n = threadIdx.x; n < 16 * S16; n += kBlock) {
+    float2 c = make_float2(0.f, 0.f);
+    if (n < N) {
+      const HG_GLOBAL float* f = as_global(reinterpret_cast<const float*>(jb.coef + n));
+      c = make_float2(f[0], f[1]);
+    }
+    cs[n] = c;
+  }
+  __syncthreads();
+
+  // S = B F.  A operand: part of conj(B) (real output) or of i conj(B)
+  // (imaginary output); B_n(row) = C_n G_n(row) formed here in FP32.
+  f4_t sr[4], si[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) sr[t] = si[t] = f4_t{0.f, 0.f, 0.f, 0.f};
+  for (int s0 = 0; s0 < KS; s0 += kSepSteps) {
+    float2 ga[kSepSteps];
+    float fc[kSepSteps][4];
+#pragma unroll
+    for (int q = 0; q < kSepSteps; ++q) {
+      const int s = min(s0 + q, KS - 1);  // a repeated step is loaded, not used
+      const HG_GLOBAL float* gp =
+          as_global(reinterpret_cast<const float*>(jb.sepGa + op_index(rb, s, KS, lane)));
+      ga[q] = make_float2(gp[0], gp[1]);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) fc[q][t] = as_global(jb.sepFc)[op_index(4 * tx + t, s, KS, lane)];
+    }
+#pragma unroll
+    for (int q = 0; q < kSepSteps; ++q) {
+      if (s0 + q >= KS) break;
+      const float2 c = cs[2 * (s0 + q) + (lg >> 1)];
+      const float br = c.x * ga[q].x - c.y * ga[q].y, bi = c.x * ga[q].y + c.y * ga[q].x;
+      const float ar = part ? -bi : br, ai = part ? br : bi;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        sr[t] = mfma4(ar, fc[q][t], sr[t]);
+        si[t] = mfma4(ai, fc[q][t], si[t]);
+      }
+    }
+  }
+
+  if (FINAL) {
+    HG_GLOBAL float* out = as_global_mut(d.out);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + 4 * lg + r, col = col0 + 16 * t + lr;
+        if (row < H && col < W) out[(int64_t)row * W + col] = atan2f(si[t][r], sr[t][r]);
+      }
+    return;
+  }
+
+  // u = e^{i Phi} over the grid (0 outside it), in LDS.
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = row0 + 4 * lg + r, col = col0 + 16 * t + lr;
+      float2 u = make_float2(0.f, 0.f);
+      if (row < H && col < W) {
+        const float m2 = sr[t][r] * sr[t][r] + si[t][r] * si[t][r];
+        u = make_float2(1.f, 0.f);
+        if (m2 > 0.f) {
+          const float inv = rsqrtf(m2);
+          u = make_float2(sr[t][r] * inv, si[t][r] * inv);
+        }
+      }
+      us[wave][4 * lg + r][16 * t + lr] = u;
+    }
+  __syncthreads();
+
+  // T = U conj(F)^T for the wave's 16 rows, 64 spots per chunk; the tile's
+  // partial V_n = sum_j conj(G_n(j)) T[j][n] joins its group's exact sums.
+  const int g = lb / d.plan.group_size;
+  for (int sb0 = 0; sb0 < S16; sb0 += 4) {
+    f4_t tr[4], ti[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) tr[k] = ti[k] = f4_t{0.f, 0.f, 0.f, 0.f};
+    for (int c0 = 0; c0 < kSepTile / 2; c0 += kSepCols) {
+      float fn[kSepCols][4];
+#pragma unroll
+      for (int q = 0; q < kSepCols; ++q)
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          fn[q][k] = sb0 + k < S16
+                         ? as_global(jb.sepFn)[op_index(sb0 + k, col0 / 2 + c0 + q, CP, lane)]
+                         : 0.f;
+#pragma unroll
+      for (int q = 0; q < kSepCols; ++q) {
+        const float2 u = us[wave][lr][2 * (c0 + q) + (lg >> 1)];
+        const float ar = part ? u.y : u.x, ai = part ? -u.x : u.y;  // parts of u and of -i u
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (sb0 + k < S16) {
+            tr[k] = mfma4(ar, fn[q][k], tr[k]);
+            ti[k] = mfma4(ai, fn[q][k], ti[k]);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      float vr = 0.f, vi = 0.f;
+      if (sb0 + k < S16) {
+        const int64_t gv = op_index(rb, sb0 + k, S16, lane) * 2;
+        const f4_t g01 = as_global(reinterpret_cast<const f4_t*>(jb.sepGv))[gv];
+        const f4_t g23 = as_global(reinterpret_cast<const f4_t*>(jb.sepGv))[gv + 1];
+        const float gr[4] = {g01[0], g01[2], g23[0], g23[2]};
+        const float gi[4] = {g01[1], g01[3], g23[1], g23[3]};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          vr = fmaf(gr[r], tr[k][r], fmaf(gi[r], ti[k][r], vr));
+          vi = fmaf(gr[r], ti[k][r], fmaf(-gi[r], tr[k][r], vi));
+        }
+      }
+      vr += __shfl_xor(vr, 16);
+      vi += __shfl_xor(vi, 16);
+      vr += __shfl_xor(vr, 32);
+      vi += __shfl_xor(vi, 32);
+      if (lg == 0) red[wave][16 * k + lr] = make_float2(vr, vi);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const int n = 16 * sb0 + threadIdx.x;
+      if (n < N) {
+        float2 v = red[0][threadIdx.x];
+#pragma unroll
+        for (int w = 1; w < kWaves; ++w) {
+          v.x += red[w][threadIdx.x].x;
+          v.y += red[w][threadIdx.x].y;
+        }
+        acc_add(jb.acc, N, d.plan.shift, 1 + g, n, v);
+      }
+    }
+    __syncthreads();
+  }
+
+  PassCtx a;
+  a.sp = jb.sp;
+  a.coef = jb.coef;
+  a.N = N;
+  a.W = W;
+  a.H = H;
+  a.ps = PixelSet{nullptr, nullptr, 0, W * H, W * H};
+  a.phi = nullptr;
+  a.plan = d.plan;
+  a.lb = lb;
+  a.partial = jb.partial;
+  a.gpart = jb.gpart;
+  a.acc = jb.acc;
+  a.counters = jb.counters;
+  a.inv_count = d.inv_count;
+  a.V = d.V;
+  a.status = jb.status;
+  a.update = d.update;
+  a.from_phi = 0;
+  const int size = min(d.plan.group_size, d.plan.tiles - g * d.plan.group_size);
+  if (arrive_last(&jb.counters[g * kCounterStride], (unsigned)size, &flag) &&
+      tail_group(a, g, &flag))
+    tail_final(a, wsum);
+}
+
+}  // namespace
+
+int sep_table_blocks(const JobDev& j) {
+  const int64_t total = (int64_t)16 * (j.mx_cblocks + j.mx_rblocks) * 16 * j.mx_steps;
+  return ceil_div(total, 256);
+}
+
+void launch_sep_tables(const JobDev* jobs, const JobSlice* slices, int nslices, int total_blocks,
+                       hipStream_t s) {
+  if (nslices <= 0 || total_blocks <= 0) return;
+  hipLaunchKernelGGL(k_sep_tables, dim3(total_blocks), dim3(256), 0, s, jobs, slices, nslices);
+}
+
+PassPlan plan_sep(int W, int H) {
+  PassPlan p;
+  p.tiles = ceil_div(W, kSepTile) * ceil_div(H, kSepTile);
+  p.sub = 1;
+  p.blocks = p.tiles;
+  int gs = 1;
+  while (gs * gs < p.blocks) ++gs;
+  p.group_size = gs;
+  p.ngroups = ceil_div(p.blocks, gs);
+  p.shift = sum_shift((int64_t)W * H);
+  return p;
+}
+
+void launch_sep_pass(const JobDev* jobs, const SepDesc* descs, int ndesc, int total_blocks,
+                     bool final, int max_steps, hipStream_t s) {
+  if (ndesc <= 0 || total_blocks <= 0) return;
+  const size_t shmem = sizeof(float2) * 16 * (size_t)(max_steps > 0 ? max_steps : 1);
+  if (final)
+    hipLaunchKernelGGL(k_sep_pass<true>, dim3(total_blocks), dim3(kBlock), shmem, s, jobs, descs,
+                       ndesc);
+  else
+    hipLaunchKernelGGL(k_sep_pass<false>, dim3(total_blocks), dim3(kBlock), shmem, s, jobs, descs,
+                       ndesc);
+}
+
+}  // namespace hg

@@ -245,6 +245,7 @@ JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev
   j.trace = s.trace_host ? 1 : 0;
   j.status = status_dev;
   j.mixed = s.precision == HG_PREC_MIXED ? 1 : 0;
+  j.shared_e = (!j.mixed && tp.pass_form == 1 && pass_e_width(s.N) > 0) ? 1 : 0;
   L.separable = !j.mixed && tp.separable_full && !s.full_direct;
   L.plan_all = plan_pass(j.M, tp.full_block_cap);
   L.plan_sub = j.compressed ? plan_pass(j.m, tp.subset_block_cap) : L.plan_all;
@@ -252,12 +253,15 @@ JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev
   L.plan_mx = plan_mx(j.W, j.H);
   // partial-sum rows: one per tile of the largest pass the job can run
   int max_rows = 0, max_groups = 0;
-  if (j.mixed) {
-    max_rows = L.plan_mx.tiles;
-    max_groups = L.plan_mx.ngroups;
+  if (j.mixed || L.separable) {  // operand tables of the matrix-core passes
+    static_assert(kSepTile == kMxTile, "one table geometry for both full-grid forms");
     j.mx_steps = (s.N + 15) / 16;
     j.mx_cblocks = (s.W + kMxTile - 1) / kMxTile * (kMxTile / 16);
     j.mx_rblocks = (s.H + kMxTile - 1) / kMxTile * (kMxTile / 16);
+  }
+  if (j.mixed) {
+    max_rows = L.plan_mx.tiles;
+    max_groups = L.plan_mx.ngroups;
   } else {
     // direct full-grid passes: without the separable form, and for the
     // single-pass entry points
@@ -297,15 +301,22 @@ JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev
     L.off_mxGv = take(32 * ops * j.mx_rblocks);
     L.off_rank = j.compressed ? take(sizeof(uint32_t) * (size_t)j.M) : 0;
   }
-  L.off_partial = take(sizeof(float2) * (size_t)max_rows * s.N);
-  L.off_gpart = take(sizeof(double2) * (size_t)max_groups * s.N);
+  if (j.mixed) {  // compensated FP32 sums of the mixed-precision passes
+    L.off_partial = take(sizeof(float2) * (size_t)max_rows * s.N);
+    L.off_gpart = take(sizeof(double2) * (size_t)max_groups * s.N);
+  } else {        // exact fixed-point sums of the FP32 passes
+    j.acc_len = (int64_t)(max_groups + 1) * s.N * 2;
+    L.off_acc = take(sizeof(unsigned long long) * (size_t)j.acc_len);
+  }
   L.off_counters = take(sizeof(unsigned) * (size_t)j.counters_len);
   L.off_V = take(sizeof(double2) * (size_t)s.N *
                  (s.trace_host && s.iterations > 0 ? s.iterations : 1));
   if (L.separable) {
-    L.off_sepF = take(sizeof(float2) * (size_t)s.N * s.W);
-    L.off_sepB = take(sizeof(float2) * (size_t)s.N * s.H);
-    L.off_sepG = take(sizeof(float2) * (size_t)s.N * s.H);
+    const size_t ops = (size_t)j.mx_steps * 64;  // operand lanes per 16-row/column block
+    L.off_sepFc = take(sizeof(float) * 8 * ops * j.mx_cblocks);
+    L.off_sepFn = take(sizeof(float) * 8 * ops * j.mx_cblocks);
+    L.off_sepGa = take(sizeof(float2) * 8 * ops * j.mx_rblocks);
+    L.off_sepGv = take(sizeof(float2) * 4 * ops * j.mx_rblocks);
   }
   L.bytes = align_up(bytes, 256);
   return L;
@@ -323,14 +334,18 @@ JobDev bind_job(const JobLayout& L, const JobSpec& s, char* base, const double* 
   j.coef = reinterpret_cast<float2*>(base + L.off_coef);
   j.tab = j.compressed ? reinterpret_cast<uint32_t*>(base + L.off_tab) : nullptr;
   j.perm = j.compressed ? reinterpret_cast<int32_t*>(base + L.off_perm) : nullptr;
-  j.partial = reinterpret_cast<float2*>(base + L.off_partial);
-  j.gpart = reinterpret_cast<double2*>(base + L.off_gpart);
+  j.partial = j.mixed ? reinterpret_cast<float2*>(base + L.off_partial) : nullptr;
+  j.gpart = j.mixed ? reinterpret_cast<double2*>(base + L.off_gpart) : nullptr;
+  j.acc = j.mixed ? nullptr : reinterpret_cast<unsigned long long*>(base + L.off_acc);
   j.counters = reinterpret_cast<unsigned*>(base + L.off_counters);
   j.grab = j.counters + L.grab_offset;
   j.V = reinterpret_cast<double2*>(base + L.off_V);
-  j.sepF = L.separable ? reinterpret_cast<float2*>(base + L.off_sepF) : nullptr;
-  j.sepB = L.separable ? reinterpret_cast<float2*>(base + L.off_sepB) : nullptr;
-  j.sepG = L.separable ? reinterpret_cast<float2*>(base + L.off_sepG) : nullptr;
+  if (L.separable) {
+    j.sepFc = reinterpret_cast<float*>(base + L.off_sepFc);
+    j.sepFn = reinterpret_cast<float*>(base + L.off_sepFn);
+    j.sepGa = reinterpret_cast<float2*>(base + L.off_sepGa);
+    j.sepGv = reinterpret_cast<float4*>(base + L.off_sepGv);
+  }
   if (j.mixed) {
     j.mxFc = reinterpret_cast<uint4*>(base + L.off_mxFc);
     j.mxFn = reinterpret_cast<uint4*>(base + L.off_mxFn);
@@ -422,20 +437,18 @@ void LaunchSet::add_iteration(const JobDev& j, const JobLayout& L, int it, int i
     return;
   }
   if (!sub && L.separable) {
-    tabs.push_back(JobSlice{tab_blocks, index});
-    tab_blocks += sep_table_blocks(j.W, j.H, j.N);
     SepDesc d = sep_desc(j, L, index, sep_blocks);
     d.update = 1;
     d.V = j.V + (j.trace ? (size_t)(it - 1) * j.N : 0);
     sep.push_back(d);
     sep_blocks += d.plan.blocks;
+    sep_steps = std::max(sep_steps, j.mx_steps);
     return;
   }
   const PassDesc d = iteration_desc(j, L, it, index, pass_blocks);
   pass.push_back(d);
   pass_blocks += d.plan.blocks;
-  const int ew = pass_e_width(j.N);
-  if (ew > 0) e_width = std::max(e_width, ew);
+  if (j.shared_e) e_width = std::max(e_width, pass_e_width(j.N));
   else units = std::max(units, pass_units_per_wave(j.N));
 }
 
@@ -450,12 +463,11 @@ void LaunchSet::add_final(const JobDev& j, const JobLayout& L, int index) {
     return;
   }
   if (L.separable) {
-    tabs.push_back(JobSlice{tab_blocks, index});
-    tab_blocks += sep_table_blocks(j.W, j.H, j.N);
     SepDesc d = sep_desc(j, L, index, sep_blocks);
     d.out = j.phi;
     sep.push_back(d);
     sep_blocks += d.plan.blocks;
+    sep_steps = std::max(sep_steps, j.mx_steps);
     sep_final = true;
     return;
   }
@@ -470,8 +482,7 @@ void LaunchSet::add_final(const JobDev& j, const JobLayout& L, int index) {
 
 size_t LaunchSet::bytes() const {
   return align_up(sizeof(PassDesc) * pass.size(), 256) + align_up(sizeof(SepDesc) * sep.size(), 256) +
-         align_up(sizeof(JobSlice) * tabs.size(), 256) + align_up(sizeof(BackDesc) * back.size(), 256) +
-         align_up(sizeof(MxDesc) * mx.size(), 256);
+         align_up(sizeof(BackDesc) * back.size(), 256) + align_up(sizeof(MxDesc) * mx.size(), 256);
 }
 
 size_t LaunchSet::stage(char* host, char* dev) {
@@ -484,7 +495,6 @@ size_t LaunchSet::stage(char* host, char* dev) {
   };
   d_pass = reinterpret_cast<const PassDesc*>(put(pass.data(), sizeof(PassDesc) * pass.size()));
   d_sep = reinterpret_cast<const SepDesc*>(put(sep.data(), sizeof(SepDesc) * sep.size()));
-  d_tabs = reinterpret_cast<const JobSlice*>(put(tabs.data(), sizeof(JobSlice) * tabs.size()));
   d_back = reinterpret_cast<const BackDesc*>(put(back.data(), sizeof(BackDesc) * back.size()));
   d_mx = reinterpret_cast<const MxDesc*>(put(mx.data(), sizeof(MxDesc) * mx.size()));
   return o;
@@ -495,11 +505,10 @@ void LaunchSet::launch(const JobDev* jobs, hipStream_t s, bool capture) const {
     if (capture) f();
     else timed(s, name, f);
   };
-  if (!tabs.empty())
-    run("k_sep_tables", [&] { launch_sep_tables(jobs, d_tabs, (int)tabs.size(), tab_blocks, s); });
   if (!sep.empty())
-    run(sep_final ? "k_sep_final" : "k_sep_pass",
-        [&] { launch_sep_pass(jobs, d_sep, (int)sep.size(), sep_blocks, sep_final, s); });
+    run(sep_final ? "k_sep_final" : "k_sep_pass", [&] {
+      launch_sep_pass(jobs, d_sep, (int)sep.size(), sep_blocks, sep_final, sep_steps, s);
+    });
   if (!pass.empty()) {
     bool any_full = false, any_sub = false;
     for (const PassDesc& d : pass) (d.ps.count == d.ps.M && !d.ps.perm ? any_full : any_sub) = true;
@@ -565,6 +574,8 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
   perm_blocks_ = 0;
   mxtab_.clear();
   mxtab_blocks_ = 0;
+  septab_.clear();
+  septab_blocks_ = 0;
   for (int i = 0; i < count; ++i) {
     const JobDev& j = jobs_[i];
     if (j.phi) final_.add_final(j, layouts_[i], i);
@@ -576,13 +587,20 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
       mxtab_.push_back(JobSlice{mxtab_blocks_, i});
       mxtab_blocks_ += mx_table_blocks(j);
     }
+    if (layouts_[i].separable) {
+      septab_.push_back(JobSlice{septab_blocks_, i});
+      septab_blocks_ += sep_table_blocks(j);
+    }
   }
-  // descriptor tables: [JobDev][JobSlice perm][JobSlice mx tables][rounds...][final]
+  // descriptor tables: [JobDev][JobSlice perm][JobSlice mx tables]
+  // [JobSlice sep tables][rounds...][final]
   size_t tb = align_up(sizeof(JobDev) * count, 256);
   const size_t t_perm = tb;
   tb = align_up(tb + sizeof(JobSlice) * perm_.size(), 256);
   const size_t t_mxtab = tb;
   tb = align_up(tb + sizeof(JobSlice) * mxtab_.size(), 256);
+  const size_t t_septab = tb;
+  tb = align_up(tb + sizeof(JobSlice) * septab_.size(), 256);
   const size_t t_sets = tb;
   for (const LaunchSet& ls : rounds_) tb += ls.bytes();
   tb += final_.bytes();
@@ -597,6 +615,9 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
   mxtab_dev_ = reinterpret_cast<JobSlice*>(table_.p + t_mxtab);
   if (!mxtab_.empty())
     std::memcpy(staging_.p + t_mxtab, mxtab_.data(), sizeof(JobSlice) * mxtab_.size());
+  septab_dev_ = reinterpret_cast<JobSlice*>(table_.p + t_septab);
+  if (!septab_.empty())
+    std::memcpy(staging_.p + t_septab, septab_.data(), sizeof(JobSlice) * septab_.size());
   size_t o = t_sets;
   for (LaunchSet& ls : rounds_) o += ls.stage(staging_.p + o, table_.p + o);
   o += final_.stage(staging_.p + o, table_.p + o);
@@ -630,6 +651,10 @@ hg_status Batch::enqueue_prologue(hipStream_t s, bool capture) {
   if (mxtab_blocks_ > 0)
     run("k_mx_tables", [&] {
       launch_mx_tables(jobs_dev_, mxtab_dev_, (int)mxtab_.size(), mxtab_blocks_, s);
+    });
+  if (septab_blocks_ > 0)
+    run("k_sep_tables", [&] {
+      launch_sep_tables(jobs_dev_, septab_dev_, (int)septab_.size(), septab_blocks_, s);
     });
   return HG_OK;
 }
@@ -683,6 +708,7 @@ void Batch::release() {
   jobs_dev_ = nullptr;
   perm_dev_ = nullptr;
   mxtab_dev_ = nullptr;
+  septab_dev_ = nullptr;
 }
 
 }  // namespace hg

@@ -84,6 +84,7 @@ struct TuneParams {
   int32_t full_block_cap = kDefaultBlockCap;
   int32_t subset_block_cap = kDefaultBlockCap;
   bool separable_full = true;  // full-grid passes as separable products
+  int32_t pass_form = 0;       // 1: shared-exponential compressed passes where N allows
 };
 
 // Validation of the host-visible parts of a hologram description.
@@ -98,9 +99,10 @@ struct JobLayout {
   JobDev dev;  // every field but the pointers
   PassPlan plan_all, plan_sub, plan_sep, plan_mx;
   bool separable = false;
-  size_t off_raw = 0, off_sp = 0, off_coef = 0, off_tab = 0, off_perm = 0, off_partial = 0, off_gpart = 0,
-         off_counters = 0, off_V = 0, off_sepF = 0, off_sepB = 0, off_sepG = 0, off_mxFc = 0,
-         off_mxFn = 0, off_mxGa = 0, off_mxGv = 0, off_rank = 0;
+  size_t off_raw = 0, off_sp = 0, off_coef = 0, off_tab = 0, off_perm = 0, off_partial = 0,
+         off_gpart = 0, off_acc = 0, off_counters = 0, off_V = 0, off_sepFc = 0, off_sepFn = 0,
+         off_sepGa = 0, off_sepGv = 0, off_mxFc = 0, off_mxFn = 0, off_mxGa = 0, off_mxGv = 0,
+         off_rank = 0;
   size_t bytes = 0;
   bool raw_inline = false;  // the job's own scratch holds a copy of its spot arrays
   int grab_offset = 0;      // the pass tile counters follow the group counters
@@ -116,18 +118,16 @@ PassDesc iteration_desc(const JobDev& j, const JobLayout& L, int it, int index, 
 PixelSet all_pixels(int32_t M);
 
 // The launches of one iteration round (or of the final phase) of a set of
-// jobs: compressed passes (k_pass_batch), separable full-grid passes (tables
-// then k_sep_pass), direct full-grid final phases (k_backprop_batch) and the
+// jobs: compressed passes (k_pass_batch), separable full-grid passes
+// (k_sep_pass, on the factor tables built by the prologue), direct full-grid final phases (k_backprop_batch) and the
 // passes of mixed-precision jobs (k_mx_pass).
 struct LaunchSet {
   std::vector<PassDesc> pass;
   int pass_blocks = 0, units = 1;
   int e_width = 0;  // widest shared-exponential form among the passes (0: none)
   std::vector<SepDesc> sep;
-  int sep_blocks = 0;
+  int sep_blocks = 0, sep_steps = 0;
   bool sep_final = false;
-  std::vector<JobSlice> tabs;
-  int tab_blocks = 0;
   std::vector<BackDesc> back;
   int back_blocks = 0;
   std::vector<MxDesc> mx;
@@ -136,7 +136,6 @@ struct LaunchSet {
   // device copies, set by stage()
   const PassDesc* d_pass = nullptr;
   const SepDesc* d_sep = nullptr;
-  const JobSlice* d_tabs = nullptr;
   const BackDesc* d_back = nullptr;
   const MxDesc* d_mx = nullptr;
 
@@ -150,7 +149,7 @@ struct LaunchSet {
   // Copies the descriptors into host staging at `host` and points the
   // device copies at `dev` (same offsets); returns the bytes used.
   size_t stage(char* host, char* dev);
-  // Launches (tables before the separable pass).  `capture`: no timing.
+  // Launches the set's kernels.  `capture`: no timing.
   void launch(const JobDev* jobs, hipStream_t s, bool capture) const;
 };
 
@@ -211,6 +210,9 @@ class Batch {
   std::vector<JobSlice> mxtab_;          // factor tables of the mixed-precision jobs
   int mxtab_blocks_ = 0;
   JobSlice* mxtab_dev_ = nullptr;
+  std::vector<JobSlice> septab_;         // factor tables of the separable FP32 jobs
+  int septab_blocks_ = 0;
+  JobSlice* septab_dev_ = nullptr;
   bool perm_lds_ = true;
   int max_h_ = 0;
   size_t host_spot_bytes_ = 0;

@@ -17,10 +17,11 @@ def test_table_round_trip(tmp_path):
     path = tmp_path / "t.json"
     t = autotune.Table(str(path))
     key = autotune.single_key(Grid(64, 64), 5, 3, 0.5, "fp32")
-    t.entries[key] = {"full_block_cap": 0, "subset_block_cap": 256, "ms": 1.0,
-                      "sweep_ms": {"full=0,subset=256": 1.0}}
+    t.entries[key] = {"full_block_cap": 0, "subset_block_cap": 256, "pass_form": 1, "ms": 1.0,
+                      "sweep_ms": {"full=0,subset=256,form=1": 1.0}}
     t.save()
     again = autotune.Table(str(path))
     assert again.entries == json.loads(path.read_text())
     assert autotune.Table.as_tune(again.entries[key]) == {"full_block_cap": 0,
-                                                          "subset_block_cap": 256}
+                                                          "subset_block_cap": 256,
+                                                          "pass_form": 1}

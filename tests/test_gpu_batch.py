@@ -200,3 +200,16 @@ def test_autotuner_picks_a_measured_candidate(tmp_path):
     assert entry["ms"] == min(entry["sweep_ms"].values())
     again = autotune.Table(str(tmp_path / "tune.json"))
     assert again.single(g, OPTICS, s, 8, 1 / 16) == t  # cached, not re-timed
+
+
+def test_shared_exponential_form_alone_equals_batch():
+    import torch
+    form = {"full_block_cap": 0, "subset_block_cap": 0, "pass_form": 1}
+    jobs = _jobs(CASES[:4])
+    say("shared-e batch vs alone")
+    alone = [hg.cswgs(g, OPTICS, s, I, c, seed, tune=form).clone() for g, s, I, c, seed in jobs]
+    dj = [hg.DeviceJob.from_spots(g, OPTICS, s, I, c, seed) for g, s, I, c, seed in jobs]
+    out = hg.cswgs_batch(dj, tune=form)
+    torch.cuda.synchronize()
+    for k in range(len(jobs)):
+        assert torch.equal(out[k], alone[k]), k

@@ -392,3 +392,41 @@ def test_full_size_against_stored_oracle(name):
     print(name, "e", e, gd["e"], "u", u, gd["u"], "V^1 rel", e1, "Phi sample", st)
     assert abs(e - gd["e"]) <= EU_TOL and abs(u - gd["u"]) <= EU_TOL
     assert e1 <= REL_V
+
+
+# ------------------------------------- shared-exponential pass form ---
+
+SHARED_E = {"full_block_cap": 0, "subset_block_cap": 0, "pass_form": 1}
+
+
+@pytest.mark.parametrize("W,H,N,I,c,seed", [(256, 256, 16, 20, 1 / 16, 0), (300, 170, 37, 8, 0.1, 11),
+                                             (512, 512, 100, 10, 1 / 16, 4), (96, 64, 1, 5, 0.25, 2)])
+def test_shared_exponential_form_vs_oracle(W, H, N, I, c, seed):
+    """pass_form 1: one complex exponential per (pixel, spot) pair shared by
+    both propagation directions; same bars as the two-sincos form."""
+    g = Grid(W, H)
+    s = spot_cloud(seed, N, g, z_half_mm=0.1)
+    say("shared-exponential form", W, H, N, I, c)
+    phi_g, Vg = hg.cswgs(g, OPTICS, s, I, c, seed, trace=True, tune=SHARED_E)
+    tr = oracle.Trace()
+    phi_o = oracle.cswgs(g, OPTICS, s, I, c, seed, tr)
+    eg, ug, _ = hg.metrics(g, OPTICS, s, phi_g)
+    eo, uo, _ = oracle.metrics(g, OPTICS, s, phi_o)
+    e1 = rel_mag_err(Vg[0], tr.V[0])
+    print("shared-e", W, H, N, "e", eg, eo, "u", ug, uo, "V^1 rel", e1)
+    assert abs(eg - eo) <= EU_TOL and abs(ug - uo) <= EU_TOL
+    assert e1 <= REL_V
+
+
+def test_shared_exponential_form_full_size():
+    gd = _golden("cswgs_1152x1152_n100_i30_c16_seed0")
+    g = Grid(gd["W"], gd["H"])
+    s = spot_cloud(gd["seed"], gd["n"], g, z_half_mm=gd["z_half_mm"])
+    say("shared-exponential form full size")
+    phi, V = hg.cswgs(g, OPTICS, s, gd["iterations"], gd["compression"], gd["seed"], trace=True,
+                      tune=SHARED_E)
+    e, u, _ = hg.metrics(g, OPTICS, s, phi)
+    V1 = np.array(gd["V1"])
+    e1 = rel_mag_err(V[0], V1[:, 0] + 1j * V1[:, 1])
+    print("shared-e full size e", e, gd["e"], "u", u, gd["u"], "V^1 rel", e1)
+    assert abs(e - gd["e"]) <= EU_TOL and abs(u - gd["u"]) <= EU_TOL and e1 <= REL_V
