@@ -53,14 +53,34 @@ __device__ __forceinline__ float2 backprop_field(const SpotRec* spg, int n0, int
                                                  const PixCoord& c) {
   const HG_CONST SpotRec* sp = as_const(spg);
   float sr = 0.f, si = 0.f;
-#pragma unroll 4
-  for (int n = n0; n < n1; ++n) {
-    const float scx = sp[n].cx, scy = sp[n].cy, scz = sp[n].cz, sth = sp[n].th, sA = sp[n].A;
-    const float t = fmaf(scx, c.Lx, fmaf(scy, c.Ly, fmaf(scz, c.Q, sth)));
+  // groups of four spots: the four records are requested together, so one
+  // wait covers them
+  int n = n0;
+  for (; n + 3 < n1; n += 4) {
+    float scx[4], scy[4], scz[4], sth[4], sA[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      scx[k] = sp[n + k].cx;
+      scy[k] = sp[n + k].cy;
+      scz[k] = sp[n + k].cz;
+      sth[k] = sp[n + k].th;
+      sA[k] = sp[n + k].A;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float t = fmaf(scx[k], c.Lx, fmaf(scy[k], c.Ly, fmaf(scz[k], c.Q, sth[k])));
+      float sn, cs;
+      sincos_turns(t, sn, cs);
+      sr = fmaf(sA[k], cs, sr);
+      si = fmaf(sA[k], sn, si);
+    }
+  }
+  for (; n < n1; ++n) {
+    const float t = fmaf(sp[n].cx, c.Lx, fmaf(sp[n].cy, c.Ly, fmaf(sp[n].cz, c.Q, sp[n].th)));
     float sn, cs;
     sincos_turns(t, sn, cs);
-    sr = fmaf(sA, cs, sr);
-    si = fmaf(sA, sn, si);
+    sr = fmaf(sp[n].A, cs, sr);
+    si = fmaf(sp[n].A, sn, si);
   }
   return make_float2(sr, si);
 }
@@ -351,8 +371,25 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab) {
         if (u < lm.U) {
           const int sl = u % lm.S;
           const int j0 = (sl * kTile) / lm.S + r, j1 = ((sl + 1) * kTile) / lm.S;
-          for (int j = j0; j < j1; j += lm.R)
-            forward_term(cx[k], cy[k], cz[k], px[j], pui[j], vr[k], vi[k]);
+          // one unit per wave: four pixels per step, read from LDS
+          // together, into two sums (with more units the registers go to
+          // the units' sums)
+          float ar = vr[k], ai = vi[k], br = 0.f, bi = 0.f;
+          int j = j0;
+          if (MAXU == 1)
+          for (; j + 3 * lm.R < j1; j += 4 * lm.R) {
+            const float4 p0 = px[j], p1 = px[j + lm.R], p2 = px[j + 2 * lm.R],
+                         p3 = px[j + 3 * lm.R];
+            const float u0 = pui[j], u1 = pui[j + lm.R], u2 = pui[j + 2 * lm.R],
+                        u3 = pui[j + 3 * lm.R];
+            forward_term(cx[k], cy[k], cz[k], p0, u0, ar, ai);
+            forward_term(cx[k], cy[k], cz[k], p1, u1, br, bi);
+            forward_term(cx[k], cy[k], cz[k], p2, u2, ar, ai);
+            forward_term(cx[k], cy[k], cz[k], p3, u3, br, bi);
+          }
+          for (; j < j1; j += lm.R) forward_term(cx[k], cy[k], cz[k], px[j], pui[j], ar, ai);
+          vr[k] = ar + br;
+          vi[k] = ai + bi;
         }
       }
       __syncthreads();

@@ -101,9 +101,117 @@ __global__ __launch_bounds__(256) void k_sep_tables(const JobDev* __restrict__ j
 constexpr int kSepSteps = 8;  // K-steps of the back-propagation product per load group
 constexpr int kSepCols = 8;   // column pairs of the forward product per load group
 
-// One kSepTile x kSepTile tile per block; wave w owns rows 16 w .. 16 w + 15
-// of the tile.  FINAL: write Phi = atan2(S) and stop; otherwise u = S / |S|,
-// T and the tile's partial V, added into the exact sums of its group.
+// Operands of kSepSteps K-steps of S = B F for one wave: G_n(row) of its
+// rows and the F operand of the tile's four 16-column blocks.  Loads of the
+// next group are issued before the products of the current one.
+struct BpOps {
+  float2 ga[kSepSteps];
+  float fc[kSepSteps][4];
+};
+__device__ __forceinline__ void bp_load(BpOps& o, const JobDev& jb, int rb, int tx, int s0, int KS,
+                                        int lane) {
+#pragma unroll
+  for (int q = 0; q < kSepSteps; ++q) {
+    const HG_GLOBAL float* gp =
+        as_global(reinterpret_cast<const float*>(jb.sepGa + op_index(rb, s0 + q, KS, lane)));
+    o.ga[q] = make_float2(gp[0], gp[1]);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) o.fc[q][t] = as_global(jb.sepFc)[op_index(4 * tx + t, s0 + q, KS, lane)];
+  }
+}
+// A operand: part of B (real output: (Br, -Bi)) or of i B (imaginary
+// output: (Bi, Br)) with B_n(row) = C_n G_n(row) formed in FP32.
+__device__ __forceinline__ void bp_mma(const BpOps& o, const float2* cs, int s0, int lg, int part,
+                                       f4_t* sr, f4_t* si) {
+#pragma unroll
+  for (int q = 0; q < kSepSteps; ++q) {
+    const float2 c = cs[2 * (s0 + q) + (lg >> 1)];
+    const float br = c.x * o.ga[q].x - c.y * o.ga[q].y, bi = c.x * o.ga[q].y + c.y * o.ga[q].x;
+    const float ar = part ? -bi : br, ai = part ? br : bi;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      sr[t] = mfma4(ar, o.fc[q][t], sr[t]);
+      si[t] = mfma4(ai, o.fc[q][t], si[t]);
+    }
+  }
+}
+
+// T = U conj(F)^T for R 16-spot blocks starting at sb0 and the wave's 16
+// rows, then the tile's partial V_n = sum_j conj(G_n(j)) T[j][n] of those
+// spots, added into the exact sums of group g.  Every thread of the block
+// calls this with the same sb0 and R.
+template <int R>
+__device__ void sep_forward(const JobDev& jb, const float2 (*us)[kSepTile + 1],
+                            float2 (*red)[64], int sb0, int rb, int col0, int S16, int CP, int lane,
+                            int wave, int shift, int g) {
+  const int lr = lane & 15, lg = lane >> 4, part = lg & 1;
+  f4_t tr[R], ti[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) tr[k] = ti[k] = f4_t{0.f, 0.f, 0.f, 0.f};
+  float fa[kSepCols][R], fb[kSepCols][R];
+  auto load = [&](float (*fn)[R], int c0) {
+#pragma unroll
+    for (int q = 0; q < kSepCols; ++q)
+#pragma unroll
+      for (int k = 0; k < R; ++k)
+        fn[q][k] = as_global(jb.sepFn)[op_index(sb0 + k, col0 / 2 + c0 + q, CP, lane)];
+  };
+  auto mma = [&](const float (*fn)[R], int c0) {
+#pragma unroll
+    for (int q = 0; q < kSepCols; ++q) {
+      const float2 u = us[lr][2 * (c0 + q) + (lg >> 1)];
+      const float ar = part ? u.y : u.x, ai = part ? -u.x : u.y;  // parts of u and of -i u
+#pragma unroll
+      for (int k = 0; k < R; ++k) {
+        tr[k] = mfma4(ar, fn[q][k], tr[k]);
+        ti[k] = mfma4(ai, fn[q][k], ti[k]);
+      }
+    }
+  };
+  static_assert(kSepTile / 2 == 4 * kSepCols, "four column groups per tile");
+  load(fa, 0);
+  load(fb, kSepCols);
+  mma(fa, 0);
+  load(fa, 2 * kSepCols);
+  mma(fb, kSepCols);
+  load(fb, 3 * kSepCols);
+  mma(fa, 2 * kSepCols);
+  mma(fb, 3 * kSepCols);
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int64_t gv = op_index(rb, sb0 + k, S16, lane) * 2;
+    const f4_t g01 = as_global(reinterpret_cast<const f4_t*>(jb.sepGv))[gv];
+    const f4_t g23 = as_global(reinterpret_cast<const f4_t*>(jb.sepGv))[gv + 1];
+    const float gr[4] = {g01[0], g01[2], g23[0], g23[2]};
+    const float gi[4] = {g01[1], g01[3], g23[1], g23[3]};
+    float vr = 0.f, vi = 0.f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      vr = fmaf(gr[r], tr[k][r], fmaf(gi[r], ti[k][r], vr));
+      vi = fmaf(gr[r], ti[k][r], fmaf(-gi[r], tr[k][r], vi));
+    }
+    vr += __shfl_xor(vr, 16);
+    vi += __shfl_xor(vi, 16);
+    vr += __shfl_xor(vr, 32);
+    vi += __shfl_xor(vi, 32);
+    if (lg == 0) red[wave][16 * k + lr] = make_float2(vr, vi);
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < 16 * R) {
+    const int n = 16 * sb0 + threadIdx.x;
+    if (n < jb.N) {
+      float2 v = red[0][threadIdx.x];
+#pragma unroll
+      for (int w = 1; w < kWaves; ++w) {
+        v.x += red[w][threadIdx.x].x;
+        v.y += red[w][threadIdx.x].y;
+      }
+      acc_add(jb.acc, jb.N, shift, 1 + g, n, v);
+    }
+  }
+  __syncthreads();
+}
+
 template <bool FINAL>
 __global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ jobs,
                                                      const SepDesc* __restrict__ descs,
@@ -135,33 +243,22 @@ __global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ 
   }
   __syncthreads();
 
-  // S = B F.  A operand: part of conj(B) (real output) or of i conj(B)
-  // (imaginary output); B_n(row) = C_n G_n(row) formed here in FP32.
+  // S = B F, K = 2 Np in groups of kSepSteps steps (KS = 8 S16 is a
+  // multiple of kSepSteps), the next group's operands loaded ahead.
   f4_t sr[4], si[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) sr[t] = si[t] = f4_t{0.f, 0.f, 0.f, 0.f};
-  for (int s0 = 0; s0 < KS; s0 += kSepSteps) {
-    float2 ga[kSepSteps];
-    float fc[kSepSteps][4];
-#pragma unroll
-    for (int q = 0; q < kSepSteps; ++q) {
-      const int s = min(s0 + q, KS - 1);  // a repeated step is loaded, not used
-      const HG_GLOBAL float* gp =
-          as_global(reinterpret_cast<const float*>(jb.sepGa + op_index(rb, s, KS, lane)));
-      ga[q] = make_float2(gp[0], gp[1]);
-#pragma unroll
-      for (int t = 0; t < 4; ++t) fc[q][t] = as_global(jb.sepFc)[op_index(4 * tx + t, s, KS, lane)];
-    }
-#pragma unroll
-    for (int q = 0; q < kSepSteps; ++q) {
-      if (s0 + q >= KS) break;
-      const float2 c = cs[2 * (s0 + q) + (lg >> 1)];
-      const float br = c.x * ga[q].x - c.y * ga[q].y, bi = c.x * ga[q].y + c.y * ga[q].x;
-      const float ar = part ? -bi : br, ai = part ? br : bi;
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        sr[t] = mfma4(ar, fc[q][t], sr[t]);
-        si[t] = mfma4(ai, fc[q][t], si[t]);
+  {
+    static_assert(kSepSteps == 8, "K-step groups of 8: KS = 8 S16");
+    const int G = KS / kSepSteps;
+    BpOps P, Q;
+    bp_load(P, jb, rb, tx, 0, KS, lane);
+    for (int gi = 0; gi < G; gi += 2) {
+      if (gi + 1 < G) bp_load(Q, jb, rb, tx, (gi + 1) * kSepSteps, KS, lane);
+      bp_mma(P, cs, gi * kSepSteps, lg, part, sr, si);
+      if (gi + 1 < G) {
+        if (gi + 2 < G) bp_load(P, jb, rb, tx, (gi + 2) * kSepSteps, KS, lane);
+        bp_mma(Q, cs, (gi + 1) * kSepSteps, lg, part, sr, si);
       }
     }
   }
@@ -197,70 +294,23 @@ __global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ 
     }
   __syncthreads();
 
-  // T = U conj(F)^T for the wave's 16 rows, 64 spots per chunk; the tile's
-  // partial V_n = sum_j conj(G_n(j)) T[j][n] joins its group's exact sums.
+  // T and the partial V in groups of four 16-spot blocks, then the rest.
   const int g = lb / d.plan.group_size;
-  for (int sb0 = 0; sb0 < S16; sb0 += 4) {
-    f4_t tr[4], ti[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) tr[k] = ti[k] = f4_t{0.f, 0.f, 0.f, 0.f};
-    for (int c0 = 0; c0 < kSepTile / 2; c0 += kSepCols) {
-      float fn[kSepCols][4];
-#pragma unroll
-      for (int q = 0; q < kSepCols; ++q)
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-          fn[q][k] = sb0 + k < S16
-                         ? as_global(jb.sepFn)[op_index(sb0 + k, col0 / 2 + c0 + q, CP, lane)]
-                         : 0.f;
-#pragma unroll
-      for (int q = 0; q < kSepCols; ++q) {
-        const float2 u = us[wave][lr][2 * (c0 + q) + (lg >> 1)];
-        const float ar = part ? u.y : u.x, ai = part ? -u.x : u.y;  // parts of u and of -i u
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          if (sb0 + k < S16) {
-            tr[k] = mfma4(ar, fn[q][k], tr[k]);
-            ti[k] = mfma4(ai, fn[q][k], ti[k]);
-          }
-        }
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      float vr = 0.f, vi = 0.f;
-      if (sb0 + k < S16) {
-        const int64_t gv = op_index(rb, sb0 + k, S16, lane) * 2;
-        const f4_t g01 = as_global(reinterpret_cast<const f4_t*>(jb.sepGv))[gv];
-        const f4_t g23 = as_global(reinterpret_cast<const f4_t*>(jb.sepGv))[gv + 1];
-        const float gr[4] = {g01[0], g01[2], g23[0], g23[2]};
-        const float gi[4] = {g01[1], g01[3], g23[1], g23[3]};
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          vr = fmaf(gr[r], tr[k][r], fmaf(gi[r], ti[k][r], vr));
-          vi = fmaf(gr[r], ti[k][r], fmaf(-gi[r], tr[k][r], vi));
-        }
-      }
-      vr += __shfl_xor(vr, 16);
-      vi += __shfl_xor(vi, 16);
-      vr += __shfl_xor(vr, 32);
-      vi += __shfl_xor(vi, 32);
-      if (lg == 0) red[wave][16 * k + lr] = make_float2(vr, vi);
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-      const int n = 16 * sb0 + threadIdx.x;
-      if (n < N) {
-        float2 v = red[0][threadIdx.x];
-#pragma unroll
-        for (int w = 1; w < kWaves; ++w) {
-          v.x += red[w][threadIdx.x].x;
-          v.y += red[w][threadIdx.x].y;
-        }
-        acc_add(jb.acc, N, d.plan.shift, 1 + g, n, v);
-      }
-    }
-    __syncthreads();
+  int sb0 = 0;
+  for (; sb0 + 4 <= S16; sb0 += 4)
+    sep_forward<4>(jb, us[wave], red, sb0, rb, col0, S16, CP, lane, wave, d.plan.shift, g);
+  switch (S16 - sb0) {
+    case 3:
+      sep_forward<3>(jb, us[wave], red, sb0, rb, col0, S16, CP, lane, wave, d.plan.shift, g);
+      break;
+    case 2:
+      sep_forward<2>(jb, us[wave], red, sb0, rb, col0, S16, CP, lane, wave, d.plan.shift, g);
+      break;
+    case 1:
+      sep_forward<1>(jb, us[wave], red, sb0, rb, col0, S16, CP, lane, wave, d.plan.shift, g);
+      break;
+    default:
+      break;
   }
 
   PassCtx a;
