@@ -119,11 +119,18 @@ typedef struct hg_spots {
  * one per propagation direction; 1 = one complex exponential per pair, kept
  * in registers between the directions (jobs with N <= 100; others use 0).
  * The form changes the rounding of the sums (both stay within the same
- * accuracy bars).  Chosen per shape by the package's autotuner. */
+ * accuracy bars).
+ * chain_passes: 1 = the compressed passes of a single FP32 hologram
+ * (hg_cswgs, hg_cswgs_ex; two-sincos form, N <= 256) run in one cooperative
+ * launch, each pass handing the updated spot state to the next through
+ * device memory, when all its blocks fit on the device at once; 0 = one
+ * launch per pass.  Both give bit-identical results.
+ * Chosen per shape by the package's autotuner. */
 typedef struct hg_tune {
   int32_t full_block_cap;
   int32_t subset_block_cap;
   int32_t pass_form;
+  int32_t chain_passes;
 } hg_tune;
 
 typedef struct hg_params {

@@ -72,7 +72,7 @@ class _Job(ctypes.Structure):
 
 class _Tune(ctypes.Structure):
     _fields_ = [("full_block_cap", ctypes.c_int32), ("subset_block_cap", ctypes.c_int32),
-                ("pass_form", ctypes.c_int32)]
+                ("pass_form", ctypes.c_int32), ("chain_passes", ctypes.c_int32)]
 
 
 class _EngineConfig(ctypes.Structure):
@@ -269,7 +269,7 @@ def cswgs(grid, optics, spots, iterations: int, compression: float, seed: int, p
         return phi
     tr = np.zeros((max(int(iterations), 1), sa.n, 2)) if trace else None
     params = _Params(int(iterations), float(compression), int(seed), flags,
-                     tr.ctypes.data_as(_DP) if trace else None, _tune(tune) or _Tune(0, 0, 0))
+                     tr.ctypes.data_as(_DP) if trace else None, _tune(tune) or _Tune(0, 0, 0, 0))
     _check(lib.hg_cswgs_ex(_grid(grid), _optics(optics), sa.struct, ctypes.byref(params),
                            _dev_f32(phi, grid.W * grid.H, "phi"), _stream(stream)))
     if trace:
@@ -374,7 +374,7 @@ def cswgs_device(grid, optics, spots_dev, iterations: int, compression: float, s
     sp = _Spots(n, *ptrs)
     phi = _new_phi(grid) if phi is None else phi
     params = _Params(int(iterations), float(compression), int(seed),
-                     _flags(precision) | SPOTS_ON_DEVICE, None, _tune(tune) or _Tune(0, 0, 0))
+                     _flags(precision) | SPOTS_ON_DEVICE, None, _tune(tune) or _Tune(0, 0, 0, 0))
     _check(lib.hg_cswgs_ex(_grid(grid), _optics(optics), sp, ctypes.byref(params),
                            _dev_f32(phi, grid.W * grid.H, "phi"), _stream(stream)))
     return phi
@@ -439,7 +439,7 @@ def _tune(tune):
         return None
     if isinstance(tune, dict):
         return _Tune(int(tune.get("full_block_cap", 0)), int(tune.get("subset_block_cap", 0)),
-                     int(tune.get("pass_form", 0)))
+                     int(tune.get("pass_form", 0)), int(tune.get("chain_passes", 0)))
     return _Tune(*(int(v) for v in tune))
 
 
@@ -491,7 +491,7 @@ class Engine:
 
     def __init__(self, mem_budget_bytes: int, max_slots: int = 64, tune=None):
         lib = load()
-        t = _tune(tune) or _Tune(0, 0, 0)
+        t = _tune(tune) or _Tune(0, 0, 0, 0)
         cfg = _EngineConfig(int(mem_budget_bytes), int(max_slots), t)
         h = ctypes.c_void_p()
         _check(lib.hg_engine_create(ctypes.byref(cfg), ctypes.byref(h)))

@@ -2,8 +2,9 @@
 
 A pass runs on min(tiles, cap) blocks that take its tiles of pixels
 dynamically; the caps of the compressed and of the full-grid per-pixel
-passes, and the form of the compressed pass (two sincos per pixel-spot
-pair, or one shared complex exponential), are the tunable parameters.
+passes, the form of the compressed pass (two sincos per pixel-spot pair, or
+one shared complex exponential) and, for one hologram at a time, whether
+its compressed passes run chained in one launch are the tunable parameters.
 Partial sums are kept per tile, so the caps never change the results; the
 form changes the rounding only.
 
@@ -26,6 +27,7 @@ from typing import Dict, Iterable, List, Optional
 SUBSET_CAPS = (256, 512, 768, 1024, 1536, 2048, 4096)
 FULL_CAPS = (1024, 2048, 4096)
 PASS_FORMS = (0, 1)
+LAUNCHES = (0, 1)  # chain_passes: chained compressed passes (single hologram) or not
 
 
 def _hg():
@@ -60,9 +62,11 @@ def _time(run, reps: int, stream) -> float:
 
 
 def _candidates(subset_caps: Iterable[int], full_caps: Iterable[int],
-                forms: Iterable[int] = PASS_FORMS) -> List[Dict[str, int]]:
-    return [{"full_block_cap": int(f), "subset_block_cap": int(s), "pass_form": int(p)}
-            for p in forms for f in full_caps for s in subset_caps]
+                forms: Iterable[int] = PASS_FORMS,
+                launches: Iterable[int] = (0,)) -> List[Dict[str, int]]:
+    return [{"full_block_cap": int(f), "subset_block_cap": int(s), "pass_form": int(p),
+             "chain_passes": int(q)}
+            for q in launches for p in forms for f in full_caps for s in subset_caps]
 
 
 def _best(sweep: Dict[str, float], cands: List[Dict[str, int]]) -> dict:
@@ -74,12 +78,13 @@ def _best(sweep: Dict[str, float], cands: List[Dict[str, int]]) -> dict:
 
 
 def _label(c: Dict[str, int]) -> str:
-    return f"full={c['full_block_cap']},subset={c['subset_block_cap']},form={c['pass_form']}"
+    return (f"full={c['full_block_cap']},subset={c['subset_block_cap']},form={c['pass_form']},"
+            f"chain={c.get('chain_passes', 0)}")
 
 
 def tune_single(grid, optics, spots, iterations: int, compression: float, seed: int = 0,
                 precision: str = "fp32", reps: int = 5, subset_caps=SUBSET_CAPS,
-                full_caps=(0,), forms=PASS_FORMS, stream=None) -> dict:
+                full_caps=(0,), forms=PASS_FORMS, launches=LAUNCHES, stream=None) -> dict:
     """Fastest geometry for one hologram at a time of this shape."""
     import numpy as np
     import torch
@@ -89,7 +94,7 @@ def tune_single(grid, optics, spots, iterations: int, compression: float, seed: 
                                  np.asarray(spots.z_mm), np.asarray(spots.amp)]),
                        dtype=torch.float64, device="cuda")
     phi = torch.empty(grid.W * grid.H, dtype=torch.float32, device="cuda")
-    cands = _candidates(subset_caps, full_caps, forms)
+    cands = _candidates(subset_caps, full_caps, forms, launches)
     sweep = {}
     for c in cands:
         sweep[_label(c)] = _time(lambda: hg.cswgs_device(
@@ -137,7 +142,8 @@ class Table:
     def as_tune(entry: dict) -> Dict[str, int]:
         return {"full_block_cap": int(entry["full_block_cap"]),
                 "subset_block_cap": int(entry["subset_block_cap"]),
-                "pass_form": int(entry.get("pass_form", 0))}
+                "pass_form": int(entry.get("pass_form", 0)),
+                "chain_passes": int(entry.get("chain_passes", 0))}
 
     def single(self, grid, optics, spots, iterations: int, compression: float,
                precision: str = "fp32", **kw) -> Dict[str, int]:

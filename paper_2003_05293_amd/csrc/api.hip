@@ -110,6 +110,7 @@ hg::TuneParams tune_params(const hg_tune* t) {
   if (t && t->full_block_cap > 0) tp.full_block_cap = t->full_block_cap;
   if (t && t->subset_block_cap > 0) tp.subset_block_cap = t->subset_block_cap;
   if (t) tp.pass_form = t->pass_form;
+  if (t) tp.chain_passes = t->chain_passes != 0;
   return tp;
 }
 
@@ -124,7 +125,7 @@ hg_status run_one(const hg_grid* g, const hg_optics* o, const hg_spots* s, int32
   HG_TRY(get_workspace(stream, &ws));
   std::lock_guard<std::mutex> lk(ws->mu);
   HG_TRY(ws->init_status());
-  HG_TRY(ws->batch.build(&spec, 1, tp, ws->status.p));
+  HG_TRY(ws->batch.build(&spec, 1, tp, ws->status.p, /*allow_chain=*/true));
   HG_TRY(ws->batch.enqueue(ws->stream));
   if (trace_host) {
     HG_TRY(ws->batch.fetch_traces(ws->stream));
@@ -222,8 +223,8 @@ hg_status job_specs(int32_t count, const hg_job* jobs, const hg_tune* tune,
                     std::vector<hg::JobSpec>* out) {
   if (count < 1 || !jobs) return set_error(HG_EINVAL, "count must be >= 1 and jobs non-NULL");
   if (tune && (tune->full_block_cap < 0 || tune->subset_block_cap < 0 || tune->pass_form < 0 ||
-               tune->pass_form > 1))
-    return set_error(HG_EINVAL, "tune caps must be >= 0 and pass_form 0 or 1");
+               tune->pass_form > 1 || tune->chain_passes < 0 || tune->chain_passes > 1))
+    return set_error(HG_EINVAL, "tune caps must be >= 0, pass_form and chain_passes 0 or 1");
   out->resize(count);
   for (int32_t i = 0; i < count; ++i) {
     const hg_job& j = jobs[i];
@@ -281,8 +282,9 @@ hg_status hg_cswgs_ex(const hg_grid* grid, const hg_optics* optics, const hg_spo
   HG_TRY(check_compression(params->compression));
   HG_TRY(validate_flags(params->flags, HG_SPOTS_ON_DEVICE | HG_FULL_DIRECT));
   if (params->tune.full_block_cap < 0 || params->tune.subset_block_cap < 0 ||
-      params->tune.pass_form < 0 || params->tune.pass_form > 1)
-    return set_error(HG_EINVAL, "tune caps must be >= 0 and pass_form 0 or 1");
+      params->tune.pass_form < 0 || params->tune.pass_form > 1 ||
+      params->tune.chain_passes < 0 || params->tune.chain_passes > 1)
+    return set_error(HG_EINVAL, "tune caps must be >= 0, pass_form and chain_passes 0 or 1");
   return run_one(grid, optics, spots, params->iterations, params->compression, params->seed,
                  params->flags, phi_dev, params->trace_V, stream, tune_params(&params->tune));
 }

@@ -156,8 +156,9 @@ hg_status hg_engine_create(const hg_engine_config* cfg, hg_engine** out) {
   if (cfg->mem_budget_bytes < (size_t)(1 << 20))
     return set_error(HG_EINVAL, "mem_budget_bytes must be at least 1 MiB");
   if (cfg->tune.full_block_cap < 0 || cfg->tune.subset_block_cap < 0 ||
-      cfg->tune.pass_form < 0 || cfg->tune.pass_form > 1)
-    return set_error(HG_EINVAL, "tune caps must be >= 0 and pass_form 0 or 1");
+      cfg->tune.pass_form < 0 || cfg->tune.pass_form > 1 ||
+      cfg->tune.chain_passes < 0 || cfg->tune.chain_passes > 1)
+    return set_error(HG_EINVAL, "tune caps must be >= 0, pass_form and chain_passes 0 or 1");
   auto e = std::make_unique<hg_engine>();
   HG_HIP(hipGetDevice(&e->device));
   e->budget = cfg->mem_budget_bytes;

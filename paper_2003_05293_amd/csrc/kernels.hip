@@ -85,6 +85,41 @@ __device__ __forceinline__ float2 backprop_field(const SpotRec* spg, int n0, int
   return make_float2(sr, si);
 }
 
+// The same sum with the spot records in LDS (chained launches, where the
+// records change between passes of one launch): the four records of a group
+// are read together (every lane the same address: broadcast reads).
+__device__ __forceinline__ float2 backprop_field_lds(const SpotRec* recs, int n0, int n1,
+                                                     const PixCoord& c) {
+  float sr = 0.f, si = 0.f;
+  int n = n0;
+  for (; n + 3 < n1; n += 4) {
+    float4 q[4];
+    float sA[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      q[k] = *reinterpret_cast<const float4*>(&recs[n + k].cx);
+      sA[k] = recs[n + k].A;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float t = fmaf(q[k].x, c.Lx, fmaf(q[k].y, c.Ly, fmaf(q[k].z, c.Q, q[k].w)));
+      float sn, cs;
+      sincos_turns(t, sn, cs);
+      sr = fmaf(sA[k], cs, sr);
+      si = fmaf(sA[k], sn, si);
+    }
+  }
+  for (; n < n1; ++n) {
+    const float t =
+        fmaf(recs[n].cx, c.Lx, fmaf(recs[n].cy, c.Ly, fmaf(recs[n].cz, c.Q, recs[n].th)));
+    float sn, cs;
+    sincos_turns(t, sn, cs);
+    sr = fmaf(recs[n].A, cs, sr);
+    si = fmaf(recs[n].A, sn, si);
+  }
+  return make_float2(sr, si);
+}
+
 // ---------------------------------------------------------------- setup ---
 
 // Spot coefficients in FP64, rounded once to FP32; theta^0 from Philox;
@@ -133,9 +168,15 @@ __global__ __launch_bounds__(256) void k_setup_batch(const JobDev* __restrict__ 
 // pi(k) for every k < M of each compressed job (and, for mixed-precision
 // jobs, the inverse: the rank of every pixel in the order).  With LDS, the Feistel
 // tables (h <= 11: 48 KB) are staged in LDS; otherwise read from memory.
+//
+// The cycle walks have geometric lengths (mean 4^h / M), so a wave that gave
+// each lane a fixed set of k would run for its longest walk.  Instead each
+// wave takes a chunk of kPermChunk consecutive k and keeps its lanes busy:
+// a lane whose walk has ended takes the next k of the chunk.
 constexpr int kPermThreads = 512;
 constexpr int kPermLdsHalfBits = 11;
-constexpr int kPermPerThread = 4;
+constexpr int kPermChunk = 256;  // k per wave
+constexpr int kPermPerThread = kPermChunk / 64;
 
 template <bool LDS>
 __global__ __launch_bounds__(kPermThreads) void k_perm_batch(const JobDev* __restrict__ jobs,
@@ -145,7 +186,6 @@ __global__ __launch_bounds__(kPermThreads) void k_perm_batch(const JobDev* __res
   const int si = find_desc(slices, nslices, blockIdx.x);
   const JobDev& jb = jobs[slices[si].job];
   const int lb = blockIdx.x - slices[si].block_begin;
-  const int nb = ceil_div(jb.M, (int64_t)kPermThreads * kPermPerThread);
   const uint32_t* tab = jb.tab;
   if (LDS) {
     const int total = kFeistelRounds << jb.h;
@@ -153,34 +193,37 @@ __global__ __launch_bounds__(kPermThreads) void k_perm_batch(const JobDev* __res
     __syncthreads();
     tab = tab_s;
   }
-  // The kPermPerThread walks of a thread advance in lock step, so that their
-  // table reads overlap instead of forming one long dependent chain.
   const uint32_t M = (uint32_t)jb.M;
-  const int64_t k0 = (int64_t)lb * kPermThreads + threadIdx.x, dk = (int64_t)nb * kPermThreads;
-  uint32_t y[kPermPerThread];
-#pragma unroll
-  for (int i = 0; i < kPermPerThread; ++i) {
-    const int64_t k = k0 + i * dk;
-    y[i] = k < M ? feistel((uint32_t)k, tab, jb.h) : 0u;  // 0: nothing to walk
-  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint32_t c0 = ((uint32_t)lb * (kPermThreads / 64) + wave) * kPermChunk;
+  if (c0 >= M) return;  // whole wave
+  const uint32_t c1 = min(c0 + (uint32_t)kPermChunk, M);
+  // lane state: the k being walked and the latest point y of its walk
+  uint32_t k = c0 + lane, y = k;
+  bool active = k < c1;
+  uint32_t next = c0 + 64;  // next k of the chunk to hand out (uniform)
   const uint32_t cap = 1u << (2 * jb.h < 32 ? 2 * jb.h : 31);
-  for (uint32_t step = 0; step < cap; ++step) {
-    bool more = false;
-#pragma unroll
-    for (int i = 0; i < kPermPerThread; ++i) more |= y[i] >= M;
-    if (!more) break;
-#pragma unroll
-    for (int i = 0; i < kPermPerThread; ++i) {
-      const uint32_t z = feistel(y[i], tab, jb.h);
-      y[i] = y[i] >= M ? z : y[i];
+  uint32_t steps = 0;
+  while (__ballot(active) != 0ull) {
+    y = feistel(y, tab, jb.h);
+    ++steps;
+    // the cycle of k contains k < M, so every walk ends within 4^h steps
+    if (active && (y < M || steps >= cap)) {
+      jb.perm[k] = (int32_t)y;
+      if (jb.rank) jb.rank[y] = k;  // pixel y is the k-th of the random order
+      active = false;
     }
-  }
-#pragma unroll
-  for (int i = 0; i < kPermPerThread; ++i) {
-    const int64_t k = k0 + i * dk;
-    if (k >= M) continue;
-    jb.perm[k] = (int32_t)y[i];
-    if (jb.rank) jb.rank[y[i]] = (uint32_t)k;  // pixel y is the k-th of the random order
+    const uint64_t idle = __ballot(!active);
+    const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(idle >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)idle, 0u));
+    if (!active && next + r < c1) {
+      k = next + r;
+      y = k;
+      steps = 0;
+      active = true;
+    }
+    next += (uint32_t)__popcll(idle);
+    if (next > c1) next = c1;
   }
 }
 
@@ -269,7 +312,9 @@ __host__ __device__ inline LaneMap lane_map(int N) {
   return m;
 }
 
-template <int MAXU>
+// CHAIN: the spot records come from LDS (a.recs) and the block that
+// completes the pass publishes the generation word after the update.
+template <int MAXU, bool CHAIN = false>
 __device__ void pass_block(const PassCtx& a, unsigned* grab) {
   __shared__ float2 sw[kWaves][kTile];
   __shared__ float4 px[kTile];
@@ -294,10 +339,16 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab) {
     const int n = (u / lm.S) * lm.Lg + g;
     cx[k] = cy[k] = cz[k] = 0.f;
     if (u < lm.U && n < N) {
-      const HG_GLOBAL SpotRec* rec = as_global(sp + n);
-      cx[k] = rec->cx;
-      cy[k] = rec->cy;
-      cz[k] = rec->cz;
+      if (CHAIN) {
+        cx[k] = a.recs[n].cx;
+        cy[k] = a.recs[n].cy;
+        cz[k] = a.recs[n].cz;
+      } else {
+        const HG_GLOBAL SpotRec* rec = as_global(sp + n);
+        cx[k] = rec->cx;
+        cy[k] = rec->cy;
+        cz[k] = rec->cz;
+      }
     }
   }
   const int n_lo = (wave * N) / kWaves, n_hi = ((wave + 1) * N) / kWaves;
@@ -337,7 +388,8 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab) {
           ticket = atomicAdd(grab, p >= 0 ? 1u : 1u);
         PixCoord c{0.f, 0.f, 0.f};
         if (valid) c = pixel_coord(p, a.W, a.H);
-        sw[wave][lane] = backprop_field(sp, n_lo, n_hi, c);
+        sw[wave][lane] = CHAIN ? backprop_field_lds(a.recs, n_lo, n_hi, c)
+                               : backprop_field(sp, n_lo, n_hi, c);
         __syncthreads();
         if (wave == 0) {
           float4 rec = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -429,7 +481,10 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab) {
   }
   count_tiles(a, done, ndone, owned, &nowned);
   for (int i = 0; i < nowned; ++i)
-    if (tail_group(a, owned[i], &flag)) tail_final(a, wsum);
+    if (tail_group(a, owned[i], &flag)) {
+      tail_final(a, wsum);
+      if (CHAIN) publish_gen(a);
+    }
 }
 
 }  // namespace
@@ -609,6 +664,61 @@ __global__ __launch_bounds__(kBlock, MAXU > 4 ? 2 : (MAXE > 16 ? 6 : 8)) void k_
     }
   }
   pass_block<MAXU>(a, jb.grab + d.grab_slot);
+}
+
+// Compressed passes descs[0..npass) of one job in one cooperative launch;
+// every pass has the same grid.  See kernels.hpp (chained compressed passes).
+constexpr int kChainSpinLimit = 1 << 20;  // polls of one wait (about a second)
+template <int MAXU>
+__global__ __launch_bounds__(kBlock, MAXU > 4 ? 2 : 6) void k_pass_chain(
+    const JobDev* __restrict__ jobs, const PassDesc* __restrict__ descs, int npass) {
+  __shared__ SpotRec recs[kChainMaxSpots];
+  __shared__ int stop;
+  const JobDev& jb = jobs[descs[0].job];
+  for (int p = 0; p < npass; ++p) {
+    __syncthreads();  // the previous pass's use of LDS is over
+    if (p > 0) {
+      if (threadIdx.x == 0) {
+        const unsigned* g = jb.gen + (blockIdx.x % kGenCopies) * kCounterStride;
+        int spins = 0;
+        while (__hip_atomic_load(g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)p &&
+               ++spins < kChainSpinLimit)
+          __builtin_amdgcn_s_sleep(2);
+        stop = spins >= kChainSpinLimit;
+        if (stop) jb.status[0] = 5;  // HG_EDEVICE: the previous pass did not complete
+      }
+      __syncthreads();
+      if (stop) return;
+    }
+    // the spot state of this pass (written by the previous pass's update)
+    load_recs_dev(jb.sp, jb.N, recs);
+    __syncthreads();
+    const PassDesc& d = descs[p];
+    PassCtx a;
+    a.sp = jb.sp;
+    a.coef = jb.coef;
+    a.N = jb.N;
+    a.W = jb.W;
+    a.H = jb.H;
+    a.ps = d.ps;
+    a.phi = jb.phi;
+    a.plan = d.plan;
+    a.lb = blockIdx.x;
+    a.partial = jb.partial;
+    a.gpart = jb.gpart;
+    a.acc = jb.acc;
+    a.counters = jb.counters;
+    a.inv_count = d.inv_count;
+    a.V = d.V;
+    a.status = jb.status;
+    a.update = d.update;
+    a.from_phi = 0;
+    a.chain = 1;
+    a.recs = recs;
+    a.gen = jb.gen;
+    a.gen_next = (unsigned)(p + 1);
+    pass_block<MAXU, true>(a, jb.grab + d.grab_slot);
+  }
 }
 
 // Final hologram on a pixel set: Phi = atan2(Im S, Re S), written to out[q].
@@ -799,6 +909,44 @@ void launch_pass_batch(const JobDev* jobs, const PassDesc* descs, int ndesc, int
   if (max_units <= 1) launch_pass_u<1>(jobs, descs, ndesc, total_blocks, e_width, s);
   else if (max_units <= 4) launch_pass_u<4>(jobs, descs, ndesc, total_blocks, e_width, s);
   else launch_pass_u<16>(jobs, descs, ndesc, total_blocks, e_width, s);
+}
+
+namespace {
+template <int MAXU>
+int chain_capacity_u() {
+  static int cached = -1;  // per process: the device is the same for every call
+  if (cached < 0) {
+    int dev = 0, per_cu = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pass_chain<MAXU>, kBlock, 0) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return 0;
+    cached = per_cu * cus;
+  }
+  return cached;
+}
+template <int MAXU>
+hipError_t launch_chain_u(const JobDev* jobs, const PassDesc* descs, int npass, int blocks,
+                          hipStream_t s) {
+  void* args[] = {(void*)&jobs, (void*)&descs, (void*)&npass};
+  return hipLaunchCooperativeKernel((const void*)k_pass_chain<MAXU>, dim3(blocks), dim3(kBlock),
+                                    args, 0, s);
+}
+}  // namespace
+
+int pass_chain_capacity(int max_units) {
+  if (max_units <= 1) return chain_capacity_u<1>();
+  if (max_units <= 4) return chain_capacity_u<4>();
+  return chain_capacity_u<16>();
+}
+
+hipError_t launch_pass_chain(const JobDev* jobs, const PassDesc* descs, int npass, int blocks,
+                             int max_units, hipStream_t s) {
+  if (npass <= 0 || blocks <= 0) return hipSuccess;
+  if (max_units <= 1) return launch_chain_u<1>(jobs, descs, npass, blocks, s);
+  if (max_units <= 4) return launch_chain_u<4>(jobs, descs, npass, blocks, s);
+  return launch_chain_u<16>(jobs, descs, npass, blocks, s);
 }
 
 int backprop_blocks(int32_t count) { return ceil_div(count, kBlock); }

@@ -51,6 +51,9 @@ struct PassPlan {
   int32_t shift;       // fixed-point scale 2^shift of the exact sums (|sum| <= pixels)
 };
 constexpr int32_t kMaxTiles = 8192;
+// Words per spot in the rows of exact sums: the atomic additions of
+// different spots go to different cache lines.
+constexpr int kAccSpotWords = 2;
 // Fixed-point scale of the exact sums of a pass over `pixels` pixels: every
 // term has magnitude <= 1, so |sum| * 2^shift <= 2^62.
 int sum_shift(int64_t pixels);
@@ -77,12 +80,14 @@ struct JobDev {
   float2* partial;     // [max pass tiles][N] (mixed-precision passes)
   double2* gpart;      // [max pass groups][N] (mixed-precision passes)
   // exact fixed-point sums of the FP32 passes: row 0 the pass total, row
-  // 1 + g group g; (re, im) two's-complement pairs per spot, zero between passes
-  unsigned long long* acc;  // [max pass groups + 1][N][2]
+  // 1 + g group g; per spot a (re, im) two's-complement pair at the start of
+  // an entry of kAccSpotWords words; zero between passes
+  unsigned long long* acc;  // [max pass groups + 1][N][kAccSpotWords]
   int64_t acc_len;
   unsigned* counters;  // [max pass groups + 1] group and pass counters, kCounterStride apart
   unsigned* grab;      // [iterations + 2] tile counters of the passes (PassDesc::grab_slot)
-  int32_t counters_len;  // counters and grab, zeroed by the setup
+  int32_t counters_len;  // counters, grab and gen, zeroed by the setup
+  unsigned* gen;       // [kGenCopies * kCounterStride] passes completed in a chained launch
   int32_t trace;       // V is [iterations][N] instead of [N]
   double2* V;
   int32_t* status;     // sticky status word of the caller's stream
@@ -171,6 +176,21 @@ void launch_pass_batch(const JobDev* jobs, const PassDesc* descs, int ndesc, int
 void launch_backprop_batch(const JobDev* jobs, const BackDesc* descs, int ndesc,
                            int total_blocks, hipStream_t s);
 int backprop_blocks(int32_t count);
+
+// ---- chained compressed passes ----
+// The compressed passes of one job in one cooperative launch (all blocks
+// resident): the block that completes pass p applies the update, writes the
+// spot state with device-scope stores and then sets the generation word to
+// p + 1 (in kGenCopies copies, one per 128-byte line, so that the waiting
+// blocks poll different lines); the others wait for it, then read the state
+// with device-scope loads into LDS.  Waits are bounded: a wait that runs out
+// sets the status word (HG_EDEVICE) and ends the launch.
+constexpr int kChainMaxSpots = 256;
+constexpr int kGenCopies = 16;
+// Largest grid of k_pass_chain<units> that is resident at once (0: none).
+int pass_chain_capacity(int max_units);
+hipError_t launch_pass_chain(const JobDev* jobs, const PassDesc* descs, int npass, int blocks,
+                             int max_units, hipStream_t s);
 
 // ---- separable full-grid passes ----
 // eq. (2) splits into a part in x' and a part in y': with doubled offsets,

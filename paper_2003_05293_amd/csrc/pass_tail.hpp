@@ -30,7 +30,29 @@ struct PassCtx {
   double2* V;
   int32_t* status;
   int update, from_phi;
+  // chained launches: the pass's spot state in LDS, and the generation word
+  // to publish after the update
+  int chain = 0;
+  const SpotRec* recs = nullptr;
+  unsigned* gen = nullptr;
+  unsigned gen_next = 0;
 };
+
+// Device-scope copies of a spot record (read by the other blocks of a
+// chained launch after the generation word says it is complete).
+__device__ __forceinline__ void store_rec_dev(SpotRec* p, const SpotRec& r) {
+  uint64_t w[4];
+  __builtin_memcpy(w, &r, sizeof(w));
+  HG_GLOBAL uint64_t* q = as_global_mut(reinterpret_cast<uint64_t*>(p));
+#pragma unroll
+  for (int i = 0; i < 4; ++i) __hip_atomic_store(q + i, w[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void load_recs_dev(const SpotRec* sp, int N, SpotRec* recs_lds) {
+  const HG_GLOBAL uint64_t* q = as_global(reinterpret_cast<const uint64_t*>(sp));
+  uint64_t* d = reinterpret_cast<uint64_t*>(recs_lds);
+  for (int k = threadIdx.x; k < 4 * N; k += kBlock)
+    d[k] = __hip_atomic_load(q + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Exact sums.  Each tile's per-spot partial is rounded once to a 64-bit
 // fixed-point integer (scale 2^shift, |sum over the pass| <= pixels, so no
@@ -40,7 +62,7 @@ struct PassCtx {
 __device__ __forceinline__ void acc_add(unsigned long long* acc, int N, int shift, int row, int n,
                                         float2 v) {
   const double scale = ldexp(1.0, shift);
-  unsigned long long* p = acc + ((int64_t)row * N + n) * 2;
+  unsigned long long* p = acc + ((int64_t)row * N + n) * kAccSpotWords;
   atomicAdd(p, (unsigned long long)llrint((double)v.x * scale));
   atomicAdd(p + 1, (unsigned long long)llrint((double)v.y * scale));
 }
@@ -56,8 +78,9 @@ __device__ __forceinline__ unsigned long long take_dev(unsigned long long* p) {
 // that completes the last group.
 __device__ bool tail_group(const PassCtx& a, int g, int* flag) {
   for (int k = threadIdx.x; k < 2 * a.N; k += kBlock) {
-    const unsigned long long v = take_dev(a.acc + (int64_t)(1 + g) * a.N * 2 + k);
-    atomicAdd(a.acc + k, v);
+    const int64_t e = (int64_t)(k >> 1) * kAccSpotWords + (k & 1);  // spot k / 2, part k % 2
+    const unsigned long long v = take_dev(a.acc + (int64_t)(1 + g) * a.N * kAccSpotWords + e);
+    atomicAdd(a.acc + e, v);
   }
   return arrive_last(&a.counters[a.plan.ngroups * kCounterStride], (unsigned)a.plan.ngroups, flag);
 }
@@ -70,14 +93,20 @@ __device__ void tail_final(const PassCtx& a, double* wsum) {
   const double inv = ldexp(1.0, -a.plan.shift) * a.inv_count;
   double magsum = 0.0;
   for (int n = threadIdx.x; n < N; n += kBlock) {
-    const long long re = (long long)take_dev(a.acc + 2 * n);
-    const long long im = (long long)take_dev(a.acc + 2 * n + 1);
+    const long long re = (long long)take_dev(a.acc + (int64_t)n * kAccSpotWords);
+    const long long im = (long long)take_dev(a.acc + (int64_t)n * kAccSpotWords + 1);
     const double2 t = make_double2((double)re * inv, (double)im * inv);
     a.V[n] = t;
     magsum += sqrt(t.x * t.x + t.y * t.y);
   }
-  // the counters are ready for the next pass (kernel end orders these writes)
-  for (int k = threadIdx.x; k <= a.plan.ngroups; k += kBlock) a.counters[k * kCounterStride] = 0u;
+  // the counters are ready for the next pass (kernel end orders these
+  // writes; in a chained launch, the generation word)
+  for (int k = threadIdx.x; k <= a.plan.ngroups; k += kBlock) {
+    if (a.chain)
+      __hip_atomic_store(a.counters + k * kCounterStride, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+      a.counters[k * kCounterStride] = 0u;
+  }
   if (!a.update) return;
   // sum of |V_n| in a fixed order: per thread, within each wave, then the waves
   for (int off = 32; off > 0; off >>= 1) magsum += __shfl_xor(magsum, off);
@@ -89,7 +118,7 @@ __device__ void tail_final(const PassCtx& a, double* wsum) {
   for (int n = threadIdx.x; n < N; n += kBlock) {
     const double2 v = a.V[n];  // written above by this same thread
     const double mag = sqrt(v.x * v.x + v.y * v.y);
-    SpotRec r = a.sp[n];
+    SpotRec r = a.chain ? a.recs[n] : a.sp[n];
     const double w = (double)r.w * (mean / mag);
     if (!(mag > 0.0) || !isfinite(w)) {
       a.status[0] = 4;  // HG_ENUMERIC
@@ -100,11 +129,22 @@ __device__ void tail_final(const PassCtx& a, double* wsum) {
     // theta is kept in FP32 turns: the FP32 arctangent of the FP64 sum
     // (rounded to FP32) is within a few FP32 ulps of the rounded FP64 one
     r.th = atan2f((float)v.y, (float)v.x) * 0.15915494309189535f;
-    a.sp[n] = r;
+    if (a.chain) store_rec_dev(a.sp + n, r);
+    else a.sp[n] = r;
     // C_n = A_n e^{i theta_n} = A_n V_n / |V_n|
     const double Am = w * (double)r.a0 / mag;
     a.coef[n] = make_float2((float)(Am * v.x), (float)(Am * v.y));
   }
+}
+
+// Chained launch: the update of this pass is complete (this block's state
+// stores first), so the next pass may start.
+__device__ void publish_gen(const PassCtx& a) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if ((int)threadIdx.x < kGenCopies)
+    __hip_atomic_store(a.gen + threadIdx.x * kCounterStride, a.gen_next, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Counts `count` tiles listed in done[] into their groups (the block's own

@@ -279,7 +279,9 @@ JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev
     max_groups = std::max(max_groups, L.plan_sep.ngroups);
   }
   L.grab_offset = (max_groups + 1) * kCounterStride;
-  j.counters_len = L.grab_offset + (s.iterations + 2);
+  L.gen_offset = (L.grab_offset + s.iterations + 2 + kCounterStride - 1) / kCounterStride *
+                 kCounterStride;
+  j.counters_len = L.gen_offset + kGenCopies * kCounterStride;
   size_t bytes = 0;
   auto take = [&](size_t n) {
     bytes = align_up(bytes, 256);
@@ -305,7 +307,7 @@ JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev
     L.off_partial = take(sizeof(float2) * (size_t)max_rows * s.N);
     L.off_gpart = take(sizeof(double2) * (size_t)max_groups * s.N);
   } else {        // exact fixed-point sums of the FP32 passes
-    j.acc_len = (int64_t)(max_groups + 1) * s.N * 2;
+    j.acc_len = (int64_t)(max_groups + 1) * s.N * kAccSpotWords;
     L.off_acc = take(sizeof(unsigned long long) * (size_t)j.acc_len);
   }
   L.off_counters = take(sizeof(unsigned) * (size_t)j.counters_len);
@@ -339,6 +341,7 @@ JobDev bind_job(const JobLayout& L, const JobSpec& s, char* base, const double* 
   j.acc = j.mixed ? nullptr : reinterpret_cast<unsigned long long*>(base + L.off_acc);
   j.counters = reinterpret_cast<unsigned*>(base + L.off_counters);
   j.grab = j.counters + L.grab_offset;
+  j.gen = j.counters + L.gen_offset;
   j.V = reinterpret_cast<double2*>(base + L.off_V);
   if (L.separable) {
     j.sepFc = reinterpret_cast<float*>(base + L.off_sepFc);
@@ -532,7 +535,7 @@ void LaunchSet::launch(const JobDev* jobs, hipStream_t s, bool capture) const {
 // ------------------------------------------------------------------- batch --
 
 hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
-                       int32_t* status_dev) {
+                       int32_t* status_dev, bool allow_chain) {
   specs_.assign(specs, specs + count);
   jobs_.assign(count, JobDev{});
   layouts_.resize(count);
@@ -592,8 +595,23 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
       septab_blocks_ += sep_table_blocks(j);
     }
   }
+  // chained launch of a single FP32 job's compressed passes
+  chain_descs_.clear();
+  chain_rounds_ = 0;
+  if (allow_chain && tp.chain_passes && count == 1) {
+    const JobDev& j = jobs_[0];
+    const int passes = j.iterations - 1;  // iterations 1..I-1 are compressed
+    const int units = pass_units_per_wave(j.N);
+    if (j.compressed && !j.mixed && !j.shared_e && j.N <= kChainMaxSpots && passes >= 2 &&
+        layouts_[0].plan_sub.blocks <= pass_chain_capacity(units)) {
+      for (int r = 0; r < passes; ++r) chain_descs_.push_back(rounds_[r].pass.at(0));
+      chain_rounds_ = passes;
+      chain_blocks_ = layouts_[0].plan_sub.blocks;
+      chain_units_ = units;
+    }
+  }
   // descriptor tables: [JobDev][JobSlice perm][JobSlice mx tables]
-  // [JobSlice sep tables][rounds...][final]
+  // [JobSlice sep tables][chain passes][rounds...][final]
   size_t tb = align_up(sizeof(JobDev) * count, 256);
   const size_t t_perm = tb;
   tb = align_up(tb + sizeof(JobSlice) * perm_.size(), 256);
@@ -601,6 +619,8 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
   tb = align_up(tb + sizeof(JobSlice) * mxtab_.size(), 256);
   const size_t t_septab = tb;
   tb = align_up(tb + sizeof(JobSlice) * septab_.size(), 256);
+  const size_t t_chain = tb;
+  tb = align_up(tb + sizeof(PassDesc) * chain_descs_.size(), 256);
   const size_t t_sets = tb;
   for (const LaunchSet& ls : rounds_) tb += ls.bytes();
   tb += final_.bytes();
@@ -615,6 +635,9 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
   mxtab_dev_ = reinterpret_cast<JobSlice*>(table_.p + t_mxtab);
   if (!mxtab_.empty())
     std::memcpy(staging_.p + t_mxtab, mxtab_.data(), sizeof(JobSlice) * mxtab_.size());
+  chain_dev_ = reinterpret_cast<PassDesc*>(table_.p + t_chain);
+  if (!chain_descs_.empty())
+    std::memcpy(staging_.p + t_chain, chain_descs_.data(), sizeof(PassDesc) * chain_descs_.size());
   septab_dev_ = reinterpret_cast<JobSlice*>(table_.p + t_septab);
   if (!septab_.empty())
     std::memcpy(staging_.p + t_septab, septab_.data(), sizeof(JobSlice) * septab_.size());
@@ -661,7 +684,16 @@ hg_status Batch::enqueue_prologue(hipStream_t s, bool capture) {
 
 hg_status Batch::enqueue(hipStream_t s, bool capture) {
   HG_TRY(enqueue_prologue(s, capture));
-  for (const LaunchSet& ls : rounds_) ls.launch(jobs_dev_, s, capture);
+  size_t r0 = 0;
+  if (chain_rounds_ > 0 && !capture) {
+    hipError_t ce = hipSuccess;
+    timed(s, "k_pass_chain", [&] {
+      ce = launch_pass_chain(jobs_dev_, chain_dev_, chain_rounds_, chain_blocks_, chain_units_, s);
+    });
+    if (ce == hipSuccess) r0 = (size_t)chain_rounds_;
+    else (void)hipGetLastError();  // not launched: one launch per pass instead
+  }
+  for (size_t r = r0; r < rounds_.size(); ++r) rounds_[r].launch(jobs_dev_, s, capture);
   final_.launch(jobs_dev_, s, capture);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess)
@@ -709,6 +741,7 @@ void Batch::release() {
   perm_dev_ = nullptr;
   mxtab_dev_ = nullptr;
   septab_dev_ = nullptr;
+  chain_dev_ = nullptr;
 }
 
 }  // namespace hg

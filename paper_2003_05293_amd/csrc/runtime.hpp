@@ -85,6 +85,7 @@ struct TuneParams {
   int32_t subset_block_cap = kDefaultBlockCap;
   bool separable_full = true;  // full-grid passes as separable products
   int32_t pass_form = 0;       // 1: shared-exponential compressed passes where N allows
+  bool chain_passes = false;   // chained launch of a single job's compressed passes
 };
 
 // Validation of the host-visible parts of a hologram description.
@@ -106,6 +107,7 @@ struct JobLayout {
   size_t bytes = 0;
   bool raw_inline = false;  // the job's own scratch holds a copy of its spot arrays
   int grab_offset = 0;      // the pass tile counters follow the group counters
+  int gen_offset = 0;       // then the generation words of chained launches
 };
 // raw_inline: reserve room for the 4N input doubles of host-resident spots.
 JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev,
@@ -178,7 +180,10 @@ void timed(hipStream_t s, const char* name, F&& launch) {
 class Batch {
  public:
   // Plans the jobs and lays out their scratch; allocates as needed.
-  hg_status build(const JobSpec* specs, int count, const TuneParams& tp, int32_t* status_dev);
+  // allow_chain: a single FP32 job may run its compressed passes as one
+  // chained launch (not for schedules captured into a graph).
+  hg_status build(const JobSpec* specs, int count, const TuneParams& tp, int32_t* status_dev,
+                  bool allow_chain = false);
   // Uploads the tables (and host spot arrays), then the whole schedule:
   // setup, random orders, one pass launch per iteration round, final phase.
   // With `capture`, the enqueue is being recorded into a graph: no event is
@@ -213,6 +218,11 @@ class Batch {
   std::vector<JobSlice> septab_;         // factor tables of the separable FP32 jobs
   int septab_blocks_ = 0;
   JobSlice* septab_dev_ = nullptr;
+  // chained launch of the compressed passes (single job): iterations
+  // 1..chain_rounds_ run in one k_pass_chain launch instead of rounds_
+  std::vector<PassDesc> chain_descs_;
+  PassDesc* chain_dev_ = nullptr;
+  int chain_rounds_ = 0, chain_blocks_ = 0, chain_units_ = 1;
   bool perm_lds_ = true;
   int max_h_ = 0;
   size_t host_spot_bytes_ = 0;

@@ -24,4 +24,5 @@ def test_table_round_trip(tmp_path):
     assert again.entries == json.loads(path.read_text())
     assert autotune.Table.as_tune(again.entries[key]) == {"full_block_cap": 0,
                                                           "subset_block_cap": 256,
-                                                          "pass_form": 1}
+                                                          "pass_form": 1,
+                                                          "chain_passes": 0}

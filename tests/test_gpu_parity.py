@@ -430,3 +430,27 @@ def test_shared_exponential_form_full_size():
     e1 = rel_mag_err(V[0], V1[:, 0] + 1j * V1[:, 1])
     print("shared-e full size e", e, gd["e"], "u", u, gd["u"], "V^1 rel", e1)
     assert abs(e - gd["e"]) <= EU_TOL and abs(u - gd["u"]) <= EU_TOL and e1 <= REL_V
+
+
+# --------------------------------------------- chained compressed passes ---
+
+CHAINED = {"full_block_cap": 0, "subset_block_cap": 0, "pass_form": 0, "chain_passes": 1}
+
+
+@pytest.mark.parametrize("W,H,N,I,c,seed", [(1152, 1152, 100, 30, 1 / 16, 0),
+                                             (300, 170, 37, 8, 0.1, 11),
+                                             (256, 256, 256, 6, 0.25, 3),
+                                             (97, 61, 1, 4, 0.5, 2)])
+def test_chained_passes_bit_identical(W, H, N, I, c, seed):
+    """The compressed passes of one hologram chained in one cooperative
+    launch give the same bits as one launch per pass (hologram and the spot
+    fields of every iteration)."""
+    import torch
+    g = Grid(W, H)
+    s = spot_cloud(seed, N, g, z_half_mm=0.1)
+    say("chained vs per-pass launches", W, H, N, I, c)
+    a, Va = hg.cswgs(g, OPTICS, s, I, c, seed, trace=True)
+    b, Vb = hg.cswgs(g, OPTICS, s, I, c, seed, trace=True, tune=CHAINED)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert np.array_equal(Va, Vb)
