@@ -42,11 +42,55 @@ CLOUDS = 10
 # per (pixel, spot) pair.
 FLOPS_BACK = 10
 FLOPS_FWD = 14
-PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (256 CU, 2.4 GHz, packed FMA)
+# Issue-limited ALU peak of the per-pixel passes.  The build disables packed
+# FP32, so the vector ALU issues 256 CU x 4 SIMD x 16 lanes x 2.4 GHz =
+# 39.3 T lane-operations/s (the 157.3 TFLOP/s vector figure counts packed
+# FMAs).  A (pixel, spot) pair of the two-sincos pass issues 3 FMA + fract +
+# sin + cos + 2 FMA (back-propagation) and 3 FMA + fract + sin + cos + 4 FMA
+# (forward); v_sin / v_cos issue at half the FMA rate on this chip (measured
+# by a microbenchmark: 19.0 T/s each against 39.3 T/s for FMA), so a pair
+# takes 22 issue slots and the chip completes at most 39.3 / 22 = 1.787 T
+# pairs/s = 42.9 TFLOP/s at 24 algorithmic flops per pair.
+ISSUE_T_PER_S = 256 * 4 * 16 * 2.4e9 / 1e12
+SLOTS_PER_PAIR = 22
+PEAK_ALU_TFLOPS = round(ISSUE_T_PER_S / SLOTS_PER_PAIR * (FLOPS_BACK + FLOPS_FWD), 1)
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (packed FMA), for reference
 # Launch tags of the library's kernel timing (hg_timing_read).
 KERNELS = ("k_setup", "k_perm", "k_sep_tables", "k_sep_pass", "k_sep_final", "k_pass_subset",
            "k_pass_full", "k_pass_mixed", "k_backprop_phi", "k_mx_tables", "k_mx_subset",
            "k_mx_full", "k_mx_final")
+
+
+# HBM traffic of the dominant kernel per launch, from the rocprofv3 PMC
+# summary committed under profiles/ (FETCH_SIZE and WRITE_SIZE, each scaled
+# by what the same counter reads for a copy of known size).  It holds only
+# while the kernel's sources are those the counters were taken on.
+TRAFFIC_SOURCES = ("kernels.hip", "kernels.hpp", "pass_tail.hpp", "device_common.hpp",
+                   "device_math.hpp")
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2003_05293_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(kernel: str):
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel}_{WORKLOAD}.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("traffic-json:"):
+                t = json.loads(line[len("traffic-json:"):])
+                if t.get("sources_sha256") != kernel_sources_sha256():
+                    return None
+                return round(1024.0 * (t["fetch_kib"] * t["fetch_scale"]
+                                       + t["write_kib"] * t["write_scale"]))
+    return None
 
 
 def cpu_baseline(grid, optics, spots, seed):
@@ -315,6 +359,7 @@ def main():
     m = math.ceil(COMP * W * H)
     # (pixel, spot) pairs per launch and the steps each launch performs
     pairs = {"k_pass_subset": (m, FLOPS_BACK + FLOPS_FWD),
+             "k_pass_chain": (m * (ITER - 1), FLOPS_BACK + FLOPS_FWD),
              "k_pass_full": (W * H, FLOPS_BACK + FLOPS_FWD),
              "k_sep_pass": (W * H, FLOPS_BACK + FLOPS_FWD),
              "k_sep_final": (W * H, FLOPS_BACK),
@@ -328,8 +373,12 @@ def main():
     flops = px * N * fl
     achieved = flops / (kern[dominant]["avg_us"] * 1e-6) / 1e12
     roofline = {
-        "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+        "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_ALU_TFLOPS,
+        "unit": "TFLOP/s", "frac": round(achieved / PEAK_ALU_TFLOPS, 4),
+        "traffic": profiled_traffic(dominant),
+        "peak_basis": f"{SLOTS_PER_PAIR} issue slots per (pixel, spot) pair at "
+                      f"{ISSUE_T_PER_S:.1f} T slots/s (non-packed FP32, sin/cos at half rate)",
+        "frac_of_fp32_vector_peak": round(achieved / PEAK_FP32_TFLOPS, 4),
         "kernel": dominant, "avg_launch_us": round(kern[dominant]["avg_us"], 3),
         "flops_per_launch": flops,
         "kernels": {k: {"avg_us": round(v["avg_us"], 3),

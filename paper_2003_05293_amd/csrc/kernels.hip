@@ -312,10 +312,13 @@ __host__ __device__ inline LaneMap lane_map(int N) {
   return m;
 }
 
-// CHAIN: the spot records come from LDS (a.recs) and the block that
-// completes the pass publishes the generation word after the update.
+// CHAIN: the spot records come from LDS (a.recs), the pixel index of this
+// thread in the block's first sub-tile may come prefetched (has_pre, pre_p),
+// and the block that completes the pass publishes the generation word after
+// the update.
 template <int MAXU, bool CHAIN = false>
-__device__ void pass_block(const PassCtx& a, unsigned* grab) {
+__device__ void pass_block(const PassCtx& a, unsigned* grab, bool has_pre = false,
+                           int32_t pre_p = 0) {
   __shared__ float2 sw[kWaves][kTile];
   __shared__ float4 px[kTile];
   __shared__ float pui[kTile];
@@ -383,7 +386,9 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab) {
         }
         __syncthreads();
       } else {
-        const int32_t p = valid ? pixel_of(a.ps, q) : 0;
+        const int32_t p = (CHAIN && has_pre && tile == a.lb && st == 0)
+                              ? pre_p
+                              : (valid ? pixel_of(a.ps, q) : 0);
         if (dynamic && st == a.plan.sub - 1 && threadIdx.x == 0)
           ticket = atomicAdd(grab, p >= 0 ? 1u : 1u);
         PixCoord c{0.f, 0.f, 0.f};
@@ -675,6 +680,8 @@ __global__ __launch_bounds__(kBlock, MAXU > 4 ? 2 : 6) void k_pass_chain(
   __shared__ SpotRec recs[kChainMaxSpots];
   __shared__ int stop;
   const JobDev& jb = jobs[descs[0].job];
+  bool has_pre = false;
+  int32_t pre_p = 0;
   for (int p = 0; p < npass; ++p) {
     __syncthreads();  // the previous pass's use of LDS is over
     if (p > 0) {
@@ -717,7 +724,15 @@ __global__ __launch_bounds__(kBlock, MAXU > 4 ? 2 : 6) void k_pass_chain(
     a.recs = recs;
     a.gen = jb.gen;
     a.gen_next = (unsigned)(p + 1);
-    pass_block<MAXU, true>(a, jb.grab + d.grab_slot);
+    pass_block<MAXU, true>(a, jb.grab + d.grab_slot, has_pre, pre_p);
+    // the pixel index of the next pass's first sub-tile, requested while the
+    // block waits for this pass to complete
+    if (p + 1 < npass) {
+      const PassDesc& dn = descs[p + 1];
+      const int32_t q = blockIdx.x * dn.plan.sub * kTile + (int)(threadIdx.x & 63);
+      pre_p = q < dn.ps.count ? pixel_of(dn.ps, q) : 0;
+      has_pre = true;
+    }
   }
 }
 

@@ -198,12 +198,13 @@ hipError_t launch_pass_chain(const JobDev* jobs, const PassDesc* descs, int npas
 // so e^{i phi_n(i,j)} = F_n(i) G_n(j).  A full-grid back-propagation is then
 // the complex product S = B F (B_n(j) = C_n G_n(j), C_n = A_n e^{i th_n}) and the
 // full-grid forward sum is V_n = (1/M) sum_j conj(G_n(j)) sum_i u(j,i) conj(F_n(i)).
-constexpr int kSepTile = 64;  // output tile edge of the separable passes
+constexpr int kSepTileH = 64;  // output tile of the separable passes: rows (16 per wave)
+constexpr int kSepTileW = 32;  // and columns
 struct SepDesc {
   int32_t block_begin;
   int32_t job;
-  int32_t tiles_x;      // ceil(W / kSepTile)
-  int32_t tiles_y;
+  int32_t tiles_x;      // ceil(W / kSepTileW)
+  int32_t tiles_y;      // ceil(H / kSepTileH)
   PassPlan plan;        // blocks = tiles_x * tiles_y, reduction groups
   int32_t update;       // weight update after the sums (fused passes)
   double inv_count;

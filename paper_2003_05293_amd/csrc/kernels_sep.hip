@@ -100,13 +100,14 @@ __global__ __launch_bounds__(256) void k_sep_tables(const JobDev* __restrict__ j
 
 constexpr int kSepSteps = 8;  // K-steps of the back-propagation product per load group
 constexpr int kSepCols = 8;   // column pairs of the forward product per load group
+constexpr int kSepCB = kSepTileW / 16;  // 16-column blocks per tile
 
 // Operands of kSepSteps K-steps of S = B F for one wave: G_n(row) of its
-// rows and the F operand of the tile's four 16-column blocks.  Loads of the
+// rows and the F operand of the tile's 16-column blocks.  Loads of the
 // next group are issued before the products of the current one.
 struct BpOps {
   float2 ga[kSepSteps];
-  float fc[kSepSteps][4];
+  float fc[kSepSteps][kSepCB];
 };
 __device__ __forceinline__ void bp_load(BpOps& o, const JobDev& jb, int rb, int tx, int s0, int KS,
                                         int lane) {
@@ -116,7 +117,8 @@ __device__ __forceinline__ void bp_load(BpOps& o, const JobDev& jb, int rb, int 
         as_global(reinterpret_cast<const float*>(jb.sepGa + op_index(rb, s0 + q, KS, lane)));
     o.ga[q] = make_float2(gp[0], gp[1]);
 #pragma unroll
-    for (int t = 0; t < 4; ++t) o.fc[q][t] = as_global(jb.sepFc)[op_index(4 * tx + t, s0 + q, KS, lane)];
+    for (int t = 0; t < kSepCB; ++t)
+      o.fc[q][t] = as_global(jb.sepFc)[op_index(kSepCB * tx + t, s0 + q, KS, lane)];
   }
 }
 // A operand: part of B (real output: (Br, -Bi)) or of i B (imaginary
@@ -129,7 +131,7 @@ __device__ __forceinline__ void bp_mma(const BpOps& o, const float2* cs, int s0,
     const float br = c.x * o.ga[q].x - c.y * o.ga[q].y, bi = c.x * o.ga[q].y + c.y * o.ga[q].x;
     const float ar = part ? -bi : br, ai = part ? br : bi;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < kSepCB; ++t) {
       sr[t] = mfma4(ar, o.fc[q][t], sr[t]);
       si[t] = mfma4(ai, o.fc[q][t], si[t]);
     }
@@ -141,7 +143,7 @@ __device__ __forceinline__ void bp_mma(const BpOps& o, const float2* cs, int s0,
 // spots, added into the exact sums of group g.  Every thread of the block
 // calls this with the same sb0 and R.
 template <int R>
-__device__ void sep_forward(const JobDev& jb, const float2 (*us)[kSepTile + 1],
+__device__ void sep_forward(const JobDev& jb, const float2 (*us)[kSepTileW + 1],
                             float2 (*red)[64], int sb0, int rb, int col0, int S16, int CP, int lane,
                             int wave, int shift, int g) {
   const int lr = lane & 15, lg = lane >> 4, part = lg & 1;
@@ -168,15 +170,11 @@ __device__ void sep_forward(const JobDev& jb, const float2 (*us)[kSepTile + 1],
       }
     }
   };
-  static_assert(kSepTile / 2 == 4 * kSepCols, "four column groups per tile");
+  static_assert(kSepTileW / 2 == 2 * kSepCols, "two column groups per tile");
   load(fa, 0);
   load(fb, kSepCols);
   mma(fa, 0);
-  load(fa, 2 * kSepCols);
   mma(fb, kSepCols);
-  load(fb, 3 * kSepCols);
-  mma(fa, 2 * kSepCols);
-  mma(fb, 3 * kSepCols);
 #pragma unroll
   for (int k = 0; k < R; ++k) {
     const int64_t gv = op_index(rb, sb0 + k, S16, lane) * 2;
@@ -217,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ 
                                                      const SepDesc* __restrict__ descs,
                                                      int ndesc) {
   extern __shared__ float2 cs[];                      // [Np] C_n = A_n e^{i theta_n}
-  __shared__ float2 us[kWaves][16][kSepTile + 1];     // u of each wave's rows
+  __shared__ float2 us[kWaves][16][kSepTileW + 1];    // u of each wave's rows
   __shared__ float2 red[kWaves][64];
   __shared__ int flag;
   __shared__ double wsum[kWaves];
@@ -231,7 +229,7 @@ __global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ 
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4, part = lg & 1;
   const int rb = 4 * ty + wave;
-  const int row0 = 16 * rb, col0 = kSepTile * tx;
+  const int row0 = 16 * rb, col0 = kSepTileW * tx;
 
   for (int n = threadIdx.x; n < 16 * S16; n += kBlock) {
     float2 c = make_float2(0.f, 0.f);
@@ -245,9 +243,9 @@ __global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ 
 
   // S = B F, K = 2 Np in groups of kSepSteps steps (KS = 8 S16 is a
   // multiple of kSepSteps), the next group's operands loaded ahead.
-  f4_t sr[4], si[4];
+  f4_t sr[kSepCB], si[kSepCB];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) sr[t] = si[t] = f4_t{0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < kSepCB; ++t) sr[t] = si[t] = f4_t{0.f, 0.f, 0.f, 0.f};
   {
     static_assert(kSepSteps == 8, "K-step groups of 8: KS = 8 S16");
     const int G = KS / kSepSteps;
@@ -266,7 +264,7 @@ __global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ 
   if (FINAL) {
     HG_GLOBAL float* out = as_global_mut(d.out);
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < kSepCB; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = row0 + 4 * lg + r, col = col0 + 16 * t + lr;
@@ -277,7 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ 
 
   // u = e^{i Phi} over the grid (0 outside it), in LDS.
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < kSepCB; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = row0 + 4 * lg + r, col = col0 + 16 * t + lr;
@@ -353,7 +351,7 @@ void launch_sep_tables(const JobDev* jobs, const JobSlice* slices, int nslices, 
 
 PassPlan plan_sep(int W, int H) {
   PassPlan p;
-  p.tiles = ceil_div(W, kSepTile) * ceil_div(H, kSepTile);
+  p.tiles = ceil_div(W, kSepTileW) * ceil_div(H, kSepTileH);
   p.sub = 1;
   p.blocks = p.tiles;
   int gs = 1;

@@ -254,7 +254,8 @@ JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev
   // partial-sum rows: one per tile of the largest pass the job can run
   int max_rows = 0, max_groups = 0;
   if (j.mixed || L.separable) {  // operand tables of the matrix-core passes
-    static_assert(kSepTile == kMxTile, "one table geometry for both full-grid forms");
+    static_assert(kSepTileH == kMxTile && kMxTile % kSepTileW == 0,
+                  "one table geometry for both full-grid forms");
     j.mx_steps = (s.N + 15) / 16;
     j.mx_cblocks = (s.W + kMxTile - 1) / kMxTile * (kMxTile / 16);
     j.mx_rblocks = (s.H + kMxTile - 1) / kMxTile * (kMxTile / 16);
@@ -386,8 +387,8 @@ SepDesc sep_desc(const JobDev& j, const JobLayout& L, int index, int block_begin
   SepDesc d;
   d.block_begin = block_begin;
   d.job = index;
-  d.tiles_x = (j.W + kSepTile - 1) / kSepTile;
-  d.tiles_y = (j.H + kSepTile - 1) / kSepTile;
+  d.tiles_x = (j.W + kSepTileW - 1) / kSepTileW;
+  d.tiles_y = (j.H + kSepTileH - 1) / kSepTileH;
   d.plan = L.plan_sep;
   d.update = 0;
   d.inv_count = 1.0 / (double)j.M;
