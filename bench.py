@@ -18,6 +18,7 @@ on the host cores on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import math
 import os
@@ -42,17 +43,18 @@ CLOUDS = 10
 # per (pixel, spot) pair.
 FLOPS_BACK = 10
 FLOPS_FWD = 14
-# Issue-limited ALU peak of the per-pixel passes.  The build disables packed
-# FP32, so the vector ALU issues 256 CU x 4 SIMD x 16 lanes x 2.4 GHz =
-# 39.3 T lane-operations/s (the 157.3 TFLOP/s vector figure counts packed
-# FMAs).  A (pixel, spot) pair of the two-sincos pass issues 3 FMA + fract +
-# sin + cos + 2 FMA (back-propagation) and 3 FMA + fract + sin + cos + 4 FMA
-# (forward); v_sin / v_cos issue at half the FMA rate on this chip (measured
-# by a microbenchmark: 19.0 T/s each against 39.3 T/s for FMA), so a pair
-# takes 22 issue slots and the chip completes at most 39.3 / 22 = 1.787 T
-# pairs/s = 42.9 TFLOP/s at 24 algorithmic flops per pair.
-ISSUE_T_PER_S = 256 * 4 * 16 * 2.4e9 / 1e12
-SLOTS_PER_PAIR = 22
+# Issue-limited ALU peak of the per-pixel passes, from the chip's unit
+# counts and clock: the FP32 vector peak of 157.3 TFLOP/s is 256 CU x 2.4 GHz
+# x 128 FMA lanes per clock per CU = 78.65 T FMA/s.  Transcendentals
+# (v_sin_f32, v_cos_f32) issue at a quarter of that rate (19.7 T/s; the
+# microbenchmark paper_2003_05293_amd/bench_alu measures 19.0 and 19.4 T/s).
+# A (pixel, spot) pair of the two-sincos pass issues 3 FMA + fract + sin +
+# cos + 2 FMA (back-propagation) and 3 FMA + fract + sin + cos + 4 FMA
+# (forward): 12 FMA + 2 fract + 4 transcendentals = 30 full-rate issue
+# slots, so the chip completes at most 78.65 / 30 = 2.62 T pairs/s, i.e.
+# 62.9 TFLOP/s at 24 algorithmic flops per pair.
+ISSUE_T_PER_S = 256 * 2.4e9 * 128 / 1e12
+SLOTS_PER_PAIR = 12 + 2 + 4 * 4
 PEAK_ALU_TFLOPS = round(ISSUE_T_PER_S / SLOTS_PER_PAIR * (FLOPS_BACK + FLOPS_FWD), 1)
 PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (packed FMA), for reference
 # Launch tags of the library's kernel timing (hg_timing_read).
@@ -292,6 +294,13 @@ def main():
         print(json.dumps({"calibrate_copy_bytes_read_per_copy": 4 * n,
                           "calibrate_copy_bytes_written_per_copy": 4 * n, "copies": 3}))
         return
+    # Python's cyclic garbage collector is off for the whole run: its full
+    # collections (one every ~200 hologram calls here, from the binding's
+    # per-call ctypes objects) stall the host for 45-60 ms, long enough to
+    # starve the GPU; the objects are freed by reference counting anyway.
+    gc.collect()
+    gc.freeze()
+    gc.disable()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the hologram "
               "path has no multi-GPU form in this build", file=sys.stderr)
@@ -376,8 +385,8 @@ def main():
         "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_ALU_TFLOPS,
         "unit": "TFLOP/s", "frac": round(achieved / PEAK_ALU_TFLOPS, 4),
         "traffic": profiled_traffic(dominant),
-        "peak_basis": f"{SLOTS_PER_PAIR} issue slots per (pixel, spot) pair at "
-                      f"{ISSUE_T_PER_S:.1f} T slots/s (non-packed FP32, sin/cos at half rate)",
+        "peak_basis": f"{SLOTS_PER_PAIR} full-rate issue slots per (pixel, spot) pair "
+                      f"(12 FMA, 2 fract, 4 sin/cos at quarter rate) at {ISSUE_T_PER_S:.2f} T/s",
         "frac_of_fp32_vector_peak": round(achieved / PEAK_FP32_TFLOPS, 4),
         "kernel": dominant, "avg_launch_us": round(kern[dominant]["avg_us"], 3),
         "flops_per_launch": flops,

@@ -1,4 +1,6 @@
-"""Builds libhg.so (the HIP kernels and the C ABI) in-tree for gfx950.
+"""Builds libhg.so (the HIP kernels and the C ABI) and two microbenchmarks
+(bench_alu: ALU issue rates; bench_launch: launch and same-word atomic
+costs) in-tree for gfx950.
 
     python -m paper_2003_05293_amd.build
 
@@ -19,6 +21,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libhg.so")
+MICROBENCH = ("bench_alu", "bench_launch")
 SOURCES = ["kernels.hip", "kernels_mx.hip", "kernels_sep.hip", "runtime.hip", "api.hip", "engine.hip"]
 ARCH = "gfx950"
 
@@ -59,6 +62,18 @@ def build(verbose: bool = False) -> str:
         subprocess.run(cmd, check=True)
         shutil.copyfile(out_tmp, LIB + ".tmp")
         os.replace(LIB + ".tmp", LIB)
+        # microbenchmarks behind the roofline and the hand-off design
+        # (standalone programs)
+        for name in MICROBENCH:
+            exe_tmp = os.path.join(tmp, name)
+            cmd = [cc, *HIP_FLAGS, os.path.join(CSRC, name + ".hip"), "-o", exe_tmp]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            subprocess.run(cmd, check=True)
+            dst = os.path.join(PKG, name)
+            shutil.copyfile(exe_tmp, dst + ".tmp")
+            os.chmod(dst + ".tmp", 0o755)
+            os.replace(dst + ".tmp", dst)
     return LIB
 
 

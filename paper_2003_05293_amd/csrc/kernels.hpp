@@ -225,7 +225,7 @@ void launch_sep_pass(const JobDev* jobs, const SepDesc* descs, int ndesc, int to
 
 // ---- mixed-precision passes (FP16 matrix cores, FP32 sums) ----
 // A pass is the separable recast above on the matrix cores: per output tile
-// of kMxTile x kMxTile pixels (wave w: rows 16w..16w+15), S = B F with FP16
+// of kMxTile x kMxTileW pixels (wave w: rows 16w..16w+15), S = B F with FP16
 // operands and FP32 accumulation (K = 2 Np: real and imaginary parts
 // interleaved), u = S / |S| where the pixel is in the pass's pixel set
 // (else 0), T = u conj(F)^T the same way, and the tile's partial
@@ -233,7 +233,8 @@ void launch_sep_pass(const JobDev* jobs, const SepDesc* descs, int ndesc, int to
 // over all pixels with u = 0 outside the window: pixel p is in window
 // [start, start + count) of the random order when (rank[p] - start) mod M
 // < count.  Partials are added across tiles with compensated FP32 sums.
-constexpr int kMxTile = 64;
+constexpr int kMxTile = 64;   // table geometry: rows and columns padded to it
+constexpr int kMxTileW = 32;  // columns of a pass tile (rows: kMxTile)
 enum MxMode : int32_t { kMxIterate = 0, kMxFinal = 1, kMxFromPhi = 2 };
 struct MxDesc {
   int32_t block_begin;

@@ -134,7 +134,8 @@ __device__ __forceinline__ void ksum(float& s, float& c, float x) {
 // loads are in flight before any is used; rows past row_end fall outside
 // the buffer resource and load as zero.
 constexpr int kMxBatch = 12;
-constexpr int kMxSteps = 4;  // K-steps of the back-propagation product per load group
+constexpr int kMxSteps = 2;  // K-steps of the back-propagation product per load group
+constexpr int kMxCB = kMxTileW / 16;  // 16-column blocks per tile
 __device__ __forceinline__ float4 column_ksum(const ColumnSrc& src, int n, int s, int k0,
                                               int k1, int S) {
   float sr = 0.f, si = 0.f, cr = 0.f, ci = 0.f;
@@ -251,14 +252,59 @@ __device__ void mx_tail(const JobDev& jb, const MxDesc& d, int lb) {
   }
 }
 
-// One kMxTile x kMxTile tile per block; wave w owns rows 16 w .. 16 w + 15
+// Operands of kMxSteps K-steps of S = B F for one wave: G of its rows and
+// the F operand of the tile's 16-column blocks (steps past the last are
+// loaded clamped and not used).
+struct MxOps {
+  f4_t ga[kMxSteps][2];
+  u4_t fc[kMxSteps][kMxCB];
+};
+__device__ __forceinline__ void mx_load(MxOps& o, const f4_t* Ga, const u4_t* Fc, int rb, int tx,
+                                        int s0, int S16, int lane) {
+#pragma unroll
+  for (int q = 0; q < kMxSteps; ++q) {
+    const int s = min(s0 + q, S16 - 1);
+    const int64_t gi = g_index(rb, s, S16, lane) * 2;
+    o.ga[q][0] = as_global(Ga)[gi];
+    o.ga[q][1] = as_global(Ga)[gi + 1];
+#pragma unroll
+    for (int t = 0; t < kMxCB; ++t) o.fc[q][t] = as_global(Fc)[fc_index(kMxCB * tx + t, s, S16, lane)];
+  }
+}
+// A operands conj(B) (real part) and i conj(B) (imaginary part), B = C G.
+__device__ __forceinline__ void mx_mma(const MxOps& o, const float2* cs, int s0, int S16, int lg,
+                                       f4_t* sr, f4_t* si) {
+#pragma unroll
+  for (int q = 0; q < kMxSteps; ++q) {
+    if (s0 + q < S16) {
+      const f4_t g01 = o.ga[q][0], g23 = o.ga[q][1];
+      const int n0 = 16 * (s0 + q) + 4 * lg;
+      const float2 c0 = cs[n0], c1 = cs[n0 + 1], c2 = cs[n0 + 2], c3 = cs[n0 + 3];
+      const float br0 = c0.x * g01[0] - c0.y * g01[1], bi0 = c0.x * g01[1] + c0.y * g01[0];
+      const float br1 = c1.x * g01[2] - c1.y * g01[3], bi1 = c1.x * g01[3] + c1.y * g01[2];
+      const float br2 = c2.x * g23[0] - c2.y * g23[1], bi2 = c2.x * g23[1] + c2.y * g23[0];
+      const float br3 = c3.x * g23[2] - c3.y * g23[3], bi3 = c3.x * g23[3] + c3.y * g23[2];
+      const u4_t ar = {pack_h2(br0, -bi0), pack_h2(br1, -bi1), pack_h2(br2, -bi2),
+                       pack_h2(br3, -bi3)};
+      const u4_t ai = {pack_h2(bi0, br0), pack_h2(bi1, br1), pack_h2(bi2, br2),
+                       pack_h2(bi3, br3)};
+#pragma unroll
+      for (int t = 0; t < kMxCB; ++t) {
+        sr[t] = mfma16(ar, o.fc[q][t], sr[t]);
+        si[t] = mfma16(ai, o.fc[q][t], si[t]);
+      }
+    }
+  }
+}
+
+// One kMxTile x kMxTileW tile per block; wave w owns rows 16 w .. 16 w + 15
 // of the tile, so each wave's products, normalisation and forward operands
 // stay within the wave until the tile's partial V is formed.
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_mx_pass(const JobDev* __restrict__ jobs,
+__global__ __launch_bounds__(kBlock, 3) void k_mx_pass(const JobDev* __restrict__ jobs,
                                                     const MxDesc* __restrict__ descs, int ndesc) {
-  extern __shared__ float2 cs[];                    // [Np] C_n = A_n e^{i theta_n}
-  __shared__ uint32_t us[kWaves][16][kMxTile + 4];  // u of each wave's rows (half pairs)
+  extern __shared__ float2 cs[];                     // [Np] C_n = A_n e^{i theta_n}
+  __shared__ uint32_t us[kWaves][16][kMxTileW + 4];  // u of each wave's rows (half pairs)
   __shared__ float2 red[kWaves][64];
   const int di = find_desc(descs, ndesc, blockIdx.x);
   const MxDesc& d = descs[di];
@@ -269,19 +315,19 @@ __global__ __launch_bounds__(kBlock) void k_mx_pass(const JobDev* __restrict__ j
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63, lr = lane & 15, lg = lane >> 4;
   const int rb = 4 * ty + wave;  // 16-row block of this wave
-  const int row0 = 16 * rb, col0 = kMxTile * tx;
+  const int row0 = 16 * rb, col0 = kMxTileW * tx;
 
-  f4_t sr[4], si[4];
+  f4_t sr[kMxCB], si[kMxCB];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) sr[t] = si[t] = f4_t{0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < kMxCB; ++t) sr[t] = si[t] = f4_t{0.f, 0.f, 0.f, 0.f};
 
-  // ranks of this lane's 16 pixels in the random order (window membership),
+  // ranks of this lane's pixels in the random order (window membership),
   // loaded first so that they arrive during the products
   const int M = jb.M;
   const bool windowed = MODE == kMxIterate && d.count < M;
-  uint32_t rk[4][4];
+  uint32_t rk[kMxCB][4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < kMxCB; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = row0 + 4 * lg + r, col = col0 + 16 * t + lr;
@@ -298,42 +344,18 @@ __global__ __launch_bounds__(kBlock) void k_mx_pass(const JobDev* __restrict__ j
       cs[n] = c;
     }
     __syncthreads();
-    // S = B F: A operand conj(B) (real part) and i conj(B) (imaginary part).
-    // K-steps go in groups of kMxSteps whose operand loads are all issued
-    // before the group's products, so a group costs one memory round trip.
+    // S = B F in groups of kMxSteps K-steps, the next group's operands
+    // loaded before the current group's products.
     const u4_t* Fc = reinterpret_cast<const u4_t*>(jb.mxFc);
     const f4_t* Ga = reinterpret_cast<const f4_t*>(jb.mxGa);
-    for (int s0 = 0; s0 < S16; s0 += kMxSteps) {
-      f4_t ga[kMxSteps][2];
-      u4_t fc[kMxSteps][4];
-#pragma unroll
-      for (int q = 0; q < kMxSteps; ++q) {
-        const int s = min(s0 + q, S16 - 1);  // a repeated step is loaded, not used
-        const int64_t gi = g_index(rb, s, S16, lane) * 2;
-        ga[q][0] = as_global(Ga)[gi];
-        ga[q][1] = as_global(Ga)[gi + 1];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) fc[q][t] = as_global(Fc)[fc_index(4 * tx + t, s, S16, lane)];
-      }
-#pragma unroll
-      for (int q = 0; q < kMxSteps; ++q) {
-        if (s0 + q >= S16) break;
-        const f4_t g01 = ga[q][0], g23 = ga[q][1];
-        const int n0 = 16 * (s0 + q) + 4 * lg;
-        const float2 c0 = cs[n0], c1 = cs[n0 + 1], c2 = cs[n0 + 2], c3 = cs[n0 + 3];
-        const float br0 = c0.x * g01[0] - c0.y * g01[1], bi0 = c0.x * g01[1] + c0.y * g01[0];
-        const float br1 = c1.x * g01[2] - c1.y * g01[3], bi1 = c1.x * g01[3] + c1.y * g01[2];
-        const float br2 = c2.x * g23[0] - c2.y * g23[1], bi2 = c2.x * g23[1] + c2.y * g23[0];
-        const float br3 = c3.x * g23[2] - c3.y * g23[3], bi3 = c3.x * g23[3] + c3.y * g23[2];
-        const u4_t ar = {pack_h2(br0, -bi0), pack_h2(br1, -bi1), pack_h2(br2, -bi2),
-                         pack_h2(br3, -bi3)};
-        const u4_t ai = {pack_h2(bi0, br0), pack_h2(bi1, br1), pack_h2(bi2, br2),
-                         pack_h2(bi3, br3)};
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          sr[t] = mfma16(ar, fc[q][t], sr[t]);
-          si[t] = mfma16(ai, fc[q][t], si[t]);
-        }
+    MxOps P, Q;
+    mx_load(P, Ga, Fc, rb, tx, 0, S16, lane);
+    for (int s0 = 0; s0 < S16; s0 += 2 * kMxSteps) {
+      if (s0 + kMxSteps < S16) mx_load(Q, Ga, Fc, rb, tx, s0 + kMxSteps, S16, lane);
+      mx_mma(P, cs, s0, S16, lg, sr, si);
+      if (s0 + kMxSteps < S16) {
+        if (s0 + 2 * kMxSteps < S16) mx_load(P, Ga, Fc, rb, tx, s0 + 2 * kMxSteps, S16, lane);
+        mx_mma(Q, cs, s0 + kMxSteps, S16, lg, sr, si);
       }
     }
   }
@@ -341,7 +363,7 @@ __global__ __launch_bounds__(kBlock) void k_mx_pass(const JobDev* __restrict__ j
   if (MODE == kMxFinal) {
     HG_GLOBAL float* out = as_global_mut(d.out);
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < kMxCB; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = row0 + 4 * lg + r, col = col0 + 16 * t + lr;
@@ -352,7 +374,7 @@ __global__ __launch_bounds__(kBlock) void k_mx_pass(const JobDev* __restrict__ j
 
   // u = e^{i Phi} on the pixel set, 0 elsewhere, as half pairs in LDS.
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < kMxCB; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = row0 + 4 * lg + r, col = col0 + 16 * t + lr;
@@ -385,10 +407,11 @@ __global__ __launch_bounds__(kBlock) void k_mx_pass(const JobDev* __restrict__ j
   __syncthreads();
 
   // T = U conj(F)^T for this wave's 16 rows, 64 spots per chunk, and the
-  // tile's partial V_n = sum_j conj(G_n(j)) T[j][n].
-  u4_t ua[4], ub[4];
+  // tile's partial V_n = sum_j conj(G_n(j)) T[j][n].  The chunk's F operands
+  // are loaded before its products.
+  u4_t ua[kMxCB], ub[kMxCB];
 #pragma unroll
-  for (int ks = 0; ks < 4; ++ks) {
+  for (int ks = 0; ks < kMxCB; ++ks) {
     const uint32_t* src = &us[wave][lr][16 * ks + 4 * lg];
     ua[ks] = u4_t{src[0], src[1], src[2], src[3]};
     ub[ks] = u4_t{times_minus_i(src[0]), times_minus_i(src[1]), times_minus_i(src[2]),
@@ -398,16 +421,21 @@ __global__ __launch_bounds__(kBlock) void k_mx_pass(const JobDev* __restrict__ j
   const f4_t* Gv = reinterpret_cast<const f4_t*>(jb.mxGv);
   for (int sb0 = 0; sb0 < S16; sb0 += 4) {
     f4_t tr[4], ti[4];
+    u4_t fn[kMxCB][4];
+#pragma unroll
+    for (int ks = 0; ks < kMxCB; ++ks)
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        fn[ks][u] = as_global(Fn)[fn_index(min(sb0 + u, S16 - 1), kMxCB * tx + ks, CB, lane)];
 #pragma unroll
     for (int u = 0; u < 4; ++u) tr[u] = ti[u] = f4_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks)
+    for (int ks = 0; ks < kMxCB; ++ks)
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         if (sb0 + u < S16) {
-          const u4_t f = as_global(Fn)[fn_index(sb0 + u, 4 * tx + ks, CB, lane)];
-          tr[u] = mfma16(ua[ks], f, tr[u]);
-          ti[u] = mfma16(ub[ks], f, ti[u]);
+          tr[u] = mfma16(ua[ks], fn[ks][u], tr[u]);
+          ti[u] = mfma16(ub[ks], fn[ks][u], ti[u]);
         }
       }
 #pragma unroll
@@ -452,7 +480,7 @@ __global__ __launch_bounds__(kBlock) void k_mx_pass(const JobDev* __restrict__ j
 
 PassPlan plan_mx(int W, int H) {
   PassPlan p;
-  p.tiles = ceil_div(W, kMxTile) * ceil_div(H, kMxTile);
+  p.tiles = ceil_div(W, kMxTileW) * ceil_div(H, kMxTile);
   p.sub = 1;
   p.shift = 0;  // the mixed passes use compensated FP32 sums
   p.blocks = p.tiles;

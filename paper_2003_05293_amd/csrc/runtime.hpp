@@ -147,6 +147,9 @@ struct LaunchSet {
   // pixels, no update).
   void add_forward_mx(const JobDev& j, const JobLayout& L, int index);
   bool empty() const { return pass.empty() && sep.empty() && back.empty() && mx.empty(); }
+  // Timing name of the set's per-pixel pass launch when that is all the set
+  // launches, else nullptr.
+  const char* pass_only_name() const;
   size_t bytes() const;
   // Copies the descriptors into host staging at `host` and points the
   // device copies at `dev` (same offsets); returns the bytes used.
@@ -160,7 +163,7 @@ struct LaunchSet {
 bool timing_enabled();
 void timing_enable(bool on);
 hipEvent_t timing_start(hipStream_t s);
-void timing_stop(hipStream_t s, const char* name, hipEvent_t start);
+void timing_stop(hipStream_t s, const char* name, hipEvent_t start, int count = 1);
 hg_status timing_reset();
 hg_status timing_read(const char* name, double* total_ms, int64_t* launches);
 
