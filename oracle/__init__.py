@@ -21,5 +21,5 @@ from .sampler import (  # noqa: F401
 )
 from .hg import (  # noqa: F401
     pixel_offsets_mm, spot_phase, backward, forward, update, rs, wgs, cswgs,
-    metrics, Trace,
+    metrics, Trace, pupil_pixels, illumination,
 )

@@ -28,6 +28,16 @@ Written from the paper (Pozzi & Mapelli, arXiv 2003.05293), section 2:
   hologram over all pixels, V*_n; I_n = |V*_n|^2; e = sum_n I_n (the fraction
   of the SLM power that lands in the spots: with the mean normalisation a
   single spot gets all of it); u = 1 - (max I - min I)/(max I + min I).
+* The pupil (experimental setup section: a Gaussian beam of waist radius w
+  on the SLM, and the round aperture of the optical system): with a waist,
+  eq. (3) weights each pixel by the illumination amplitude
+  A(x', y') = exp(-(x'^2 + y'^2) / w^2); with an aperture of diameter D
+  pixels, Omega is the set of pixels whose centre lies within D/2 pixels of
+  the grid centre, and every pixel set of the method (the full set and the
+  random order of CS-WGS) is taken within it.  The phase of eq. (1) is still
+  computed on every pixel of the grid.  The efficiency divides by the power
+  on the SLM: e = sum_n I_n / mean_Omega(A^2), which is 1 for a single spot
+  under uniform illumination and at most 1 in general.
 
 Pixel grid: x'_i = (i - (W-1)/2) * pitch, y'_j = (j - (H-1)/2) * pitch, and
 pixel p = j*W + i (row-major [H][W]).
@@ -79,6 +89,32 @@ def _all(grid):
     return np.arange(grid.M, dtype=np.int64)
 
 
+def pupil_pixels(grid, optics) -> np.ndarray:
+    """Omega: the pixels inside the round aperture, in index order (all
+    pixels without an aperture).  With doubled integer offsets
+    Lx = 2i - (W-1), Ly = 2j - (H-1) a pixel centre lies within D/2 pixels of
+    the grid centre exactly when Lx^2 + Ly^2 <= D^2."""
+    D = float(getattr(optics, "aperture_px", 0.0))
+    if D <= 0.0:
+        return _all(grid)
+    Lx = 2 * np.arange(grid.W, dtype=np.int64) - (grid.W - 1)
+    Ly = 2 * np.arange(grid.H, dtype=np.int64) - (grid.H - 1)
+    inside = (Lx[None, :] ** 2 + Ly[:, None] ** 2) <= D * D
+    return np.flatnonzero(inside.ravel()).astype(np.int64)
+
+
+def illumination(grid, optics, p) -> np.ndarray:
+    """Illumination amplitude A at the pixels p: exp(-r^2 / w^2) with r the
+    distance of the pixel centre from the grid centre in mm (1 without a
+    waist)."""
+    p = np.asarray(p, dtype=np.int64)
+    w = float(getattr(optics, "waist_mm", 0.0))
+    if w <= 0.0:
+        return np.ones(p.shape[0])
+    xp, yp = _pixels(grid, p)
+    return np.exp(-(xp * xp + yp * yp) / (w * w))
+
+
 def backward(grid, optics, spots, w, theta, p=None) -> np.ndarray:
     """eq. (1): Phi at pixels p (default all), with a_n = w_n a_n^0."""
     p = _all(grid) if p is None else np.asarray(p, dtype=np.int64)
@@ -93,15 +129,17 @@ def backward(grid, optics, spots, w, theta, p=None) -> np.ndarray:
 
 
 def forward(grid, optics, spots, Phi_p, p=None) -> np.ndarray:
-    """eq. (3): V_n = mean over p of e^{i(Phi(p) - phi_n(p))}, complex (N,).
-    Phi_p holds Phi at the pixels p (default all pixels, in index order)."""
-    p = _all(grid) if p is None else np.asarray(p, dtype=np.int64)
+    """eq. (3): V_n = mean over p of A(p) e^{i(Phi(p) - phi_n(p))}, complex
+    (N,).  p defaults to Omega (pupil_pixels); Phi_p holds Phi at the pixels
+    p, in the order of p."""
+    p = pupil_pixels(grid, optics) if p is None else np.asarray(p, dtype=np.int64)
     Phi_p = np.asarray(Phi_p, dtype=np.float64)
     assert Phi_p.shape == p.shape
+    A = illumination(grid, optics, p)
     V = np.zeros(spots.n, dtype=np.complex128)
     for s in range(0, p.shape[0], CHUNK):
         phi = spot_phase(grid, optics, spots, p[s:s + CHUNK])
-        V += np.exp(1j * (Phi_p[s:s + CHUNK, None] - phi)).sum(axis=0)
+        V += (A[s:s + CHUNK, None] * np.exp(1j * (Phi_p[s:s + CHUNK, None] - phi))).sum(axis=0)
     return V / p.shape[0]
 
 
@@ -129,13 +167,13 @@ def rs(grid, optics, spots, seed: int) -> np.ndarray:
 def _iterate(grid, optics, spots, iterations: int, seed: int, c: Optional[float],
              trace: Optional[Trace]):
     I = int(iterations)
-    M = grid.M
+    pupil = pupil_pixels(grid, optics)
     compressed = c is not None
 
     def forward_set(j):  # pixel set of the forward sum of iteration j
         if compressed and j < I:
-            return sampler.subset(M, seed, j, c)
-        return None  # all pixels
+            return pupil[sampler.subset(pupil.shape[0], seed, j, c)]
+        return pupil  # Omega
 
     w = np.ones(spots.n)
     theta = sampler.theta0(seed, spots.n)
@@ -148,7 +186,7 @@ def _iterate(grid, optics, spots, iterations: int, seed: int, c: Optional[float]
             trace.V.append(V)
             trace.w.append(w.copy())
             trace.theta.append(theta.copy())
-        p_next = forward_set(j + 1) if j < I else None
+        p_next = forward_set(j + 1) if j < I else None          # None: all pixels
         Phi = backward(grid, optics, spots, w, theta, p_next)   # Phi^j
     return Phi
 
@@ -169,9 +207,11 @@ def cswgs(grid, optics, spots, iterations: int, compression: float, seed: int,
 
 def metrics(grid, optics, spots, Phi):
     """Efficiency e, uniformity u (eq. 7) and spot intensities I_n of the
-    hologram Phi (all pixels, index order)."""
-    V = forward(grid, optics, spots, Phi)
+    hologram Phi (all pixels, index order), over Omega."""
+    pupil = pupil_pixels(grid, optics)
+    V = forward(grid, optics, spots, np.asarray(Phi, dtype=np.float64)[pupil], pupil)
     I = np.abs(V) ** 2
-    e = float(I.sum())
+    power = float(np.mean(illumination(grid, optics, pupil) ** 2))
+    e = float(I.sum()) / power
     u = float(1.0 - (I.max() - I.min()) / (I.max() + I.min()))
     return e, u, I

@@ -22,7 +22,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 import oracle  # noqa: E402
-from workload import Grid, OPTICS, spot_cloud  # noqa: E402
+from workload import Grid, OPTICS, PUPIL_OPTICS, spot_cloud  # noqa: E402
 
 CASES = {
     # 1152 x 1152, N = 100, I = 30, CS-WGS with c = 1/16 and plain WGS.
@@ -31,25 +31,31 @@ CASES = {
     # 1920 x 1152 panel, 150 spots, deeper z range, CS-WGS with 20 iterations
     "cswgs_1920x1152_n150_i20_c16_seed3": dict(W=1920, H=1152, n=150, I=20, c=1 / 16, seed=3,
                                                z_half_mm=0.1),
+    # the headline case under the paper's pupil: Gaussian illumination of
+    # waist radius 6 mm on the round aperture 1152 pixels across
+    "cswgs_1152x1152_n100_i30_c16_pupil_seed0": dict(W=1152, H=1152, n=100, I=30, c=1 / 16,
+                                                     seed=0, pupil=True),
 }
 
 SAMPLE = 4096
 
 
-def run(name: str, W, H, n, I, c, seed, z_half_mm=0.05):
+def run(name: str, W, H, n, I, c, seed, z_half_mm=0.05, pupil=False):
     g = Grid(W, H)
+    optics = PUPIL_OPTICS if pupil else OPTICS
     s = spot_cloud(seed, n, g, z_half_mm=z_half_mm)
     tr = oracle.Trace()
     t0 = time.time()
     if c is None:
-        Phi = oracle.wgs(g, OPTICS, s, I, seed, tr)
+        Phi = oracle.wgs(g, optics, s, I, seed, tr)
     else:
-        Phi = oracle.cswgs(g, OPTICS, s, I, c, seed, tr)
-    e, u, inten = oracle.metrics(g, OPTICS, s, Phi)
+        Phi = oracle.cswgs(g, optics, s, I, c, seed, tr)
+    e, u, inten = oracle.metrics(g, optics, s, Phi)
     rng = np.random.Generator(np.random.PCG64(12345))
     pix = np.sort(rng.choice(g.M, SAMPLE, replace=False))
     out = dict(
         W=W, H=H, n=n, iterations=I, compression=c, seed=seed, z_half_mm=z_half_mm,
+        waist_mm=optics.waist_mm, aperture_px=optics.aperture_px,
         cloud="workload.spot_cloud(seed, n, Grid(W, H), z_half_mm=z_half_mm)",
         e=e, u=u, intensities=inten.tolist(),
         V1=[[float(v.real), float(v.imag)] for v in tr.V[0]],

@@ -6,6 +6,6 @@ constants of the workloads. It holds none of the hologram arithmetic
 the CPU oracle receive what it draws as plain arrays.
 """
 from .spots import (  # noqa: F401
-    Grid, Optics, Spots, OPTICS, PITCH_MM, lateral_half_range_mm,
-    spot_cloud, mixed_batch, poisson_stream, Workload, WORKLOADS,
+    Grid, Optics, Spots, OPTICS, PUPIL_OPTICS, PITCH_MM, lateral_half_range_mm,
+    spot_cloud, mixed_batch, poisson_stream, Workload, WORKLOADS, PUPIL_WORKLOAD,
 )

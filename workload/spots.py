@@ -38,12 +38,21 @@ class Grid:
 
 @dataclasses.dataclass(frozen=True)
 class Optics:
-    """Wavelength and focal length of the Fourier lens, both in mm."""
+    """Wavelength and focal length of the Fourier lens, both in mm, and the
+    pupil on the SLM: the waist radius of a Gaussian illumination beam in mm
+    (0: uniform illumination) and the diameter of a round aperture centred on
+    the grid, in pixels (0: the whole rectangle)."""
     lambda_mm: float = 0.488e-3
     focal_mm: float = 20.0
+    waist_mm: float = 0.0
+    aperture_px: float = 0.0
 
 
 OPTICS = Optics()
+# The paper's pupil (experimental setup section): a laser expanded to a beam
+# waist radius of 6 mm at the SLM panel, and the round aperture of the
+# optical system, 1152 pixels across (the short side of the panel).
+PUPIL_OPTICS = Optics(waist_mm=6.0, aperture_px=1152.0)
 
 
 @dataclasses.dataclass
@@ -163,3 +172,6 @@ WORKLOADS = {
     "cswgs_1152x1152_n100_i30_c16": Workload("cswgs_1152x1152_n100_i30_c16",
                                              Grid(1152, 1152), 100, 30, 1.0 / 16),
 }
+# The headline case under the paper's pupil (PUPIL_OPTICS): Gaussian
+# illumination on the round 1152-pixel aperture.
+PUPIL_WORKLOAD = "cswgs_1152x1152_n100_i30_c16_pupil"
