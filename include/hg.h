@@ -72,10 +72,29 @@ typedef struct hg_grid {
   double pitch_mm;  /* pixel pitch                                         */
 } hg_grid;
 
-/* Optics of eq. (2): wavelength lambda and focal length f, in mm. */
+/* Optics of eq. (2): wavelength lambda and focal length f, in mm, and the
+ * pupil of the experimental setup (section 4: a Gaussian beam on the SLM
+ * behind the round aperture of the optics).  Both pupil fields are finite
+ * and >= 0; 0 turns the part off.
+ *   waist_mm:    the forward projection (eq. 3) weights each pixel by the
+ *                illumination amplitude A = exp(-(x'^2 + y'^2) / waist^2);
+ *                the metrics then divide the efficiency by the mean of A^2
+ *                over the pupil (the power on the SLM), so e <= 1.
+ *   aperture_px: diameter D in pixels of the round aperture: the pupil
+ *                Omega is the set of pixels whose centre lies within D/2
+ *                pixel pitches of the grid centre, i.e. with doubled offsets
+ *                Lx = 2i - (W-1), Ly = 2j - (H-1), Lx^2 + Ly^2 <= D^2.  The
+ *                forward sums of every iteration (the full set, and the
+ *                random order of CS-WGS, taken over the |Omega| pupil pixels
+ *                in index order) and the metrics run over Omega only; the
+ *                hologram is still computed on every pixel.  HG_EINVAL if
+ *                Omega is empty.
+ * A zero-initialised pupil is the uniform full rectangle. */
 typedef struct hg_optics {
   double lambda_mm;
   double focal_mm;
+  double waist_mm;
+  double aperture_px;
 } hg_optics;
 
 /* N target spots X_n = (x_n, y_n, z_n) in mm and target amplitudes a_n^0
@@ -179,10 +198,11 @@ hg_status hg_cswgs_ex(const hg_grid *grid, const hg_optics *optics,
                       float *phi_dev, void *stream);
 
 /* Efficiency and uniformity of a hologram (section 2, last paragraph, and
- * eq. 7), in FP64: V*_n = mean over all pixels of e^{i(Phi - phi_n)},
- * I_n = |V*_n|^2, e = sum_n I_n, u = 1 - (max I - min I)/(max I + min I).
- * phi_dev: float32 [H][W].  intensities: NULL or host array of N doubles.
- * Blocks until the results are on the host. */
+ * eq. 7), in FP64: V*_n = mean over the pupil Omega of
+ * A(p) e^{i(Phi - phi_n)}, I_n = |V*_n|^2, e = sum_n I_n / mean_Omega(A^2),
+ * u = 1 - (max I - min I)/(max I + min I).  Without a pupil, Omega is every
+ * pixel and A = 1.  phi_dev: float32 [H][W].  intensities: NULL or host
+ * array of N doubles.  Blocks until the results are on the host. */
 hg_status hg_metrics(const hg_grid *grid, const hg_optics *optics,
                      const hg_spots *spots, const float *phi_dev, double *e,
                      double *u, double *intensities, void *stream);
@@ -284,17 +304,21 @@ hg_status hg_engine_destroy(hg_engine *engine);
 /* theta_n^0 (radians, FP64) for n < count, computed on the device.  Blocks. */
 hg_status hg_theta0(uint64_t seed, int32_t count, double *out_host);
 
-/* Pixel indices of Omega^j (j >= 1) for compression c: writes m = ceil(c*W*H)
- * int32 indices, in order, to idx_dev (capacity >= m) and m to *m_out.
- * Blocks until *m_out is set. */
-hg_status hg_subset(const hg_grid *grid, uint64_t seed, int32_t j,
-                    double compression, int32_t *idx_dev, int32_t *m_out,
-                    void *stream);
+/* Pixel indices of Omega^j (j >= 1) for compression c: writes
+ * m = ceil(c*|Omega|) int32 indices, in order, to idx_dev (capacity >= m)
+ * and m to *m_out.  optics: NULL or its aperture_px alone is read (the
+ * random order runs over the pupil pixels; |Omega| = W*H without an
+ * aperture).  Blocks until *m_out is set. */
+hg_status hg_subset(const hg_grid *grid, const hg_optics *optics, uint64_t seed,
+                    int32_t j, double compression, int32_t *idx_dev,
+                    int32_t *m_out, void *stream);
 
 /* Forward projection (eq. 3) of a given hologram: V_n = mean over the pixel
- * set of e^{i(Phi(p) - phi_n(p))}.  phi_dev: float32 [H][W].  idx_dev: NULL
- * for all pixels, else m device int32 pixel indices.  V_out: host, 2N
- * doubles (re, im).  flags: HG_PREC_*.  Blocks. */
+ * set of A(p) e^{i(Phi(p) - phi_n(p))}, A the illumination amplitude of the
+ * optics (1 without a waist).  phi_dev: float32 [H][W].  idx_dev: NULL for
+ * the pupil Omega (all pixels without an aperture), else m device int32
+ * pixel indices.  V_out: host, 2N doubles (re, im).  flags: HG_PREC_*.
+ * Blocks. */
 hg_status hg_forward(const hg_grid *grid, const hg_optics *optics,
                      const hg_spots *spots, const float *phi_dev,
                      const int32_t *idx_dev, int32_t m, uint32_t flags,
@@ -311,8 +335,8 @@ hg_status hg_backward(const hg_grid *grid, const hg_optics *optics,
 
 /* One fused iteration body: back-propagation with (w, theta) on the pixel
  * set immediately followed by the forward projection over the same set
- * (eqs. 1 and 3), returning V (host, 2N doubles).  This is the kernel the
- * iteration loop runs.  Blocks. */
+ * (eqs. 1 and 3, the pixel set and A as in hg_forward), returning V (host,
+ * 2N doubles).  This is the kernel the iteration loop runs.  Blocks. */
 hg_status hg_step(const hg_grid *grid, const hg_optics *optics,
                   const hg_spots *spots, const double *w, const double *theta,
                   const int32_t *idx_dev, int32_t m, uint32_t flags,

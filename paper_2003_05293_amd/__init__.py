@@ -9,7 +9,8 @@ built, every call raises: there is no fallback path.
 
 Grid, optics and spot arguments are duck-typed: any object with
   grid:   W, H, pitch_mm
-  optics: lambda_mm, focal_mm
+  optics: lambda_mm, focal_mm (and optionally waist_mm, aperture_px: the
+          pupil; 0 or absent means uniform illumination on the whole grid)
   spots:  x_mm, y_mm, z_mm, amp  (array-likes of equal length)
 works (for example the classes of the workload package).
 """
@@ -53,7 +54,8 @@ class _Grid(ctypes.Structure):
 
 
 class _Optics(ctypes.Structure):
-    _fields_ = [("lambda_mm", ctypes.c_double), ("focal_mm", ctypes.c_double)]
+    _fields_ = [("lambda_mm", ctypes.c_double), ("focal_mm", ctypes.c_double),
+                ("waist_mm", ctypes.c_double), ("aperture_px", ctypes.c_double)]
 
 
 _DP = ctypes.POINTER(ctypes.c_double)
@@ -109,7 +111,7 @@ def load():
         "hg_cswgs_ex": [G, O, S, c.POINTER(_Params), vp, vp],
         "hg_metrics": [G, O, S, vp, _DP, _DP, _DP, vp],
         "hg_theta0": [u64, i32, _DP],
-        "hg_subset": [G, u64, i32, dbl, vp, c.POINTER(i32), vp],
+        "hg_subset": [G, O, u64, i32, dbl, vp, c.POINTER(i32), vp],
         "hg_forward": [G, O, S, vp, vp, i32, u32, _DP, vp],
         "hg_backward": [G, O, S, _DP, _DP, vp, i32, u32, vp, vp],
         "hg_step": [G, O, S, _DP, _DP, vp, i32, u32, _DP, vp],
@@ -163,7 +165,8 @@ def _grid(g) -> _Grid:
 
 
 def _optics(o) -> _Optics:
-    return _Optics(float(o.lambda_mm), float(o.focal_mm))
+    return _Optics(float(o.lambda_mm), float(o.focal_mm),
+                   float(getattr(o, "waist_mm", 0.0)), float(getattr(o, "aperture_px", 0.0)))
 
 
 class _SpotArgs:
@@ -297,14 +300,16 @@ def theta0(seed: int, n: int) -> np.ndarray:
     return out
 
 
-def subset(grid, seed: int, j: int, compression: float, stream=None):
-    """Pixel indices of Omega^j as an int32 GPU tensor."""
+def subset(grid, seed: int, j: int, compression: float, stream=None, optics=None):
+    """Pixel indices of Omega^j as an int32 GPU tensor (within the aperture of
+    `optics`, if given)."""
     import torch
     lib = load()
     m_cap = int(np.ceil(float(compression) * grid.W * grid.H))
     idx = torch.empty(max(m_cap, 1), dtype=torch.int32, device="cuda")
     m = ctypes.c_int32()
-    _check(lib.hg_subset(_grid(grid), int(seed), int(j), float(compression),
+    opt = ctypes.byref(_optics(optics)) if optics is not None else None
+    _check(lib.hg_subset(_grid(grid), opt, int(seed), int(j), float(compression),
                          ctypes.c_void_p(idx.data_ptr()), ctypes.byref(m), _stream(stream)))
     return idx[:m.value]
 

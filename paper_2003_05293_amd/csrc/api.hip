@@ -193,7 +193,8 @@ hg_status single_pass(Workspace* ws, const hg::PixelSet& ps, bool from_phi, doub
   d.update = 0;
   d.from_phi = from_phi ? 1 : 0;
   d.grab_slot = 0;
-  d.inv_count = 1.0 / (double)ps.count;
+  // eq. (3): the mean over the set (the whole grid stands for the pupil)
+  d.inv_count = 1.0 / (double)(ps.idx ? ps.count : j.P);
   d.V = j.V;
   void* dev = nullptr;
   HG_TRY(ws->batch.upload_custom(&d, sizeof(d), ws->stream, &dev));
@@ -323,10 +324,13 @@ hg_status hg_metrics(const hg_grid* grid, const hg_optics* optics, const hg_spot
   HG_TRY(ws->mpart.reserve((size_t)nblk * N));
   HG_TRY(ws->V.reserve(N));
   hg::launch_metric_tables(a, in, ws->Ex.p, ws->Ey.p, ws->stream);
-  hg::launch_metric_rows(ws->Ex.p, ws->Ey.p, N, grid->W, grid->H, phi_dev, ws->mpart.p,
-                         ws->stream);
-  hg::launch_metric_reduce(ws->mpart.p, nblk, N, 1.0 / ((double)grid->W * grid->H), ws->V.p,
-                           ws->stream);
+  // the pupil: V* is the mean over Omega of A e^{i(Phi - phi_n)}
+  const int32_t ap_q = hg::aperture_bound(optics);
+  const double ill_a = hg::illumination_exponent(grid->pitch_mm, optics->waist_mm);
+  const int64_t P = hg::pupil_count(grid->W, grid->H, ap_q);
+  hg::launch_metric_rows(ws->Ex.p, ws->Ey.p, N, grid->W, grid->H, phi_dev, ap_q, ill_a,
+                         ws->mpart.p, ws->stream);
+  hg::launch_metric_reduce(ws->mpart.p, nblk, N, 1.0 / (double)P, ws->V.p, ws->stream);
   HG_TRY(check_launch());
   std::vector<double> V(2 * (size_t)N);
   HG_HIP(hipMemcpyAsync(V.data(), ws->V.p, sizeof(double2) * N, hipMemcpyDeviceToHost,
@@ -341,7 +345,8 @@ hg_status hg_metrics(const hg_grid* grid, const hg_optics* optics, const hg_spot
     lo = I < lo ? I : lo;
     hi = I > hi ? I : hi;
   }
-  *e = sum;
+  // the fraction of the power on the SLM, mean_Omega(A^2), in the spots
+  *e = sum / hg::pupil_power(grid->W, grid->H, ap_q, ill_a);
   *u = (hi + lo) > 0.0 ? 1.0 - (hi - lo) / (hi + lo) : 0.0;
   return HG_OK;
 }
@@ -361,16 +366,16 @@ hg_status hg_theta0(uint64_t seed, int32_t count, double* out_host) {
   return HG_OK;
 }
 
-hg_status hg_subset(const hg_grid* grid, uint64_t seed, int32_t j, double compression,
-                    int32_t* idx_dev, int32_t* m_out, void* stream) {
+hg_status hg_subset(const hg_grid* grid, const hg_optics* optics, uint64_t seed, int32_t j,
+                    double compression, int32_t* idx_dev, int32_t* m_out, void* stream) {
   HG_TRY(hg::validate_grid(grid));
   if (j < 1) return set_error(HG_EINVAL, "j must be >= 1");
   HG_TRY(check_compression(compression));
   if (!idx_dev || !m_out) return set_error(HG_EINVAL, "idx_dev and m_out must be non-NULL");
-  // a one-spot job carries the random order of this grid and seed
+  // a one-spot job carries the random order of this grid, pupil and seed
   const double zero = 0.0, one = 1.0;
   const hg_spots s{1, &zero, &zero, &zero, &one};
-  const hg_optics o{1.0, 1.0};
+  const hg_optics o{1.0, 1.0, 0.0, optics ? optics->aperture_px : 0.0};
   hg::JobSpec spec;
   HG_TRY(hg::make_spec(grid, &o, &s, 2, compression, seed, 0, nullptr, nullptr, &spec));
   Workspace* ws = nullptr;
@@ -380,9 +385,9 @@ hg_status hg_subset(const hg_grid* grid, uint64_t seed, int32_t j, double compre
   HG_TRY(ws->batch.build(&spec, 1, hg::TuneParams{}, ws->status.p));
   HG_TRY(ws->batch.enqueue_prologue(ws->stream));
   const hg::JobDev& jb = ws->batch.job(0);
-  hg::PixelSet ps = pixel_set(nullptr, 0, jb.M);
+  hg::PixelSet ps = pixel_set(nullptr, 0, jb.P);
   ps.perm = jb.perm;
-  ps.start = (int64_t)(j - 1) * jb.m % jb.M;
+  ps.start = (int64_t)(j - 1) * jb.m % jb.P;
   ps.count = jb.m;
   hg::launch_gather(ps, idx_dev, ws->stream);
   HG_TRY(check_launch());

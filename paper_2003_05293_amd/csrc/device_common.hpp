@@ -106,5 +106,14 @@ __device__ __forceinline__ ColumnSrc column_src(const T* base, int row_end, int 
 }
 constexpr int kDeviceScope = 1 << 4;  // buffer cache policy: device-scope coherent (sc1)
 
+// Pupil weight of a pixel (paper section 4) with Q = Lx^2 + Ly^2 in doubled
+// offsets (Qi exact, Q in FP32): 0 outside the aperture (ap_q >= 0 and
+// Qi > ap_q), else the illumination amplitude A = exp(-Q ill_a) (1 when
+// ill_a = 0).
+__device__ __forceinline__ float pupil_weight(int32_t Qi, float Q, int32_t ap_q, float ill_a) {
+  if (ap_q >= 0 && Qi > ap_q) return 0.f;
+  return ill_a > 0.f ? expf(-Q * ill_a) : 1.f;
+}
+
 }  // namespace
 }  // namespace hg

@@ -252,7 +252,7 @@ hg_status hg_engine_step(hg_engine* e, void* stream, int32_t* pending_out) {
     const hg::JobDev& j = e->slots[si].dev;
     if (j.compressed) {
       perm.push_back(hg::JobSlice{perm_blocks, (int32_t)newjobs.size()});
-      perm_blocks += hg::perm_blocks(j.M);
+      perm_blocks += hg::perm_blocks(j.P);
       max_h = std::max(max_h, j.h);
       if (j.h > 11) perm_lds = false;
     }

@@ -29,9 +29,11 @@ __device__ __forceinline__ int32_t pixel_of(const PixelSet& ps, int32_t q) {
   return q;
 }
 
-// Doubled integer offsets of pixel p from the grid centre and Q = Lx^2+Ly^2.
+// Doubled integer offsets of pixel p from the grid centre and Q = Lx^2+Ly^2
+// (also as an integer, for the aperture test).
 struct PixCoord {
   float Lx, Ly, Q;
+  int32_t Qi;
 };
 
 __device__ __forceinline__ PixCoord pixel_coord(int32_t p, int W, int H) {
@@ -42,7 +44,8 @@ __device__ __forceinline__ PixCoord pixel_coord(int32_t p, int W, int H) {
   PixCoord c;
   c.Lx = (float)lx;
   c.Ly = (float)ly;
-  c.Q = (float)(lx * lx + ly * ly);
+  c.Qi = lx * lx + ly * ly;
+  c.Q = (float)c.Qi;
   return c;
 }
 
@@ -122,12 +125,60 @@ __device__ __forceinline__ float2 backprop_field_lds(const SpotRec* recs, int n0
 
 // ---------------------------------------------------------------- setup ---
 
+// Row tables of the pupil for the random order (one block of kSetupThreads):
+// rows[j] = pupil pixels in rows 0..j-1 (j <= H), rows[H + 1 + j] = the first
+// pupil column of row j.  Each thread takes a run of consecutive rows; the
+// runs' counts are scanned in thread order.
+constexpr int kSetupThreads = 256;
+__device__ void pupil_rows(const JobDev& jb) {
+  __shared__ int32_t run_start[kSetupThreads];
+  const int per = (jb.H + kSetupThreads - 1) / kSetupThreads;
+  const int j0 = min(jb.H, (int)threadIdx.x * per), j1 = min(jb.H, j0 + per);
+  int32_t cnt = 0;
+  for (int j = j0; j < j1; ++j) {
+    int32_t i0, i1;
+    cnt += pupil_run(jb.W, jb.H, jb.ap_q, j, &i0, &i1);
+    jb.rows[jb.H + 1 + j] = i0;
+  }
+  run_start[threadIdx.x] = cnt;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t total = 0;
+    for (int t = 0; t < kSetupThreads; ++t) {
+      const int32_t c = run_start[t];
+      run_start[t] = total;
+      total += c;
+    }
+    jb.rows[jb.H] = total;  // = P
+  }
+  __syncthreads();
+  int32_t before = run_start[threadIdx.x];
+  for (int j = j0; j < j1; ++j) {
+    jb.rows[j] = before;
+    int32_t i0, i1;
+    before += pupil_run(jb.W, jb.H, jb.ap_q, j, &i0, &i1);
+  }
+}
+
+// The r-th pupil pixel in index order (r < P): the row j with
+// rows[j] <= r < rows[j + 1], then the column.
+__device__ __forceinline__ int32_t pupil_pixel(const JobDev& jb, uint32_t r) {
+  const HG_GLOBAL int32_t* rows = as_global(jb.rows);
+  int lo = 0, hi = jb.H;  // rows[lo] <= r < rows[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if ((uint32_t)rows[mid] <= r) lo = mid;
+    else hi = mid;
+  }
+  return lo * jb.W + rows[jb.H + 1 + lo] + (int32_t)(r - (uint32_t)rows[lo]);
+}
+
 // Spot coefficients in FP64, rounded once to FP32; theta^0 from Philox;
 // w = 1; pass counters cleared.  Spot values that are not finite, or
 // amplitudes that are not positive, raise the argument status flag
 // (device-resident inputs cannot be checked on the host).  Blocks with
 // blockIdx.y > 0 fill the Feistel round tables of compressed jobs.
-__global__ __launch_bounds__(256) void k_setup_batch(const JobDev* __restrict__ jobs) {
+__global__ __launch_bounds__(kSetupThreads) void k_setup_batch(const JobDev* __restrict__ jobs) {
   const JobDev& jb = jobs[blockIdx.x];
   if (blockIdx.y == 0) {
     const double lf = jb.lambda_mm * jb.focal_mm;
@@ -151,6 +202,7 @@ __global__ __launch_bounds__(256) void k_setup_batch(const JobDev* __restrict__ 
       jb.coef[n] = make_float2((float)(amp * cn), (float)(amp * sn));
     }
     for (int k = threadIdx.x; k < jb.counters_len; k += blockDim.x) jb.counters[k] = 0u;
+    if (jb.rows) pupil_rows(jb);
   }
   // the exact sums start at zero (every block of the job takes a share)
   for (int64_t k = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; k < jb.acc_len;
@@ -165,8 +217,10 @@ __global__ __launch_bounds__(256) void k_setup_batch(const JobDev* __restrict__ 
   }
 }
 
-// pi(k) for every k < M of each compressed job (and, for mixed-precision
-// jobs, the inverse: the rank of every pixel in the order).  With LDS, the Feistel
+// pi(k) for every k < P of each compressed job (and, for mixed-precision
+// jobs, the inverse: the rank of every pixel in the order).  With an
+// aperture the order runs over the P pupil pixels: pi(k) < P is the index
+// of a pupil pixel in index order, mapped to its grid pixel.  With LDS, the Feistel
 // tables (h <= 11: 48 KB) are staged in LDS; otherwise read from memory.
 //
 // The cycle walks have geometric lengths (mean 4^h / M), so a wave that gave
@@ -193,7 +247,7 @@ __global__ __launch_bounds__(kPermThreads) void k_perm_batch(const JobDev* __res
     __syncthreads();
     tab = tab_s;
   }
-  const uint32_t M = (uint32_t)jb.M;
+  const uint32_t M = (uint32_t)jb.P;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const uint32_t c0 = ((uint32_t)lb * (kPermThreads / 64) + wave) * kPermChunk;
   if (c0 >= M) return;  // whole wave
@@ -209,8 +263,11 @@ __global__ __launch_bounds__(kPermThreads) void k_perm_batch(const JobDev* __res
     ++steps;
     // the cycle of k contains k < M, so every walk ends within 4^h steps
     if (active && (y < M || steps >= cap)) {
-      jb.perm[k] = (int32_t)y;
-      if (jb.rank) jb.rank[y] = k;  // pixel y is the k-th of the random order
+      // (a walk always ends inside; the cap only bounds the loop)
+      const uint32_t yk = y < M ? y : k;
+      const int32_t p = jb.rows ? pupil_pixel(jb, yk) : (int32_t)yk;
+      jb.perm[k] = p;
+      if (jb.rank) jb.rank[p] = k;  // pixel p is the k-th of the random order
       active = false;
     }
     const uint64_t idle = __ballot(!active);
@@ -378,6 +435,11 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab, bool has_pre = fals
             const PixCoord c = pixel_coord(p, a.W, a.H);
             float sn, cs;
             sincos_turns(as_global(a.phi)[p] * 0.15915494309189535f, sn, cs);
+            if (a.ap_q >= 0 || a.ill_a > 0.f) {
+              const float wt = pupil_weight(c.Qi, c.Q, a.ap_q, a.ill_a);
+              cs *= wt;
+              sn *= wt;
+            }
             rec = make_float4(c.Lx, c.Ly, c.Q, cs);
             ui = sn;
           }
@@ -391,7 +453,7 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab, bool has_pre = fals
                               : (valid ? pixel_of(a.ps, q) : 0);
         if (dynamic && st == a.plan.sub - 1 && threadIdx.x == 0)
           ticket = atomicAdd(grab, p >= 0 ? 1u : 1u);
-        PixCoord c{0.f, 0.f, 0.f};
+        PixCoord c{0.f, 0.f, 0.f, 0};
         if (valid) c = pixel_coord(p, a.W, a.H);
         sw[wave][lane] = CHAIN ? backprop_field_lds(a.recs, n_lo, n_hi, c)
                                : backprop_field(sp, n_lo, n_hi, c);
@@ -412,6 +474,11 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab, bool has_pre = fals
               const float inv = rsqrtf(m2);
               ur = S.x * inv;
               ui = S.y * inv;
+            }
+            if (a.ap_q >= 0 || a.ill_a > 0.f) {
+              const float wt = pupil_weight(c.Qi, c.Q, a.ap_q, a.ill_a);
+              ur *= wt;
+              ui *= wt;
             }
             rec = make_float4(c.Lx, c.Ly, c.Q, ur);
           }
@@ -558,7 +625,7 @@ __device__ void pass_block_e(const PassCtx& a, unsigned* grab) {
       // the next tile is asked for once the pixel index has arrived (the
       // counter's answer is first needed after phase 1)
       if (dynamic && st == a.plan.sub - 1 && threadIdx.x == 0) ticket = atomicAdd(grab, p >= 0 ? 1u : 1u);
-      PixCoord c{0.f, 0.f, 0.f};
+      PixCoord c{0.f, 0.f, 0.f, 0};
       if (valid) c = pixel_coord(p, a.W, a.H);
       float er[MAXE], ei[MAXE];
       float Sr = 0.f, Si = 0.f;
@@ -589,6 +656,11 @@ __device__ void pass_block_e(const PassCtx& a, unsigned* grab) {
           const float inv = rsqrtf(m2);
           ur = S.x * inv;
           ui = S.y * inv;
+        }
+        if (a.ap_q >= 0 || a.ill_a > 0.f) {
+          const float wt = pupil_weight(c.Qi, c.Q, a.ap_q, a.ill_a);
+          ur *= wt;
+          ui *= wt;
         }
       }
 #pragma unroll
@@ -660,6 +732,8 @@ __global__ __launch_bounds__(kBlock, MAXU > 4 ? 2 : (MAXE > 16 ? 6 : 8)) void k_
   a.status = jb.status;
   a.update = d.update;
   a.from_phi = d.from_phi;
+  a.ill_a = jb.ill_a;
+  a.ap_q = (d.ps.perm == nullptr && d.ps.idx == nullptr) ? jb.ap_q : -1;
   // the form depends on the job alone (its N, and whether it back-propagates),
   // so a hologram gives the same bits alone and in any batch
   if constexpr (MAXE > 0) {
@@ -720,6 +794,8 @@ __global__ __launch_bounds__(kBlock, MAXU > 4 ? 2 : 6) void k_pass_chain(
     a.status = jb.status;
     a.update = d.update;
     a.from_phi = 0;
+    a.ill_a = jb.ill_a;
+    a.ap_q = (d.ps.perm == nullptr && d.ps.idx == nullptr) ? jb.ap_q : -1;
     a.chain = 1;
     a.recs = recs;
     a.gen = jb.gen;
@@ -782,9 +858,11 @@ constexpr int kMetricThreads = 128;
 constexpr int kMetricCols = 512;
 
 // V*_n partial over kMetricRows rows: sum_j Ey[j][n] * sum_i e^{i Phi(i,j)} Ex[i][n].
+// With a pupil, e^{i Phi} is weighted by A = exp(-Q ill_a) and by 0 outside
+// the aperture (Q = Lx^2 + Ly^2 > ap_q, ap_q >= 0).
 __global__ __launch_bounds__(kMetricThreads) void k_metric_rows(
     const double2* __restrict__ Ex, const double2* __restrict__ Ey, int N, int W, int H,
-    const float* __restrict__ phi, double2* __restrict__ partial) {
+    const float* __restrict__ phi, int32_t ap_q, double ill_a, double2* __restrict__ partial) {
   __shared__ double2 u[kMetricCols];
   const int j0 = blockIdx.x * kMetricRows;
   for (int n0 = 0; n0 < N; n0 += kMetricThreads) {
@@ -800,6 +878,13 @@ __global__ __launch_bounds__(kMetricThreads) void k_metric_rows(
         for (int k = threadIdx.x; k < cols; k += kMetricThreads) {
           double s, c;
           sincos((double)phi[(int64_t)j * W + i0 + k], &s, &c);
+          if (ap_q >= 0 || ill_a > 0.0) {
+            const int64_t lx = 2 * (int64_t)(i0 + k) - (W - 1), ly = 2 * (int64_t)j - (H - 1);
+            const int64_t Q = lx * lx + ly * ly;
+            const double wt = (ap_q >= 0 && Q > ap_q) ? 0.0 : (ill_a > 0.0 ? exp(-(double)Q * ill_a) : 1.0);
+            c *= wt;
+            s *= wt;
+          }
           u[k] = make_double2(c, s);
         }
         __syncthreads();
@@ -871,7 +956,7 @@ int setup_table_blocks(int max_h) {
 
 void launch_setup_batch(const JobDev* jobs, int njobs, int max_h, hipStream_t s) {
   if (njobs <= 0) return;
-  hipLaunchKernelGGL(k_setup_batch, dim3(njobs, 1 + setup_table_blocks(max_h)), dim3(256), 0, s,
+  hipLaunchKernelGGL(k_setup_batch, dim3(njobs, 1 + setup_table_blocks(max_h)), dim3(kSetupThreads), 0, s,
                      jobs);
 }
 
@@ -984,9 +1069,10 @@ void launch_metric_tables(const SetupArgs& a, const SpotPtrs& in, double2* Ex, d
 int metric_blocks(int H) { return ceil_div(H, kMetricRows); }
 
 void launch_metric_rows(const double2* Ex, const double2* Ey, int N, int W, int H,
-                        const float* phi, double2* partial, hipStream_t s) {
+                        const float* phi, int32_t ap_q, double ill_a, double2* partial,
+                        hipStream_t s) {
   hipLaunchKernelGGL(k_metric_rows, dim3(metric_blocks(H)), dim3(kMetricThreads), 0, s, Ex, Ey,
-                     N, W, H, phi, partial);
+                     N, W, H, phi, ap_q, ill_a, partial);
 }
 
 void launch_metric_reduce(const double2* partial, int nblk, int N, double inv_count,

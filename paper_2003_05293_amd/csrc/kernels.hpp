@@ -9,6 +9,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 
 namespace hg {
@@ -62,9 +63,54 @@ int sum_shift(int64_t pixels);
 PassPlan plan_pass(int32_t count, int32_t block_cap);
 constexpr int32_t kDefaultBlockCap = 4096;
 
+// Pupil of the setup (paper section 4): a round aperture of diameter D
+// pixels and a Gaussian illumination.  With doubled offsets the aperture
+// holds the pixels with Lx^2 + Ly^2 <= q, q = floor(D^2) (Lx, Ly, q
+// integers), and in row j (Ly = 2j - (H-1)) these are the columns of one
+// run: |Lx| <= s with s = floor(sqrt(q - Ly^2)).  Shared by the host (pupil
+// size) and the setup kernel (row tables of the random order).
+__host__ __device__ inline int64_t isqrt64(int64_t t) {
+  int64_t s = (int64_t)sqrt((double)t);
+  while (s * s > t) --s;
+  while ((s + 1) * (s + 1) <= t) ++s;
+  return s;
+}
+// Columns [*i0, *i1] of row j inside the aperture (q < 0: no aperture, the
+// whole row); returns the count (0: none, and then *i0 > *i1).
+__host__ __device__ inline int32_t pupil_run(int32_t W, int32_t H, int32_t q, int32_t j,
+                                             int32_t* i0, int32_t* i1) {
+  if (q < 0) {
+    *i0 = 0;
+    *i1 = W - 1;
+    return W;
+  }
+  const int64_t ly = 2 * (int64_t)j - (H - 1);
+  const int64_t t = (int64_t)q - ly * ly;
+  if (t < 0) {
+    *i0 = 1;
+    *i1 = 0;
+    return 0;
+  }
+  const int64_t s = isqrt64(t);
+  // Lx = 2i - (W-1) in [-s, s]
+  const int64_t lo = (W - 1) - s, hi = (W - 1) + s;
+  const int64_t a = lo <= 0 ? 0 : (lo + 1) / 2;
+  const int64_t b = hi / 2 < W - 1 ? hi / 2 : W - 1;
+  *i0 = (int32_t)a;
+  *i1 = (int32_t)b;
+  return b >= a ? (int32_t)(b - a + 1) : 0;
+}
+
 // One hologram resident on the device.
 struct JobDev {
   int32_t W, H, N, M;
+  int32_t P;           // pixels of the pupil Omega (M without an aperture):
+                       // the full pass's count and the random order's length
+  int32_t ap_q;        // aperture: the pixels with Lx^2 + Ly^2 <= ap_q (-1: all)
+  float ill_a;         // illumination A = exp(-Q ill_a), Q = Lx^2 + Ly^2 (0: A = 1)
+  int32_t* rows;       // [2H + 1] (aperture and a random order): pupil pixels
+                       // before row j (j <= H), then the first pupil column
+                       // of each row
   int32_t iterations;
   int32_t m;           // pixels of a compressed pass (M if not compressed)
   int32_t compressed;  // 1: passes 1..I-1 use windows of the random order
@@ -75,7 +121,7 @@ struct JobDev {
   SpotRec* sp;         // [N] iteration state
   float2* coef;        // [N] C_n = A_n e^{i 2 pi th_n}, kept with the state
   uint32_t* tab;       // [6 << h] Feistel tables (compressed only)
-  int32_t* perm;       // [M] random pixel order (compressed only)
+  int32_t* perm;       // [P] random pixel order (compressed only)
   float* phi;          // [H][W] output hologram (or input of a forward test pass)
   float2* partial;     // [max pass tiles][N] (mixed-precision passes)
   double2* gpart;      // [max pass groups][N] (mixed-precision passes)
@@ -112,8 +158,10 @@ struct JobDev {
   uint32_t* rank;      // [M] position of each pixel in the random order
 };
 
-// Pixel set of a pass: all pixels 0..count-1 (perm == idx == nullptr),
-// perm[(start + q) mod M] for q < count, or explicit indices idx[q].
+// Pixel set of a pass: all pixels 0..count-1 (perm == idx == nullptr; with
+// an aperture the pixels outside it are weighted 0, so the set is Omega),
+// perm[(start + q) mod M] for q < count (M: the order's length), or
+// explicit indices idx[q].
 struct PixelSet {
   const int32_t* perm;
   const int32_t* idx;
@@ -267,8 +315,10 @@ struct SetupArgs {
 void launch_metric_tables(const SetupArgs& a, const SpotPtrs& in, double2* Ex, double2* Ey,
                           hipStream_t s);
 int metric_blocks(int H);
+// ap_q, ill_a: the pupil (JobDev), ill_a here in FP64.
 void launch_metric_rows(const double2* Ex, const double2* Ey, int N, int W, int H,
-                        const float* phi, double2* partial, hipStream_t s);
+                        const float* phi, int32_t ap_q, double ill_a, double2* partial,
+                        hipStream_t s);
 void launch_metric_reduce(const double2* partial, int nblk, int N, double inv_count,
                           double2* V_out, hipStream_t s);
 

@@ -323,7 +323,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_mx_pass(const JobDev* __restrict_
 
   // ranks of this lane's pixels in the random order (window membership),
   // loaded first so that they arrive during the products
-  const int M = jb.M;
+  const int M = jb.P;  // length of the random order
   const bool windowed = MODE == kMxIterate && d.count < M;
   uint32_t rk[kMxCB][4];
 #pragma unroll
@@ -372,7 +372,9 @@ __global__ __launch_bounds__(kBlock, 3) void k_mx_pass(const JobDev* __restrict_
     return;
   }
 
-  // u = e^{i Phi} on the pixel set, 0 elsewhere, as half pairs in LDS.
+  // u = e^{i Phi} on the pixel set (within the pupil), 0 elsewhere, weighted
+  // by the illumination, as half pairs in LDS.
+  const bool pupil = jb.ap_q >= 0 || jb.ill_a > 0.f;
 #pragma unroll
   for (int t = 0; t < kMxCB; ++t)
 #pragma unroll
@@ -381,8 +383,14 @@ __global__ __launch_bounds__(kBlock, 3) void k_mx_pass(const JobDev* __restrict_
       uint32_t uh = 0u;
       if (row < H && col < W) {
         const int32_t p = row * W + col;
-        bool in = true;
-        if (windowed) {
+        float wt = 1.f;
+        if (pupil) {
+          const int32_t lx = 2 * col - (W - 1), ly = 2 * row - (H - 1);
+          const int32_t Qi = lx * lx + ly * ly;
+          wt = pupil_weight(Qi, (float)Qi, jb.ap_q, jb.ill_a);
+        }
+        bool in = wt != 0.f;  // outside the aperture: never in a set
+        if (in && windowed) {
           int64_t k = (int64_t)rk[t][r] - d.start;
           if (k < 0) k += M;
           in = k < d.count;
@@ -398,6 +406,10 @@ __global__ __launch_bounds__(kBlock, 3) void k_mx_pass(const JobDev* __restrict_
               ur = sr[t][r] * inv;
               ui = si[t][r] * inv;
             }
+          }
+          if (pupil) {
+            ur *= wt;
+            ui *= wt;
           }
           uh = pack_h2(ur, ui);
         }

@@ -273,7 +273,9 @@ __global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ 
     return;
   }
 
-  // u = e^{i Phi} over the grid (0 outside it), in LDS.
+  // u = e^{i Phi} over the pupil (0 outside it and outside the grid),
+  // weighted by the illumination, in LDS.
+  const bool pupil = jb.ap_q >= 0 || jb.ill_a > 0.f;
 #pragma unroll
   for (int t = 0; t < kSepCB; ++t)
 #pragma unroll
@@ -286,6 +288,13 @@ __global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ 
         if (m2 > 0.f) {
           const float inv = rsqrtf(m2);
           u = make_float2(sr[t][r] * inv, si[t][r] * inv);
+        }
+        if (pupil) {
+          const int32_t lx = 2 * col - (W - 1), ly = 2 * row - (H - 1);
+          const int32_t Qi = lx * lx + ly * ly;
+          const float wt = pupil_weight(Qi, (float)Qi, jb.ap_q, jb.ill_a);
+          u.x *= wt;
+          u.y *= wt;
         }
       }
       us[wave][4 * lg + r][16 * t + lr] = u;

@@ -30,6 +30,10 @@ struct PassCtx {
   double2* V;
   int32_t* status;
   int update, from_phi;
+  // pupil: forward terms weighted by the illumination (ill_a > 0), and
+  // pixels outside the aperture dropped (ap_q >= 0: the whole-grid set)
+  int32_t ap_q = -1;
+  float ill_a = 0.f;
   // chained launches: the pass's spot state in LDS, and the generation word
   // to publish after the update
   int chain = 0;

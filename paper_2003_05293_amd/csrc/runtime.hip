@@ -72,11 +72,60 @@ hg_status validate_grid(const hg_grid* g) {
   return HG_OK;
 }
 
+int32_t aperture_bound(const hg_optics* o) {
+  const double D = o->aperture_px;
+  if (!(D > 0.0)) return -1;
+  const double q = std::floor(D * D);  // Lx^2 + Ly^2 <= D^2 for integers
+  return q >= 2147483647.0 ? 2147483647 : (int32_t)q;
+}
+
+int64_t pupil_count(int32_t W, int32_t H, int32_t q) {
+  int64_t n = 0;
+  for (int32_t j = 0; j < H; ++j) {
+    int32_t i0, i1;
+    n += pupil_run(W, H, q, j, &i0, &i1);
+  }
+  return n;
+}
+
+double illumination_exponent(double pitch_mm, double waist_mm) {
+  // A = exp(-(x'^2 + y'^2) / w^2) with x'^2 + y'^2 = Q pitch^2 / 4
+  return waist_mm > 0.0 ? pitch_mm * pitch_mm / (4.0 * waist_mm * waist_mm) : 0.0;
+}
+
+double pupil_power(int32_t W, int32_t H, int32_t q, double ill_a) {
+  if (!(ill_a > 0.0)) return 1.0;
+  // A^2 = exp(-2 a Lx^2) exp(-2 a Ly^2), summed over each row's run
+  std::vector<double> ex((size_t)W);
+  for (int32_t i = 0; i < W; ++i) {
+    const double lx = 2.0 * i - (W - 1);
+    ex[(size_t)i] = std::exp(-2.0 * ill_a * lx * lx);
+  }
+  double total = 0.0;
+  int64_t count = 0;
+  for (int32_t j = 0; j < H; ++j) {
+    int32_t i0, i1;
+    const int32_t c = pupil_run(W, H, q, j, &i0, &i1);
+    if (c == 0) continue;
+    const double ly = 2.0 * j - (H - 1);
+    double row = 0.0;
+    for (int32_t i = i0; i <= i1; ++i) row += ex[(size_t)i];
+    total += row * std::exp(-2.0 * ill_a * ly * ly);
+    count += c;
+  }
+  return total / (double)count;
+}
+
 hg_status validate_spec(const hg_grid* g, const hg_optics* o, const hg_spots* s, bool on_device) {
   if (!g || !o || !s) return set_error(HG_EINVAL, "grid, optics and spots must be non-NULL");
   HG_TRY(validate_grid(g));
   if (!finite_pos(o->lambda_mm) || !finite_pos(o->focal_mm))
     return set_error(HG_EINVAL, "lambda_mm and focal_mm must be positive and finite");
+  if (!std::isfinite(o->waist_mm) || !(o->waist_mm >= 0.0) || !std::isfinite(o->aperture_px) ||
+      !(o->aperture_px >= 0.0))
+    return set_error(HG_EINVAL, "waist_mm and aperture_px must be finite and >= 0");
+  if (pupil_count(g->W, g->H, aperture_bound(o)) == 0)
+    return set_error(HG_EINVAL, "the aperture contains no pixel");
   if (s->n < 1 || s->n > HG_MAX_SPOTS)
     return set_error(HG_EINVAL, "spot count must be in [1, HG_MAX_SPOTS]");
   if (!s->x_mm || !s->y_mm || !s->z_mm || !s->amp)
@@ -104,6 +153,9 @@ hg_status make_spec(const hg_grid* g, const hg_optics* o, const hg_spots* s, int
   j.pitch_mm = g->pitch_mm;
   j.lambda_mm = o->lambda_mm;
   j.focal_mm = o->focal_mm;
+  j.waist_mm = o->waist_mm;
+  j.ap_q = aperture_bound(o);
+  j.pupil_n = (int32_t)pupil_count(g->W, g->H, j.ap_q);
   j.N = s->n;
   j.x = s->x_mm;
   j.y = s->y_mm;
@@ -234,10 +286,14 @@ JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev
   j.H = s.H;
   j.N = s.N;
   j.M = s.W * s.H;
+  j.P = s.pupil_n > 0 ? s.pupil_n : j.M;
+  j.ap_q = s.ap_q;
+  j.ill_a = (float)illumination_exponent(s.pitch_mm, s.waist_mm);
   j.iterations = s.iterations;
   j.compressed = (s.compression > 0.0 && s.iterations >= 2) ? 1 : 0;
-  j.m = j.compressed ? (int32_t)std::ceil(s.compression * (double)j.M) : j.M;
-  j.h = j.compressed ? half_bits(j.M) : 0;
+  // the random order runs over the pupil's P pixels
+  j.m = j.compressed ? (int32_t)std::ceil(s.compression * (double)j.P) : j.P;
+  j.h = j.compressed ? half_bits(j.P) : 0;
   j.seed = s.seed;
   j.pitch_mm = s.pitch_mm;
   j.lambda_mm = s.lambda_mm;
@@ -296,7 +352,8 @@ JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev
   L.off_sp = take(sizeof(SpotRec) * (size_t)s.N);
   L.off_coef = take(sizeof(float2) * (size_t)s.N);
   L.off_tab = j.compressed ? take(sizeof(uint32_t) * ((size_t)kFeistelRoundsHost << j.h)) : 0;
-  L.off_perm = j.compressed ? take(sizeof(int32_t) * (size_t)j.M) : 0;
+  L.off_perm = j.compressed ? take(sizeof(int32_t) * (size_t)j.P) : 0;
+  L.off_rows = (j.compressed && j.ap_q >= 0) ? take(sizeof(int32_t) * (2 * (size_t)j.H + 1)) : 0;
   if (j.mixed) {
     const size_t ops = (size_t)j.mx_steps * 64;  // operand groups per 16-row/column block
     L.off_mxFc = take(16 * ops * j.mx_cblocks);
@@ -338,6 +395,7 @@ JobDev bind_job(const JobLayout& L, const JobSpec& s, char* base, const double* 
   j.coef = reinterpret_cast<float2*>(base + L.off_coef);
   j.tab = j.compressed ? reinterpret_cast<uint32_t*>(base + L.off_tab) : nullptr;
   j.perm = j.compressed ? reinterpret_cast<int32_t*>(base + L.off_perm) : nullptr;
+  j.rows = (j.compressed && j.ap_q >= 0) ? reinterpret_cast<int32_t*>(base + L.off_rows) : nullptr;
   j.partial = j.mixed ? reinterpret_cast<float2*>(base + L.off_partial) : nullptr;
   j.gpart = j.mixed ? reinterpret_cast<double2*>(base + L.off_gpart) : nullptr;
   j.acc = j.mixed ? nullptr : reinterpret_cast<unsigned long long*>(base + L.off_acc);
@@ -366,17 +424,18 @@ PassDesc iteration_desc(const JobDev& j, const JobLayout& L, int it, int index, 
   PassDesc d;
   d.block_begin = block_begin;
   d.job = index;
-  d.ps = all_pixels(j.M);
+  d.ps = all_pixels(j.M);  // the whole grid: the pupil weights drop the pixels outside it
   if (sub) {
     d.ps.perm = j.perm;
-    d.ps.start = (int64_t)(it - 1) * j.m % j.M;
+    d.ps.start = (int64_t)(it - 1) * j.m % j.P;
     d.ps.count = j.m;
+    d.ps.M = j.P;
   }
   d.plan = sub ? L.plan_sub : L.plan_all;
   d.update = 1;
   d.from_phi = 0;
   d.grab_slot = it;
-  d.inv_count = 1.0 / (double)d.ps.count;
+  d.inv_count = 1.0 / (double)(sub ? j.m : j.P);  // eq. (3): the mean over the set
   d.V = j.V + (j.trace ? (size_t)(it - 1) * j.N : 0);
   return d;
 }
@@ -392,7 +451,7 @@ SepDesc sep_desc(const JobDev& j, const JobLayout& L, int index, int block_begin
   d.tiles_y = (j.H + kSepTileH - 1) / kSepTileH;
   d.plan = L.plan_sep;
   d.update = 0;
-  d.inv_count = 1.0 / (double)j.M;
+  d.inv_count = 1.0 / (double)j.P;
   d.V = j.V;
   d.out = nullptr;
   return d;
@@ -408,9 +467,9 @@ MxDesc mx_desc(const JobDev& j, const JobLayout& L, int index, int block_begin) 
   d.tiles_y = (j.H + kMxTile - 1) / kMxTile;
   d.plan = L.plan_mx;
   d.start = 0;
-  d.count = j.M;
+  d.count = j.P;  // the pupil (every pixel without an aperture)
   d.update = 0;
-  d.inv_count = 1.0f / (float)j.M;
+  d.inv_count = 1.0f / (float)j.P;
   d.V = j.V;
   d.out = nullptr;
   return d;
@@ -429,7 +488,7 @@ void LaunchSet::add_iteration(const JobDev& j, const JobLayout& L, int it, int i
   if (j.mixed) {
     MxDesc d = mx_desc(j, L, index, mx_blocks);
     if (sub) {
-      d.start = (int64_t)(it - 1) * j.m % j.M;
+      d.start = (int64_t)(it - 1) * j.m % j.P;
       d.count = j.m;
       d.inv_count = 1.0f / (float)j.m;
     }
@@ -593,7 +652,7 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
     if (j.phi) final_.add_final(j, layouts_[i], i);
     if (j.compressed) {
       perm_.push_back(JobSlice{perm_blocks_, i});
-      perm_blocks_ += perm_blocks(j.M);
+      perm_blocks_ += perm_blocks(j.P);
     }
     if (j.mixed) {
       mxtab_.push_back(JobSlice{mxtab_blocks_, i});

@@ -66,6 +66,9 @@ struct Staging {
 struct JobSpec {
   int32_t W = 0, H = 0;
   double pitch_mm = 0, lambda_mm = 0, focal_mm = 0;
+  double waist_mm = 0;      // illumination waist (0: uniform)
+  int32_t ap_q = -1;        // aperture bound on Lx^2 + Ly^2 (-1: none)
+  int32_t pupil_n = 0;      // pixels of the pupil (W*H without an aperture)
   int32_t N = 0;
   const double *x = nullptr, *y = nullptr, *z = nullptr, *amp = nullptr;
   bool spots_on_device = false;
@@ -88,6 +91,15 @@ struct TuneParams {
   bool chain_passes = false;   // chained launch of a single job's compressed passes
 };
 
+// Pupil of an hg_optics (validated): the aperture bound q = floor(D^2)
+// (-1 without an aperture), the pupil's pixel count, the FP64 illumination
+// exponent pitch^2 / (4 w^2) per unit of Q (0 without a waist), and the
+// power mean_Omega(A^2) (1 without a waist).
+int32_t aperture_bound(const hg_optics* o);
+int64_t pupil_count(int32_t W, int32_t H, int32_t q);
+double illumination_exponent(double pitch_mm, double waist_mm);
+double pupil_power(int32_t W, int32_t H, int32_t q, double ill_a);
+
 // Validation of the host-visible parts of a hologram description.
 hg_status validate_grid(const hg_grid* g);
 hg_status validate_spec(const hg_grid* g, const hg_optics* o, const hg_spots* s, bool on_device);
@@ -103,7 +115,7 @@ struct JobLayout {
   size_t off_raw = 0, off_sp = 0, off_coef = 0, off_tab = 0, off_perm = 0, off_partial = 0,
          off_gpart = 0, off_acc = 0, off_counters = 0, off_V = 0, off_sepFc = 0, off_sepFn = 0,
          off_sepGa = 0, off_sepGv = 0, off_mxFc = 0, off_mxFn = 0, off_mxGa = 0, off_mxGv = 0,
-         off_rank = 0;
+         off_rank = 0, off_rows = 0;
   size_t bytes = 0;
   bool raw_inline = false;  // the job's own scratch holds a copy of its spot arrays
   int grab_offset = 0;      // the pass tile counters follow the group counters

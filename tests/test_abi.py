@@ -39,9 +39,10 @@ def test_version(lib):
     assert "gfx950" in hg.version()
 
 
-def _args(W=64, H=48, pitch=9.2e-3, lam=0.488e-3, f=20.0, n=3, x=None, amp=None):
+def _args(W=64, H=48, pitch=9.2e-3, lam=0.488e-3, f=20.0, n=3, x=None, amp=None, waist=0.0,
+          aperture=0.0):
     g = hg._Grid(W, H, pitch)
-    o = hg._Optics(lam, f)
+    o = hg._Optics(lam, f, waist, aperture)
     xs = np.zeros(n) if x is None else np.asarray(x, dtype=np.float64)
     a = np.full(n, 0.5) if amp is None else np.asarray(amp, dtype=np.float64)
     keep = [xs, np.zeros(n), np.zeros(n), a]
@@ -66,6 +67,12 @@ def call_rs(lib, g, o, s, phi=1):
     (dict(x=[0.0, math.nan, 0.0]), "coordinates"),
     (dict(amp=[0.5, 0.0, 0.5]), "amplitudes"),
     (dict(amp=[0.5, -1.0, 0.5]), "amplitudes"),
+    (dict(waist=-1.0), "waist_mm"),
+    (dict(waist=math.nan), "waist_mm"),
+    (dict(aperture=-2.0), "aperture_px"),
+    (dict(aperture=math.inf), "aperture_px"),
+    # even W and H: the nearest pixel centres have Lx^2 + Ly^2 = 2 > 1.4^2
+    (dict(aperture=1.4), "no pixel"),
 ])
 def test_rs_rejects(lib, kw, msg):
     g, o, s, keep = _args(**kw)
@@ -102,8 +109,12 @@ def test_test_hook_validation(lib):
     assert lib.hg_theta0(1, 0, out.ctypes.data_as(hg._DP)) == 1
     assert lib.hg_theta0(1, 4097, out.ctypes.data_as(hg._DP)) == 1
     m = ctypes.c_int32()
-    assert lib.hg_subset(G, 1, 0, 0.5, ctypes.c_void_p(1), ctypes.byref(m), None) == 1
-    assert lib.hg_subset(G, 1, 1, 0.0, ctypes.c_void_p(1), ctypes.byref(m), None) == 1
+    assert lib.hg_subset(G, None, 1, 0, 0.5, ctypes.c_void_p(1), ctypes.byref(m), None) == 1
+    assert lib.hg_subset(G, O, 1, 1, 0.0, ctypes.c_void_p(1), ctypes.byref(m), None) == 1
+    bad = hg._Optics(0.488e-3, 20.0, 0.0, math.nan)
+    assert lib.hg_subset(G, ctypes.byref(bad), 1, 1, 0.5, ctypes.c_void_p(1), ctypes.byref(m),
+                         None) == 1
+    assert "aperture_px" in hg.last_error()
     V = np.zeros(6)
     # idx given with m out of range
     assert lib.hg_forward(G, O, S, ctypes.c_void_p(1), ctypes.c_void_p(1), 0, 0,
