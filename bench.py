@@ -153,37 +153,41 @@ def kernel_times(hg, run, count):
     return kern
 
 
-def single_form(hg, grid, clouds, spots_dev, phis, stream, form, steps, warmup, gold, tune):
-    """One hologram per call on one stream in the given precision, with its
-    e, u error against the stored FP64 oracle result of the seed-0 cloud."""
+def single_form(hg, grid, clouds, spots_dev, phis, stream, form, steps, warmup, gold, tune,
+                optics=None, label=None):
+    """One hologram per call on one stream in the given precision (and
+    optics: the uniform full grid by default), with its e, u error against
+    the stored FP64 oracle result of the seed-0 cloud."""
     import torch
     from workload import OPTICS
+    if optics is None:
+        optics = OPTICS
     for k in range(warmup):
-        hg.cswgs_device(grid, OPTICS, spots_dev[k % CLOUDS], ITER, COMP, k % CLOUDS,
+        hg.cswgs_device(grid, optics, spots_dev[k % CLOUDS], ITER, COMP, k % CLOUDS,
                         phi=phis[k % CLOUDS], stream=stream, precision=form, tune=tune)
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     a.record(stream)
     for k in range(steps):
-        hg.cswgs_device(grid, OPTICS, spots_dev[k % CLOUDS], ITER, COMP, k % CLOUDS,
+        hg.cswgs_device(grid, optics, spots_dev[k % CLOUDS], ITER, COMP, k % CLOUDS,
                         phi=phis[k % CLOUDS], stream=stream, precision=form, tune=tune)
     b.record(stream)
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / steps
     kern = kernel_times(hg, lambda k: hg.cswgs_device(
-        grid, OPTICS, spots_dev[k % CLOUDS], ITER, COMP, k % CLOUDS, phi=phis[k % CLOUDS],
+        grid, optics, spots_dev[k % CLOUDS], ITER, COMP, k % CLOUDS, phi=phis[k % CLOUDS],
         stream=stream, precision=form, tune=tune), min(steps, 10))
-    hg.cswgs_device(grid, OPTICS, spots_dev[0], ITER, COMP, 0, phi=phis[0], stream=stream,
+    hg.cswgs_device(grid, optics, spots_dev[0], ITER, COMP, 0, phi=phis[0], stream=stream,
                     precision=form, tune=tune)
-    e, u, _ = hg.metrics(grid, OPTICS, clouds[0], phis[0])
+    e, u, _ = hg.metrics(grid, optics, clouds[0], phis[0])
     out = {"holograms_per_s": round(1000.0 / ms, 3), "ms_per_hologram": round(ms, 5),
            "how": "one hologram per call, back to back on one stream", "e": e, "u": u,
            "kernels": {k: {"avg_us": round(v["avg_us"], 3), "launches_per_hologram":
                            v["launches"] / min(steps, 10)} for k, v in kern.items()}}
     if gold is not None:
         out.update({"e_abs_err": abs(e - gold["e"]), "u_abs_err": abs(u - gold["u"])})
-    print(f"[bench] {form}: {ms:.4f} ms per hologram, e {e:.6f} u {u:.6f}", file=sys.stderr,
-          flush=True)
+    print(f"[bench] {label or form}: {ms:.4f} ms per hologram, e {e:.6f} u {u:.6f}",
+          file=sys.stderr, flush=True)
     return out
 
 
@@ -415,6 +419,19 @@ def main():
     other = "mixed" if args.form == "fp32" else "fp32"
     forms[other] = single_form(hg, grid, clouds, spots_dev, phis, stream, other, args.steps,
                                args.warmup, gd, tune)
+    # the same workload under the paper's pupil (Gaussian illumination of
+    # 6 mm waist on the round 1152-pixel aperture)
+    from workload import PUPIL_OPTICS
+    pgold = os.path.join(ROOT, "tests", "golden", "cswgs_1152x1152_n100_i30_c16_pupil_seed0.json")
+    pgd = None
+    if os.path.exists(pgold):
+        with open(pgold) as f:
+            pgd = json.load(f)
+    forms["fp32_pupil"] = single_form(hg, grid, clouds, spots_dev, phis, stream, "fp32",
+                                      args.steps, args.warmup, pgd, tune, optics=PUPIL_OPTICS,
+                                      label="fp32 pupil")
+    forms["fp32_pupil"]["optics"] = {"waist_mm": PUPIL_OPTICS.waist_mm,
+                                     "aperture_px": PUPIL_OPTICS.aperture_px}
     if not args.no_batched:
         forms.update(batched_forms(hg, grid, OPTICS, args.steps, args.batch))
     if args.serve_seconds > 0:
