@@ -269,6 +269,28 @@ def served_form(hg, optics, seconds):
                    "continuous batching, latency arrival -> observed completion"}
 
 
+def budget_sweep(hg):
+    """The paper's algorithm comparison at a fixed amount of work, on the
+    scenario stand-ins at 1152^2 under the paper's pupil (10 orientations and
+    theta^0 each); e and u as mean +- std, and the GPU time per hologram."""
+    from paper_2003_05293_amd import budget
+    from workload import Grid, PUPIL_OPTICS
+    t0 = time.perf_counter()
+    res = budget.sweep(Grid(W, H), PUPIL_OPTICS, ("grid100", "grid36", "cubes"), repeats=10)
+    out = {}
+    for name, rows in res.items():
+        out[name] = [{"algorithm": r["algorithm"], "c": r["compression"], "I": r["iterations"],
+                      "e": [round(r["e"]["mean"], 5), round(r["e"]["std"], 5)],
+                      "u": [round(r["u"]["mean"], 5), round(r["u"]["std"], 5)],
+                      "ms_per_hologram": round(r["ms_per_hologram"], 4)} for r in rows]
+    print(f"[bench] budget sweep: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    return {"budget_terms_per_pixel": budget.BUDGET_TERMS_PER_PIXEL, "repeats": 10,
+            "grid": [W, H], "optics": "pupil: waist 6 mm, aperture 1152 px",
+            "how": "every algorithm at the largest iteration count within the budget of "
+                   "(pixel, spot) terms; e, u mean and std over 10 orientations and theta^0",
+            "results": out}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -280,12 +302,20 @@ def main():
     ap.add_argument("--batch", type=int, default=32, help="holograms per batched launch")
     ap.add_argument("--serve-seconds", type=float, default=30.0,
                     help="length of the served Poisson stream (0: skip)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="time the headline workload only (no other forms, sweep or CPU leg); "
+                         "for profiling runs")
+    ap.add_argument("--no-budget-sweep", action="store_true",
+                    help="skip the fixed-work comparison of RS, WGS and CS-WGS on the scenarios")
     ap.add_argument("--no-autotune", action="store_true",
                     help="default launch parameters instead of the autotuned ones")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device to device three times (counter calibration) "
                          "and exit")
     args = ap.parse_args()
+    if args.headline_only:
+        args.no_batched = args.no_budget_sweep = args.no_cpu_baseline = True
+        args.serve_seconds = 0.0
     if args.calibrate_copy > 0:
         import torch
         n = args.calibrate_copy << 18  # float32 elements
@@ -417,8 +447,9 @@ def main():
                          "ms_per_hologram": round(ms_per_step, 5),
                          "how": "one hologram per call, back to back on one stream"}}
     other = "mixed" if args.form == "fp32" else "fp32"
-    forms[other] = single_form(hg, grid, clouds, spots_dev, phis, stream, other, args.steps,
-                               args.warmup, gd, tune)
+    if not args.headline_only:
+        forms[other] = single_form(hg, grid, clouds, spots_dev, phis, stream, other, args.steps,
+                                   args.warmup, gd, tune)
     # the same workload under the paper's pupil (Gaussian illumination of
     # 6 mm waist on the round 1152-pixel aperture)
     from workload import PUPIL_OPTICS
@@ -427,15 +458,20 @@ def main():
     if os.path.exists(pgold):
         with open(pgold) as f:
             pgd = json.load(f)
-    forms["fp32_pupil"] = single_form(hg, grid, clouds, spots_dev, phis, stream, "fp32",
-                                      args.steps, args.warmup, pgd, tune, optics=PUPIL_OPTICS,
-                                      label="fp32 pupil")
-    forms["fp32_pupil"]["optics"] = {"waist_mm": PUPIL_OPTICS.waist_mm,
-                                     "aperture_px": PUPIL_OPTICS.aperture_px}
+    if not args.headline_only:
+        forms["fp32_pupil"] = single_form(hg, grid, clouds, spots_dev, phis, stream, "fp32",
+                                          args.steps, args.warmup, pgd, tune,
+                                          optics=PUPIL_OPTICS, label="fp32 pupil")
+        forms["fp32_pupil"]["optics"] = {"waist_mm": PUPIL_OPTICS.waist_mm,
+                                         "aperture_px": PUPIL_OPTICS.aperture_px}
     if not args.no_batched:
         forms.update(batched_forms(hg, grid, OPTICS, args.steps, args.batch))
     if args.serve_seconds > 0:
         forms["fp32_served"] = served_form(hg, OPTICS, args.serve_seconds)
+
+    sweep = None
+    if not args.no_budget_sweep:
+        sweep = budget_sweep(hg)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -452,6 +488,7 @@ def main():
                    "spots": "resident in HBM", "tune": tune,
                    "tune_sweep_ms": {k: round(v, 4) for k, v in tuned["sweep_ms"].items()}},
         "roofline": roofline, "accuracy": accuracy, "forms": forms, "cpu_baseline": cpu,
+        "budget_sweep": sweep,
     }
     print(json.dumps(line), flush=True)
 

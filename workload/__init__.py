@@ -9,3 +9,6 @@ from .spots import (  # noqa: F401
     Grid, Optics, Spots, OPTICS, PUPIL_OPTICS, PITCH_MM, lateral_half_range_mm,
     spot_cloud, mixed_batch, poisson_stream, Workload, WORKLOADS, PUPIL_WORKLOAD,
 )
+from .scenarios import (  # noqa: F401
+    SCENARIOS, random_rotation, rotating_grid, two_cubes, scenario,
+)
