@@ -14,6 +14,7 @@ Parity status of each function is stated in the module headers:
                (tests/test_oracle_*.py); the full CS-WGS trajectory has no
                printed worked example in the paper and is pinned only
                through those pieces.
+  slm.py     - phase-to-gray lookup, pinned by exact arithmetic on the bins
 """
 from .philox import philox4x64_10, PHILOX_M, PHILOX_W  # noqa: F401
 from .sampler import (  # noqa: F401
@@ -23,3 +24,4 @@ from .hg import (  # noqa: F401
     pixel_offsets_mm, spot_phase, backward, forward, update, rs, wgs, cswgs,
     metrics, Trace, pupil_pixels, illumination,
 )
+from .slm import gray_index, gray_levels  # noqa: F401
