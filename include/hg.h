@@ -152,6 +152,16 @@ typedef struct hg_tune {
   int32_t chain_passes;
 } hg_tune;
 
+/* Phase-to-gray lookup table of the SLM (GPU implementation section: a
+ * fixed parameter of the SLM, uploaded to the device once at start-up and
+ * used for every hologram).  levels gray values g[0..levels-1] cover one
+ * phase period: bin k holds the phases Phi (radians, any real) with
+ * k/levels <= frac(Phi / 2 pi) < (k+1)/levels.  The bin is decided in FP32:
+ * t = fl(Phi * fl(1/(2 pi))), t = fl(t - floor(t)), k = min(floor(fl(t *
+ * levels)), levels - 1).  bits: 8 (gray images of uint8) or 16 (uint16).
+ * The table lives on the device that is current at creation. */
+typedef struct hg_lut hg_lut;
+
 typedef struct hg_params {
   int32_t iterations;    /* I >= 0                                          */
   double compression;    /* c in (0, 1]; 1 gives WGS                        */
@@ -160,6 +170,10 @@ typedef struct hg_params {
   double *trace_V;       /* NULL, or host [iterations][N][2] doubles: the
                             spot field V^j (re, im) of every iteration j    */
   hg_tune tune;          /* launch geometry (zeros: defaults)               */
+  const hg_lut *lut;     /* NULL, or the SLM table: the final pass also
+                            writes the gray image of Phi^I to gray_dev      */
+  void *gray_dev;        /* device [H][W] uint8 or uint16 (the table's
+                            bits); NULL exactly when lut is NULL            */
 } hg_params;
 
 /* ---------------------------------------------------------------------- */
@@ -225,6 +239,8 @@ typedef struct hg_job {
   uint32_t flags;
   float *phi_dev;
   double *trace_V;
+  const hg_lut *lut;  /* as in hg_params: NULL, or the gray image of Phi^I */
+  void *gray_dev;     /* to gray_dev                                      */
 } hg_job;
 
 /* Runs `count` holograms together (paper section 2 for each; the paper
@@ -341,6 +357,27 @@ hg_status hg_step(const hg_grid *grid, const hg_optics *optics,
                   const hg_spots *spots, const double *w, const double *theta,
                   const int32_t *idx_dev, int32_t m, uint32_t flags,
                   double *V_out, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* SLM output                                                             */
+/* ---------------------------------------------------------------------- */
+
+/* Uploads a phase-to-gray table (host, levels uint16 values; each <= 255
+ * when bits is 8) to the current device.  levels in [1, 65536], bits 8 or
+ * 16.  Blocks until the copy is done.  *out is owned by the caller. */
+hg_status hg_lut_create(const uint16_t *gray, int32_t levels, int32_t bits,
+                        hg_lut **out);
+
+/* Frees a table.  Calls still running on the device may read it: the
+ * caller synchronises the streams that used it first. */
+hg_status hg_lut_destroy(hg_lut *lut);
+
+/* Gray image of a hologram: gray_dev[p] = g[k(phi_dev[p])] for p < count
+ * (device arrays; gray_dev of uint8 or uint16 by the table's bits), the
+ * same conversion the final pass applies when hg_params.lut is set.
+ * Asynchronous. */
+hg_status hg_phase_to_gray(const hg_lut *lut, const float *phi_dev, int64_t count,
+                           void *gray_dev, void *stream);
 
 /* ---------------------------------------------------------------------- */
 /* Library state                                                          */

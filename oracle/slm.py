@@ -14,7 +14,8 @@ wraps into [0, 2 pi).
 The bin index is an integer decided by floating-point arithmetic, so it is
 taken here in the same precision as on the device, FP32, in these steps:
     t = fl32(Phi * fl32(1 / (2 pi)))     (one rounded product)
-    t = t - floor(t)                     (exact)
+    t = fl32(t - floor(t))               (exact for t >= 0; one rounded
+                                          difference for t < 0)
     k = floor(fl32(t * L))               (one rounded product)
     k = min(k, L - 1)                    (t rounds up to 1.0 just below a
                                           whole turn)
@@ -35,7 +36,7 @@ def gray_index(Phi, levels: int) -> np.ndarray:
     L = int(levels)
     with np.errstate(over="ignore", invalid="ignore"):
         t = phi * INV_TWO_PI_F32                   # float32 product
-        t = (t - np.floor(t)).astype(np.float32)   # exact in float32
+        t = (t - np.floor(t)).astype(np.float32)   # float32 difference
         k = np.floor(t * np.float32(L)).astype(np.int64)
     return np.minimum(k, L - 1)
 

@@ -26,7 +26,7 @@ __all__ = [
     "HGError", "lib_path", "load", "version", "last_error", "release",
     "rs", "wgs", "cswgs", "metrics", "theta0", "subset", "forward", "backward", "step",
     "PREC_FP32", "PREC_MIXED", "cswgs_device", "timing_enable", "timing_reset", "timing_read",
-    "DeviceJob", "cswgs_batch", "Batch", "Engine",
+    "DeviceJob", "cswgs_batch", "Batch", "Engine", "Lut", "phase_to_gray",
 ]
 
 PREC_FP32 = 0
@@ -69,7 +69,8 @@ class _Job(ctypes.Structure):
     _fields_ = [("grid", _Grid), ("optics", _Optics), ("spots", _Spots),
                 ("iterations", ctypes.c_int32), ("compression", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32),
-                ("phi_dev", ctypes.c_void_p), ("trace_V", _DP)]
+                ("phi_dev", ctypes.c_void_p), ("trace_V", _DP),
+                ("lut", ctypes.c_void_p), ("gray_dev", ctypes.c_void_p)]
 
 
 class _Tune(ctypes.Structure):
@@ -85,7 +86,7 @@ class _EngineConfig(ctypes.Structure):
 class _Params(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("compression", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("trace_V", _DP),
-                ("tune", _Tune)]
+                ("tune", _Tune), ("lut", ctypes.c_void_p), ("gray_dev", ctypes.c_void_p)]
 
 
 def lib_path() -> str:
@@ -128,6 +129,9 @@ def load():
         "hg_timing_enable": [c.c_int],
         "hg_timing_reset": [],
         "hg_timing_read": [c.c_char_p, _DP, c.POINTER(c.c_int64)],
+        "hg_lut_create": [c.POINTER(c.c_uint16), i32, i32, c.POINTER(vp)],
+        "hg_lut_destroy": [vp],
+        "hg_phase_to_gray": [vp, vp, c.c_int64, vp, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -256,28 +260,101 @@ def wgs(grid, optics, spots, iterations: int, seed: int, phi=None, stream=None):
 
 def cswgs(grid, optics, spots, iterations: int, compression: float, seed: int, phi=None,
           stream=None, precision: str = "fp32", trace: bool = False, direct: bool = False,
-          tune=None):
+          tune=None, lut=None, gray=None):
     """Compressed-sensing WGS hologram.  With trace=True returns (phi, V)
     where V[j-1] is the complex spot field of iteration j.  direct=True
     computes the full-grid passes with the per-pixel kernels.  tune: launch
-    geometry {"full_block_cap", "subset_block_cap"} (see autotune)."""
+    geometry {"full_block_cap", "subset_block_cap"} (see autotune).  lut (a
+    Lut) and gray (a uint8 or int16 GPU tensor of W*H elements, by the
+    table's bits): the final pass also writes the SLM's gray image."""
     lib = load()
     phi = _new_phi(grid) if phi is None else phi
     sa = _SpotArgs(spots)
     flags = _flags(precision) | (FULL_DIRECT if direct else 0)
-    if precision == "fp32" and not trace and not direct and tune is None:
+    lp, gp = _lut_args(lut, gray, grid)
+    if precision == "fp32" and not trace and not direct and tune is None and lut is None:
         _check(lib.hg_cswgs(_grid(grid), _optics(optics), sa.struct, int(iterations),
                             float(compression), int(seed),
                             _dev_f32(phi, grid.W * grid.H, "phi"), _stream(stream)))
         return phi
     tr = np.zeros((max(int(iterations), 1), sa.n, 2)) if trace else None
     params = _Params(int(iterations), float(compression), int(seed), flags,
-                     tr.ctypes.data_as(_DP) if trace else None, _tune(tune) or _Tune(0, 0, 0, 0))
+                     tr.ctypes.data_as(_DP) if trace else None, _tune(tune) or _Tune(0, 0, 0, 0),
+                     lp, gp)
     _check(lib.hg_cswgs_ex(_grid(grid), _optics(optics), sa.struct, ctypes.byref(params),
                            _dev_f32(phi, grid.W * grid.H, "phi"), _stream(stream)))
     if trace:
         return phi, (tr[..., 0] + 1j * tr[..., 1])[:int(iterations)]
     return phi
+
+
+class Lut:
+    """The SLM's phase-to-gray table on the GPU (hg_lut_create): gray values
+    of `levels` equal phase bins covering one period; bits 8 or 16 sets the
+    element type of the gray images."""
+
+    def __init__(self, table, bits: int = 8):
+        lib = load()
+        arr = np.ascontiguousarray(table, dtype=np.uint16)
+        if arr.ndim != 1:
+            raise ValueError("table must be one-dimensional")
+        h = ctypes.c_void_p()
+        _check(lib.hg_lut_create(arr.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),
+                                 int(arr.shape[0]), int(bits), ctypes.byref(h)))
+        self._h, self.levels, self.bits = h, int(arr.shape[0]), int(bits)
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("the table has been closed")
+        return self._h
+
+    def new_image(self, grid):
+        """An empty gray image of the grid, of the table's element type."""
+        import torch
+        return torch.empty(grid.W * grid.H, dtype=torch.uint8 if self.bits == 8 else torch.int16,
+                           device="cuda")
+
+    def close(self):
+        if self._h:
+            _check(load().hg_lut_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _gray_ptr(gray, lut, count: int, name: str = "gray"):
+    import torch
+    want = torch.uint8 if lut.bits == 8 else torch.int16
+    if (not isinstance(gray, torch.Tensor) or not gray.is_cuda or gray.dtype != want
+            or gray.numel() != count or not gray.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous {want} GPU tensor of {count} elements")
+    return ctypes.c_void_p(gray.data_ptr())
+
+
+def _lut_args(lut, gray, grid):
+    if lut is None and gray is None:
+        return None, None
+    if lut is None or gray is None:
+        raise ValueError("lut and gray go together")
+    return lut.handle, _gray_ptr(gray, lut, grid.W * grid.H)
+
+
+def phase_to_gray(lut, phi, gray=None, stream=None):
+    """Gray image of a hologram phi (float32 GPU tensor) through the table."""
+    lib = load()
+    count = int(phi.numel())
+    if gray is None:
+        import torch
+        gray = torch.empty(count, dtype=torch.uint8 if lut.bits == 8 else torch.int16,
+                           device="cuda")
+    _check(lib.hg_phase_to_gray(lut.handle, _dev_f32(phi, count, "phi"), count,
+                                _gray_ptr(gray, lut, count), _stream(stream)))
+    return gray
 
 
 def metrics(grid, optics, spots, phi, stream=None) -> Tuple[float, float, np.ndarray]:
@@ -411,7 +488,7 @@ class DeviceJob:
     phi: float32 GPU tensor of W*H elements (allocated if None)."""
 
     def __init__(self, grid, optics, spots_dev, iterations: int, compression: float, seed: int,
-                 phi=None, precision: str = "fp32"):
+                 phi=None, precision: str = "fp32", lut=None, gray=None):
         import torch
         if (not isinstance(spots_dev, torch.Tensor) or spots_dev.dtype != torch.float64
                 or not spots_dev.is_cuda or spots_dev.dim() != 2 or spots_dev.shape[0] != 4
@@ -421,6 +498,8 @@ class DeviceJob:
         self.iterations, self.compression, self.seed = int(iterations), float(compression), int(seed)
         self.phi = _new_phi(grid) if phi is None else phi
         self.flags = _flags(precision) | SPOTS_ON_DEVICE
+        self.lut, self.gray = lut, gray
+        _lut_args(lut, gray, grid)  # checks the pair
 
     @classmethod
     def from_spots(cls, grid, optics, spots, iterations, compression, seed, **kw):
@@ -434,9 +513,10 @@ class DeviceJob:
         n = int(self.spots_dev.shape[1])
         base = self.spots_dev.data_ptr()
         ptrs = [ctypes.cast(ctypes.c_void_p(base + 8 * n * k), _DP) for k in range(4)]
+        lp, gp = _lut_args(self.lut, self.gray, self.grid)
         return _Job(_grid(self.grid), _optics(self.optics), _Spots(n, *ptrs), self.iterations,
                     self.compression, self.seed, self.flags,
-                    _dev_f32(self.phi, self.grid.W * self.grid.H, "phi"), None)
+                    _dev_f32(self.phi, self.grid.W * self.grid.H, "phi"), None, lp, gp)
 
 
 def _tune(tune):
@@ -504,13 +584,15 @@ class Engine:
         self._keep = {}
 
     def submit(self, grid, optics, spots, iterations: int, compression: float, seed: int,
-               phi, precision: str = "fp32") -> int:
+               phi, precision: str = "fp32", lut=None, gray=None) -> int:
         sa = _SpotArgs(spots)
+        lp, gp = _lut_args(lut, gray, grid)
         job = _Job(_grid(grid), _optics(optics), sa.struct, int(iterations), float(compression),
-                   int(seed), _flags(precision), _dev_f32(phi, grid.W * grid.H, "phi"), None)
+                   int(seed), _flags(precision), _dev_f32(phi, grid.W * grid.H, "phi"), None,
+                   lp, gp)
         t = ctypes.c_uint64()
         _check(load().hg_engine_submit(self._h, ctypes.byref(job), ctypes.byref(t)))
-        self._keep[t.value] = phi
+        self._keep[t.value] = (phi, gray, lut)
         return t.value
 
     def step(self, stream=None) -> int:

@@ -117,9 +117,11 @@ hg::TuneParams tune_params(const hg_tune* t) {
 // The shared schedule of RS (I = 0), WGS (c < 0) and CS-WGS: a batch of one.
 hg_status run_one(const hg_grid* g, const hg_optics* o, const hg_spots* s, int32_t iterations,
                   double c, uint64_t seed, uint32_t flags, float* phi, double* trace_host,
-                  void* stream, const hg::TuneParams& tp = hg::TuneParams{}) {
+                  void* stream, const hg::TuneParams& tp = hg::TuneParams{},
+                  const hg_lut* lut = nullptr, void* gray = nullptr) {
   hg::JobSpec spec;
   HG_TRY(hg::make_spec(g, o, s, iterations, c, seed, flags, phi, trace_host, &spec));
+  HG_TRY(hg::apply_lut(lut, gray, &spec));
   if (!phi) return set_error(HG_EINVAL, "phi_dev must be non-NULL");
   Workspace* ws = nullptr;
   HG_TRY(get_workspace(stream, &ws));
@@ -235,6 +237,7 @@ hg_status job_specs(int32_t count, const hg_job* jobs, const hg_tune* tune,
       st = hg::make_spec(&j.grid, &j.optics, &j.spots, j.iterations, j.compression, j.seed,
                          j.flags, j.phi_dev, j.trace_V, &(*out)[i]);
     if (st == HG_OK && !j.phi_dev) st = set_error(HG_EINVAL, "phi_dev must be non-NULL");
+    if (st == HG_OK) st = hg::apply_lut(j.lut, j.gray_dev, &(*out)[i]);
     if (st != HG_OK) return set_error(st, "job " + std::to_string(i) + ": " + hg::last_error());
   }
   return HG_OK;
@@ -287,7 +290,8 @@ hg_status hg_cswgs_ex(const hg_grid* grid, const hg_optics* optics, const hg_spo
       params->tune.chain_passes < 0 || params->tune.chain_passes > 1)
     return set_error(HG_EINVAL, "tune caps must be >= 0, pass_form and chain_passes 0 or 1");
   return run_one(grid, optics, spots, params->iterations, params->compression, params->seed,
-                 params->flags, phi_dev, params->trace_V, stream, tune_params(&params->tune));
+                 params->flags, phi_dev, params->trace_V, stream, tune_params(&params->tune),
+                 params->lut, params->gray_dev);
 }
 
 hg_status hg_metrics(const hg_grid* grid, const hg_optics* optics, const hg_spots* spots,
@@ -349,6 +353,50 @@ hg_status hg_metrics(const hg_grid* grid, const hg_optics* optics, const hg_spot
   *e = sum / hg::pupil_power(grid->W, grid->H, ap_q, ill_a);
   *u = (hi + lo) > 0.0 ? 1.0 - (hi - lo) / (hi + lo) : 0.0;
   return HG_OK;
+}
+
+hg_status hg_lut_create(const uint16_t* gray, int32_t levels, int32_t bits, hg_lut** out) {
+  if (!gray || !out) return set_error(HG_EINVAL, "gray and out must be non-NULL");
+  if (levels < 1 || levels > 65536) return set_error(HG_EINVAL, "levels must be in [1, 65536]");
+  if (bits != 8 && bits != 16) return set_error(HG_EINVAL, "bits must be 8 or 16");
+  if (bits == 8)
+    for (int32_t k = 0; k < levels; ++k)
+      if (gray[k] > 255) return set_error(HG_EINVAL, "8-bit tables hold values <= 255");
+  std::unique_ptr<hg_lut> lut(new hg_lut());
+  lut->levels = levels;
+  lut->bits = bits;
+  HG_HIP(hipGetDevice(&lut->device));
+  HG_HIP(hipMalloc(reinterpret_cast<void**>(&lut->dev), sizeof(uint16_t) * (size_t)levels));
+  const hipError_t e =
+      hipMemcpy(lut->dev, gray, sizeof(uint16_t) * (size_t)levels, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(lut->dev);
+    return set_error(HG_EDEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+  }
+  *out = lut.release();
+  return HG_OK;
+}
+
+hg_status hg_lut_destroy(hg_lut* lut) {
+  if (!lut) return HG_OK;
+  int cur = 0;
+  HG_HIP(hipGetDevice(&cur));
+  HG_HIP(hipSetDevice(lut->device));
+  const hipError_t e = hipFree(lut->dev);
+  (void)hipSetDevice(cur);
+  delete lut;
+  if (e != hipSuccess) return set_error(HG_EDEVICE, std::string("hipFree: ") + hipGetErrorString(e));
+  return HG_OK;
+}
+
+hg_status hg_phase_to_gray(const hg_lut* lut, const float* phi_dev, int64_t count, void* gray_dev,
+                           void* stream) {
+  if (!lut || !lut->dev || !phi_dev || !gray_dev)
+    return set_error(HG_EINVAL, "lut, phi_dev and gray_dev must be non-NULL");
+  if (count < 0) return set_error(HG_EINVAL, "count must be >= 0");
+  hg::launch_phase_to_gray(phi_dev, count, lut->dev, lut->levels, lut->bits, gray_dev,
+                           static_cast<hipStream_t>(stream));
+  return check_launch();
 }
 
 hg_status hg_theta0(uint64_t seed, int32_t count, double* out_host) {

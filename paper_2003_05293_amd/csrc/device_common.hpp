@@ -106,6 +106,23 @@ __device__ __forceinline__ ColumnSrc column_src(const T* base, int row_end, int 
 }
 constexpr int kDeviceScope = 1 << 4;  // buffer cache policy: device-scope coherent (sc1)
 
+// Gray level of phase phi (radians) from the SLM's table of L levels, which
+// covers one phase period: bin k = floor(L frac(phi / 2 pi)), decided in
+// FP32 with individually rounded operations (never fused), clamped to L - 1
+// where the fraction rounds up to a whole turn.
+__device__ __forceinline__ uint32_t gray_level(float phi, const uint16_t* lut, int L) {
+#pragma clang fp contract(off)
+  float t = phi * 0.15915494309189535f;
+  t = t - floorf(t);
+  const int k = (int)(t * (float)L);
+  return as_global(lut)[min(k, L - 1)];
+}
+// Stores a gray level as the image's element type (8 or 16 bits).
+__device__ __forceinline__ void store_gray(void* img, int64_t p, int bits, uint32_t g) {
+  if (bits == 8) as_global_mut(static_cast<uint8_t*>(img))[p] = (uint8_t)g;
+  else as_global_mut(static_cast<uint16_t*>(img))[p] = (uint16_t)g;
+}
+
 // Pupil weight of a pixel (paper section 4) with Q = Lx^2 + Ly^2 in doubled
 // offsets (Qi exact, Q in FP32): 0 outside the aperture (ap_q >= 0 and
 // Qi > ap_q), else the illumination amplitude A = exp(-Q ill_a) (1 when

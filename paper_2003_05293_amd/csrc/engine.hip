@@ -95,8 +95,9 @@ hg_status spec_from_job(const hg_job& j, hg::JobSpec* out) {
     return set_error(HG_EINVAL, "flags: HG_FULL_DIRECT applies to HG_PREC_FP32 only");
   if (j.trace_V) return set_error(HG_EINVAL, "engine requests cannot ask for a trace");
   if (!j.phi_dev) return set_error(HG_EINVAL, "phi_dev must be non-NULL");
-  return hg::make_spec(&j.grid, &j.optics, &j.spots, j.iterations, j.compression, j.seed,
-                       j.flags, j.phi_dev, nullptr, out);
+  HG_TRY(hg::make_spec(&j.grid, &j.optics, &j.spots, j.iterations, j.compression, j.seed,
+                       j.flags, j.phi_dev, nullptr, out));
+  return hg::apply_lut(j.lut, j.gray_dev, out);
 }
 
 }  // namespace

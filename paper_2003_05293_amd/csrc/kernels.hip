@@ -823,7 +823,43 @@ __global__ __launch_bounds__(kBlock) void k_backprop_batch(const JobDev* __restr
   if (q >= d.ps.count) return;
   const PixCoord c = pixel_coord(pixel_of(d.ps, q), jb.W, jb.H);
   const float2 S = backprop_field(jb.sp, 0, jb.N, c);
-  as_global_mut(d.out)[q] = atan2f(S.y, S.x);
+  const float phi = atan2f(S.y, S.x);
+  as_global_mut(d.out)[q] = phi;
+  // the job's final hologram (over all pixels, q = p) with an SLM table
+  if (jb.gray) store_gray(jb.gray, q, jb.gray_bits, gray_level(phi, jb.lut, jb.lut_levels));
+}
+
+// -------------------------------------------------------------- SLM output ---
+
+// Gray image of a hologram, four consecutive pixels per thread (one 4- or
+// 8-byte store where the image is aligned for it).
+constexpr int kGrayThreads = 256;
+__global__ __launch_bounds__(kGrayThreads) void k_phase_to_gray(const float* __restrict__ phi,
+                                                                int64_t count,
+                                                                const uint16_t* __restrict__ lut,
+                                                                int levels, int bits,
+                                                                void* __restrict__ gray) {
+  const int64_t p0 = 4 * ((int64_t)blockIdx.x * kGrayThreads + threadIdx.x);
+  if (p0 >= count) return;
+  if (p0 + 3 < count) {
+    const HG_GLOBAL float* src = as_global(phi) + p0;
+    const float v0 = src[0], v1 = src[1], v2 = src[2], v3 = src[3];
+    const uint32_t g0 = gray_level(v0, lut, levels), g1 = gray_level(v1, lut, levels),
+                   g2 = gray_level(v2, lut, levels), g3 = gray_level(v3, lut, levels);
+    if (bits == 8 && (reinterpret_cast<uintptr_t>(gray) & 3) == 0) {
+      *as_global_mut(reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(gray) + p0)) =
+          g0 | (g1 << 8) | (g2 << 16) | (g3 << 24);
+      return;
+    }
+    if (bits == 16 && (reinterpret_cast<uintptr_t>(gray) & 3) == 0) {
+      HG_GLOBAL uint32_t* q = as_global_mut(reinterpret_cast<uint32_t*>(static_cast<uint16_t*>(gray) + p0));
+      q[0] = g0 | (g1 << 16);
+      q[1] = g2 | (g3 << 16);
+      return;
+    }
+  }
+  for (int64_t p = p0; p < p0 + 4 && p < count; ++p)
+    store_gray(gray, p, bits, gray_level(as_global(phi)[p], lut, levels));
 }
 
 // -------------------------------------------------------------- metrics ---
@@ -1067,6 +1103,14 @@ void launch_metric_tables(const SetupArgs& a, const SpotPtrs& in, double2* Ex, d
 }
 
 int metric_blocks(int H) { return ceil_div(H, kMetricRows); }
+
+void launch_phase_to_gray(const float* phi, int64_t count, const uint16_t* lut, int levels,
+                          int bits, void* gray, hipStream_t s) {
+  if (count <= 0) return;
+  const int64_t blocks = ceil_div(count, (int64_t)4 * kGrayThreads);
+  hipLaunchKernelGGL(k_phase_to_gray, dim3((unsigned)blocks), dim3(kGrayThreads), 0, s, phi,
+                     count, lut, levels, bits, gray);
+}
 
 void launch_metric_rows(const double2* Ex, const double2* Ey, int N, int W, int H,
                         const float* phi, int32_t ap_q, double ill_a, double2* partial,

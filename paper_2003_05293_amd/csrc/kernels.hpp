@@ -156,6 +156,11 @@ struct JobDev {
   float4* mxGa;        // [Hp/16][Np/16][64] x 4 float2  (rows by lane)
   float4* mxGv;        // [Hp/16][Np/16][64] x 4 float2  (spots by lane)
   uint32_t* rank;      // [M] position of each pixel in the random order
+  // SLM output: with a table, the final pass also writes the gray image
+  const uint16_t* lut; // [lut_levels] gray value of each phase bin (or nullptr)
+  int32_t lut_levels;
+  int32_t gray_bits;   // 8 or 16: element type of gray
+  void* gray;          // [H][W] gray image of the final hologram
 };
 
 // Pixel set of a pass: all pixels 0..count-1 (perm == idx == nullptr; with
@@ -305,6 +310,11 @@ void launch_mx_tables(const JobDev* jobs, const JobSlice* slices, int nslices, i
 // mode: MxMode; max_steps: largest Np / 16 among the descriptors.
 void launch_mx_pass(const JobDev* jobs, const MxDesc* descs, int ndesc, int total_blocks,
                     int mode, int max_steps, hipStream_t s);
+
+// ---- SLM output ----
+// gray[p] = lut[bin(phi[p])] for p < count (see gray_level).
+void launch_phase_to_gray(const float* phi, int64_t count, const uint16_t* lut, int levels,
+                          int bits, void* gray, hipStream_t s);
 
 // ---- metrics (FP64) ----
 struct SetupArgs {

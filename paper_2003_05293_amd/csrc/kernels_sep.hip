@@ -268,7 +268,13 @@ __global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ 
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = row0 + 4 * lg + r, col = col0 + 16 * t + lr;
-        if (row < H && col < W) out[(int64_t)row * W + col] = atan2f(si[t][r], sr[t][r]);
+        if (row < H && col < W) {
+          const float phi = atan2f(si[t][r], sr[t][r]);
+          const int64_t p = (int64_t)row * W + col;
+          out[p] = phi;
+          // the SLM's gray image of the final hologram
+          if (jb.gray) store_gray(jb.gray, p, jb.gray_bits, gray_level(phi, jb.lut, jb.lut_levels));
+        }
       }
     return;
   }

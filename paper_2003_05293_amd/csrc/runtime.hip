@@ -140,6 +140,18 @@ hg_status validate_spec(const hg_grid* g, const hg_optics* o, const hg_spots* s,
   return HG_OK;
 }
 
+hg_status apply_lut(const hg_lut* lut, void* gray, JobSpec* spec) {
+  if (!lut && !gray) return HG_OK;
+  if (!lut || !gray) return set_error(HG_EINVAL, "lut and gray_dev must be both NULL or both set");
+  if (!lut->dev || lut->levels < 1 || (lut->bits != 8 && lut->bits != 16))
+    return set_error(HG_EINVAL, "lut is not a live table of hg_lut_create");
+  spec->lut = lut->dev;
+  spec->lut_levels = lut->levels;
+  spec->gray_bits = lut->bits;
+  spec->gray = gray;
+  return HG_OK;
+}
+
 hg_status make_spec(const hg_grid* g, const hg_optics* o, const hg_spots* s, int32_t iterations,
                     double compression, uint64_t seed, uint32_t flags, float* phi,
                     double* trace_host, JobSpec* out) {
@@ -299,6 +311,10 @@ JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev
   j.lambda_mm = s.lambda_mm;
   j.focal_mm = s.focal_mm;
   j.phi = s.phi;
+  j.lut = s.lut;
+  j.lut_levels = s.lut_levels;
+  j.gray_bits = s.gray_bits;
+  j.gray = s.gray;
   j.trace = s.trace_host ? 1 : 0;
   j.status = status_dev;
   j.mixed = s.precision == HG_PREC_MIXED ? 1 : 0;

@@ -10,6 +10,14 @@
 #include "hg.h"
 #include "kernels.hpp"
 
+// A phase-to-gray table of the SLM resident on one device (hg_lut_create).
+struct hg_lut {
+  uint16_t* dev = nullptr;  // [levels]
+  int32_t levels = 0;
+  int32_t bits = 0;         // 8 or 16: element type of the gray images
+  int device = 0;
+};
+
 namespace hg {
 
 // Thread-local error message of the C ABI.
@@ -80,6 +88,11 @@ struct JobSpec {
   bool hook = false;          // single-pass entry point (any pixel set up to W*H)
   float* phi = nullptr;       // output hologram (device)
   double* trace_host = nullptr;
+  // SLM output: the final pass also writes the gray image (device)
+  const uint16_t* lut = nullptr;
+  int32_t lut_levels = 0;
+  int32_t gray_bits = 0;
+  void* gray = nullptr;
 };
 
 // Launch-geometry parameters (chosen per shape by the autotuner).
@@ -99,6 +112,9 @@ int32_t aperture_bound(const hg_optics* o);
 int64_t pupil_count(int32_t W, int32_t H, int32_t q);
 double illumination_exponent(double pitch_mm, double waist_mm);
 double pupil_power(int32_t W, int32_t H, int32_t q, double ill_a);
+
+// SLM output of a hologram: the table and the gray image (both or neither).
+hg_status apply_lut(const hg_lut* lut, void* gray, JobSpec* spec);
 
 // Validation of the host-visible parts of a hologram description.
 hg_status validate_grid(const hg_grid* g);

@@ -138,3 +138,24 @@ def test_binding_rejects_wrong_types():
         hg.backward(g, OPTICS, s, np.ones(2), np.zeros(3))
     with pytest.raises(ValueError):
         hg.cswgs(g, OPTICS, s, 3, 0.5, 1, phi=np.zeros(256, np.float32), precision="fp8")
+
+
+def test_lut_validation(lib):
+    gray = np.arange(256, dtype=np.uint16)
+    P16 = ctypes.POINTER(ctypes.c_uint16)
+    h = ctypes.c_void_p()
+    for levels, bits in ((0, 8), (65537, 16), (256, 12)):
+        assert lib.hg_lut_create(gray.ctypes.data_as(P16), levels, bits, ctypes.byref(h)) == 1
+    big = np.full(4, 300, dtype=np.uint16)
+    assert lib.hg_lut_create(big.ctypes.data_as(P16), 4, 8, ctypes.byref(h)) == 1
+    assert "255" in hg.last_error()
+    assert lib.hg_lut_create(None, 4, 8, ctypes.byref(h)) == 1
+    assert lib.hg_lut_destroy(None) == 0
+    assert lib.hg_phase_to_gray(None, ctypes.c_void_p(1), 4, ctypes.c_void_p(1), None) == 1
+    # a table without an image (and the reverse) is rejected before any GPU work
+    g, o, s, keep = _args()
+    for lut, img in ((ctypes.c_void_p(8), None), (None, ctypes.c_void_p(8))):
+        params = hg._Params(3, 0.5, 1, 0, None, hg._Tune(0, 0, 0, 0), lut, img)
+        assert lib.hg_cswgs_ex(ctypes.byref(g), ctypes.byref(o), ctypes.byref(s),
+                               ctypes.byref(params), ctypes.c_void_p(1), None) == 1
+        assert "lut and gray_dev" in hg.last_error()
