@@ -115,7 +115,7 @@ __device__ __forceinline__ uint32_t gray_level(float phi, const uint16_t* lut, i
   float t = phi * 0.15915494309189535f;
   t = t - floorf(t);
   const int k = (int)(t * (float)L);
-  return as_global(lut)[min(k, L - 1)];
+  return as_global(lut)[max(0, min(k, L - 1))];  // (a NaN phase lands in bin 0)
 }
 // Stores a gray level as the image's element type (8 or 16 bits).
 __device__ __forceinline__ void store_gray(void* img, int64_t p, int bits, uint32_t g) {
