@@ -441,9 +441,10 @@ def step(grid, optics, spots, w, theta, idx=None, precision: str = "fp32",
 
 
 def cswgs_device(grid, optics, spots_dev, iterations: int, compression: float, seed: int,
-                 phi=None, stream=None, precision: str = "fp32", tune=None):
+                 phi=None, stream=None, precision: str = "fp32", tune=None, lut=None, gray=None):
     """CS-WGS with the spot arrays already on the GPU: spots_dev is a float64
-    GPU tensor of shape (4, N) holding x_mm, y_mm, z_mm, amp."""
+    GPU tensor of shape (4, N) holding x_mm, y_mm, z_mm, amp.  lut, gray: as
+    in cswgs."""
     import torch
     lib = load()
     if (not isinstance(spots_dev, torch.Tensor) or spots_dev.dtype != torch.float64
@@ -455,8 +456,10 @@ def cswgs_device(grid, optics, spots_dev, iterations: int, compression: float, s
     ptrs = [ctypes.cast(ctypes.c_void_p(base + 8 * n * k), _DP) for k in range(4)]
     sp = _Spots(n, *ptrs)
     phi = _new_phi(grid) if phi is None else phi
+    lp, gp = _lut_args(lut, gray, grid)
     params = _Params(int(iterations), float(compression), int(seed),
-                     _flags(precision) | SPOTS_ON_DEVICE, None, _tune(tune) or _Tune(0, 0, 0, 0))
+                     _flags(precision) | SPOTS_ON_DEVICE, None, _tune(tune) or _Tune(0, 0, 0, 0),
+                     lp, gp)
     _check(lib.hg_cswgs_ex(_grid(grid), _optics(optics), sp, ctypes.byref(params),
                            _dev_f32(phi, grid.W * grid.H, "phi"), _stream(stream)))
     return phi
