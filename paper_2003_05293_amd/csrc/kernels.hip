@@ -236,16 +236,33 @@ template <bool LDS>
 __global__ __launch_bounds__(kPermThreads) void k_perm_batch(const JobDev* __restrict__ jobs,
                                                              const JobSlice* __restrict__ slices,
                                                              int nslices) {
-  __shared__ uint32_t tab_s[LDS ? (kFeistelRounds << kPermLdsHalfBits) : 1];
+  // the tables as 16-byte words (6 << h is a multiple of 4 for h >= 1)
+  constexpr int kTab4 = LDS ? (kFeistelRounds << kPermLdsHalfBits) / 4 : 1;
+  constexpr int kTabLoads = (kTab4 + kPermThreads - 1) / kPermThreads;
+  __shared__ uint4 tab_s4[kTab4];
   const int si = find_desc(slices, nslices, blockIdx.x);
   const JobDev& jb = jobs[slices[si].job];
   const int lb = blockIdx.x - slices[si].block_begin;
   const uint32_t* tab = jb.tab;
   if (LDS) {
-    const int total = kFeistelRounds << jb.h;
-    for (int k = threadIdx.x; k < total; k += kPermThreads) tab_s[k] = jb.tab[k];
+    // every load of this thread is issued before the first is waited for
+    const int total4 = (kFeistelRounds << jb.h) / 4;
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint32_t*>(jb.tab), (short)0, total4 * 16, 0x00020000);
+    uint4 v[kTabLoads];
+#pragma unroll
+    for (int i = 0; i < kTabLoads; ++i) {
+      const int k = threadIdx.x + i * kPermThreads;
+      const auto bits = __builtin_amdgcn_raw_buffer_load_b128(rsrc, k * 16, 0, 0);
+      __builtin_memcpy(&v[i], &bits, sizeof(uint4));
+    }
+#pragma unroll
+    for (int i = 0; i < kTabLoads; ++i) {
+      const int k = threadIdx.x + i * kPermThreads;
+      if (k < total4) tab_s4[k] = v[i];
+    }
     __syncthreads();
-    tab = tab_s;
+    tab = reinterpret_cast<const uint32_t*>(tab_s4);
   }
   const uint32_t M = (uint32_t)jb.P;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
