@@ -517,7 +517,21 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab, bool has_pre = fals
           // the units' sums)
           float ar = vr[k], ai = vi[k], br = 0.f, bi = 0.f;
           int j = j0;
-          if (MAXU == 1)
+          if (MAXU == 1 && lm.R == 1) {
+            // one replica (r = 0): the pixel loop is uniform across the
+            // wave, so its counter and the LDS addresses stay scalar
+            int ju = __builtin_amdgcn_readfirstlane(j0);
+            const int ju1 = __builtin_amdgcn_readfirstlane(j1);
+            for (; ju + 3 < ju1; ju += 4) {
+              const float4 p0 = px[ju], p1 = px[ju + 1], p2 = px[ju + 2], p3 = px[ju + 3];
+              const float u0 = pui[ju], u1 = pui[ju + 1], u2 = pui[ju + 2], u3 = pui[ju + 3];
+              forward_term(cx[k], cy[k], cz[k], p0, u0, ar, ai);
+              forward_term(cx[k], cy[k], cz[k], p1, u1, br, bi);
+              forward_term(cx[k], cy[k], cz[k], p2, u2, ar, ai);
+              forward_term(cx[k], cy[k], cz[k], p3, u3, br, bi);
+            }
+            j = ju;
+          } else if (MAXU == 1)
           for (; j + 3 * lm.R < j1; j += 4 * lm.R) {
             const float4 p0 = px[j], p1 = px[j + lm.R], p2 = px[j + 2 * lm.R],
                          p3 = px[j + 3 * lm.R];
