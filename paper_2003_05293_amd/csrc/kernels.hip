@@ -468,8 +468,8 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab, bool has_pre = fals
         const int32_t p = (CHAIN && has_pre && tile == a.lb && st == 0)
                               ? pre_p
                               : (valid ? pixel_of(a.ps, q) : 0);
-        if (dynamic && st == a.plan.sub - 1 && threadIdx.x == 0)
-          ticket = atomicAdd(grab, p >= 0 ? 1u : 1u);
+        // the next tile is asked for now; the answer is first needed after phase 1
+        if (dynamic && st == a.plan.sub - 1 && threadIdx.x == 0) ticket = atomicAdd(grab, 1u);
         PixCoord c{0.f, 0.f, 0.f, 0};
         if (valid) c = pixel_coord(p, a.W, a.H);
         sw[wave][lane] = CHAIN ? backprop_field_lds(a.recs, n_lo, n_hi, c)
@@ -653,9 +653,9 @@ __device__ void pass_block_e(const PassCtx& a, unsigned* grab) {
       const int32_t q = (tile * a.plan.sub + st) * kTile + lane;
       const bool valid = q < a.ps.count;
       const int32_t p = valid ? pixel_of(a.ps, q) : 0;
-      // the next tile is asked for once the pixel index has arrived (the
-      // counter's answer is first needed after phase 1)
-      if (dynamic && st == a.plan.sub - 1 && threadIdx.x == 0) ticket = atomicAdd(grab, p >= 0 ? 1u : 1u);
+      // the next tile is asked for now (the counter's answer is first needed
+      // after phase 1)
+      if (dynamic && st == a.plan.sub - 1 && threadIdx.x == 0) ticket = atomicAdd(grab, 1u);
       PixCoord c{0.f, 0.f, 0.f, 0};
       if (valid) c = pixel_coord(p, a.W, a.H);
       float er[MAXE], ei[MAXE];
