@@ -249,14 +249,20 @@ __global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ 
   {
     static_assert(kSepSteps == 8, "K-step groups of 8: KS = 8 S16");
     const int G = KS / kSepSteps;
-    BpOps P, Q;
+    // three operand buffers: the loads run two groups ahead of the products
+    BpOps P, Q, R;
     bp_load(P, jb, rb, tx, 0, KS, lane);
-    for (int gi = 0; gi < G; gi += 2) {
-      if (gi + 1 < G) bp_load(Q, jb, rb, tx, (gi + 1) * kSepSteps, KS, lane);
+    if (G > 1) bp_load(Q, jb, rb, tx, kSepSteps, KS, lane);
+    for (int gi = 0; gi < G; gi += 3) {
+      if (gi + 2 < G) bp_load(R, jb, rb, tx, (gi + 2) * kSepSteps, KS, lane);
       bp_mma(P, cs, gi * kSepSteps, lg, part, sr, si);
       if (gi + 1 < G) {
-        if (gi + 2 < G) bp_load(P, jb, rb, tx, (gi + 2) * kSepSteps, KS, lane);
+        if (gi + 3 < G) bp_load(P, jb, rb, tx, (gi + 3) * kSepSteps, KS, lane);
         bp_mma(Q, cs, (gi + 1) * kSepSteps, lg, part, sr, si);
+      }
+      if (gi + 2 < G) {
+        if (gi + 4 < G) bp_load(Q, jb, rb, tx, (gi + 4) * kSepSteps, KS, lane);
+        bp_mma(R, cs, (gi + 2) * kSepSteps, lg, part, sr, si);
       }
     }
   }
