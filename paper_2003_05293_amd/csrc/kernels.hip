@@ -270,8 +270,9 @@ __global__ __launch_bounds__(kPermThreads) void k_perm_batch(const JobDev* __res
   if (c0 >= M) return;  // whole wave
   const uint32_t c1 = min(c0 + (uint32_t)kPermChunk, M);
   // lane state: the k being walked and the latest point y of its walk
-  uint32_t k = c0 + lane, y = k;
+  uint32_t k = c0 + lane;
   bool active = k < c1;
+  uint32_t y = active ? k : 0u;  // an idle lane walks from 0: its table reads stay in range
   uint32_t next = c0 + 64;  // next k of the chunk to hand out (uniform)
   const uint32_t cap = 1u << (2 * jb.h < 32 ? 2 * jb.h : 31);
   uint32_t steps = 0;
