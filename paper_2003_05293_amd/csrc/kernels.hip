@@ -390,8 +390,10 @@ __host__ __device__ inline LaneMap lane_map(int N) {
 // CHAIN: the spot records come from LDS (a.recs), the pixel index of this
 // thread in the block's first sub-tile may come prefetched (has_pre, pre_p),
 // and the block that completes the pass publishes the generation word after
-// the update.
-template <int MAXU, bool CHAIN = false>
+// the update.  PEND: the records come from LDS too (a.recs: the state after
+// the previous pass's deferred update).  With a.defer the pass ends after
+// its groups have added into its total row.
+template <int MAXU, bool CHAIN = false, bool PEND = false>
 __device__ void pass_block(const PassCtx& a, unsigned* grab, bool has_pre = false,
                            int32_t pre_p = 0) {
   __shared__ float2 sw[kWaves][kTile];
@@ -409,6 +411,7 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab, bool has_pre = fals
   const int g = lane % lm.Lg, r = lane / lm.Lg;
   const SpotRec* __restrict__ sp = a.sp;
   if (threadIdx.x == 0) ndone = nowned = 0;
+  constexpr bool lds_recs = CHAIN || PEND;
 
   float cx[MAXU], cy[MAXU], cz[MAXU];
 #pragma unroll
@@ -417,7 +420,7 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab, bool has_pre = fals
     const int n = (u / lm.S) * lm.Lg + g;
     cx[k] = cy[k] = cz[k] = 0.f;
     if (u < lm.U && n < N) {
-      if (CHAIN) {
+      if (lds_recs) {
         cx[k] = a.recs[n].cx;
         cy[k] = a.recs[n].cy;
         cz[k] = a.recs[n].cz;
@@ -473,7 +476,7 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab, bool has_pre = fals
         if (dynamic && st == a.plan.sub - 1 && threadIdx.x == 0) ticket = atomicAdd(grab, 1u);
         PixCoord c{0.f, 0.f, 0.f, 0};
         if (valid) c = pixel_coord(p, a.W, a.H);
-        sw[wave][lane] = CHAIN ? backprop_field_lds(a.recs, n_lo, n_hi, c)
+        sw[wave][lane] = lds_recs ? backprop_field_lds(a.recs, n_lo, n_hi, c)
                                : backprop_field(sp, n_lo, n_hi, c);
         __syncthreads();
         if (wave == 0) {
@@ -515,7 +518,9 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab, bool has_pre = fals
           const int j0 = (sl * kTile) / lm.S + r, j1 = ((sl + 1) * kTile) / lm.S;
           // one unit per wave: four pixels per step, read from LDS
           // together, into two sums (with more units the registers go to
-          // the units' sums)
+          // the units' sums).  Jobs of one unit per wave always run in the
+          // MAXU = 1 launch of their round (LaunchSet), so a hologram sums
+          // in the same order alone and beside holograms of more spots.
           float ar = vr[k], ai = vi[k], br = 0.f, bi = 0.f;
           int j = j0;
           if (MAXU == 1 && lm.R == 1) {
@@ -569,7 +574,7 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab, bool has_pre = fals
           acc.x += v.x;
           acc.y += v.y;
         }
-      acc_add(a.acc, N, a.plan.shift, 1 + tile / a.plan.group_size, n, acc);
+      acc_add(a.acc, N, a.plan.shift, kAccTotalRows + tile / a.plan.group_size, n, acc);
     }
     if (threadIdx.x == 0) {
       done[ndone++] = tile;
@@ -584,11 +589,21 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab, bool has_pre = fals
     }
   }
   count_tiles(a, done, ndone, owned, &nowned);
-  for (int i = 0; i < nowned; ++i)
-    if (tail_group(a, owned[i], &flag)) {
-      tail_final(a, wsum);
-      if (CHAIN) publish_gen(a);
+  if constexpr (!CHAIN && MAXU == 1) {  // (deferring passes have one unit per wave)
+    if (a.defer) {
+      for (int i = 0; i < nowned; ++i) tail_group_deferred(a, owned[i]);
+      return;
     }
+  }
+  // the pass completes at most once, with this block's last group (the
+  // update after the loop keeps the loop's registers free)
+  bool last = false;
+  for (int i = 0; i < nowned; ++i)
+    if (tail_group(a, owned[i], &flag)) last = true;
+  if (last) {
+    tail_final(a, wsum);
+    if (CHAIN) publish_gen(a);
+  }
 }
 
 }  // namespace
@@ -715,7 +730,8 @@ __device__ void pass_block_e(const PassCtx& a, unsigned* grab) {
     }
     // the tile's partials: spot n_lo + lane of each wave
     if (lane < cnt)
-      acc_add(a.acc, N, a.plan.shift, 1 + tile / a.plan.group_size, n_lo + lane, rede[wave][lane]);
+      acc_add(a.acc, N, a.plan.shift, kAccTotalRows + tile / a.plan.group_size, n_lo + lane,
+              rede[wave][lane]);
     if (threadIdx.x == 0) {
       done[ndone++] = tile;
       next_tile = dynamic ? a.plan.blocks + (int)ticket : a.plan.tiles;
@@ -729,9 +745,13 @@ __device__ void pass_block_e(const PassCtx& a, unsigned* grab) {
     }
   }
   count_tiles(a, done, ndone, owned, &nowned);
+  bool last = false;  // (at most once, with this block's last group)
   for (int i = 0; i < nowned; ++i)
-    if (tail_group(a, owned[i], &flag)) tail_final(a, wsum);
+    if (tail_group(a, owned[i], &flag)) last = true;
+  if (last) tail_final(a, wsum);
 }
+
+static_assert(kPendMaxSpots <= kBlock, "a pending update takes one spot per thread");
 
 // Batched pass launch: blocks [descs[i].block_begin, descs[i+1].block_begin)
 // work on pass i.
@@ -771,6 +791,26 @@ __global__ __launch_bounds__(kBlock, MAXU > 4 ? 2 : (MAXE > 16 ? 6 : 8)) void k_
   if constexpr (MAXE > 0) {
     if (jb.shared_e && !d.from_phi) {
       pass_block_e<MAXE>(a, jb.grab + d.grab_slot);
+      return;
+    }
+  }
+  // deferred updates are only planned for launches of one unit per wave
+  // (elsewhere the total row is 0 and no pass defers)
+  if constexpr (MAXU == 1) {
+    a.tot_row = d.tot_row;
+    a.defer = d.defer;
+  }
+  if (d.pending) {
+    if constexpr (MAXU == 1) {
+      __shared__ SpotRec recs[kPendMaxSpots];
+      __shared__ double wsum[kWaves];
+      apply_pending(jb, d, a.lb == 0, recs, wsum);
+      a.recs = recs;
+      if (!d.defer) a.pend_row = d.prev_row;
+      pass_block<MAXU, false, true>(a, jb.grab + d.grab_slot);
+      return;
+    } else {
+      if (a.lb == 0 && threadIdx.x == 0) jb.status[0] = 5;  // HG_EDEVICE
       return;
     }
   }

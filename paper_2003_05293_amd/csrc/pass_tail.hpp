@@ -34,8 +34,14 @@ struct PassCtx {
   // pixels outside the aperture dropped (ap_q >= 0: the whole-grid set)
   int32_t ap_q = -1;
   float ill_a = 0.f;
-  // chained launches: the pass's spot state in LDS, and the generation word
-  // to publish after the update
+  // deferred updates (PassDesc): the total row of this pass's sums, whether
+  // the pass stops after the group sums, and the previous pass's total row,
+  // which the update clears (-1: none)
+  int tot_row = 0;
+  int defer = 0;
+  int pend_row = -1;
+  // chained launches and pending passes: the pass's spot state in LDS;
+  // chained launches: the generation word to publish after the update
   int chain = 0;
   const SpotRec* recs = nullptr;
   unsigned* gen = nullptr;
@@ -62,7 +68,8 @@ __device__ __forceinline__ void load_recs_dev(const SpotRec* sp, int N, SpotRec*
 // fixed-point integer (scale 2^shift, |sum over the pass| <= pixels, so no
 // sum overflows) and added with device-scope integer atomics: integer
 // addition is associative, so the sums do not depend on the order in which
-// tiles, groups or blocks arrive.  Rows: 0 = pass total, 1 + g = group g.
+// tiles, groups or blocks arrive.  Rows: 0..kAccTotalRows-1 = pass totals,
+// kAccTotalRows + g = group g.
 __device__ __forceinline__ void acc_add(unsigned long long* acc, int N, int shift, int row, int n,
                                         float2 v) {
   const double scale = ldexp(1.0, shift);
@@ -83,10 +90,50 @@ __device__ __forceinline__ unsigned long long take_dev(unsigned long long* p) {
 __device__ bool tail_group(const PassCtx& a, int g, int* flag) {
   for (int k = threadIdx.x; k < 2 * a.N; k += kBlock) {
     const int64_t e = (int64_t)(k >> 1) * kAccSpotWords + (k & 1);  // spot k / 2, part k % 2
-    const unsigned long long v = take_dev(a.acc + (int64_t)(1 + g) * a.N * kAccSpotWords + e);
-    atomicAdd(a.acc + e, v);
+    const unsigned long long v = take_dev(a.acc + (int64_t)(kAccTotalRows + g) * a.N * kAccSpotWords + e);
+    atomicAdd(a.acc + (int64_t)a.tot_row * a.N * kAccSpotWords + e, v);
   }
   return arrive_last(&a.counters[a.plan.ngroups * kCounterStride], (unsigned)a.plan.ngroups, flag);
+}
+
+// Group g of a deferring pass is complete: its sums go into the pass total,
+// which the next pass reads after this launch has ended, and the group's
+// counter is ready for the next pass (every count of this pass has arrived).
+__device__ void tail_group_deferred(const PassCtx& a, int g) {
+  for (int k = threadIdx.x; k < 2 * a.N; k += kBlock) {
+    const int64_t e = (int64_t)(k >> 1) * kAccSpotWords + (k & 1);
+    const unsigned long long v = take_dev(a.acc + (int64_t)(kAccTotalRows + g) * a.N * kAccSpotWords + e);
+    atomicAdd(a.acc + (int64_t)a.tot_row * a.N * kAccSpotWords + e, v);
+  }
+  if (threadIdx.x == 0)
+    __hip_atomic_store(a.counters + g * kCounterStride, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// |V_n| and the new record of eqs. (4)-(6): the one place that does this
+// arithmetic, so that a deferred update gives the bits of an immediate one.
+__device__ __forceinline__ double field_mag(double2 t) { return sqrt(t.x * t.x + t.y * t.y); }
+// false (record unchanged) where the weight would come out zero or not finite
+__device__ __forceinline__ bool update_rec(SpotRec& r, double2 v, double mag, double mean,
+                                           double* w_out) {
+  const double w = (double)r.w * (mean / mag);
+  if (!(mag > 0.0) || !isfinite(w)) return false;
+  r.w = (float)w;
+  r.A = (float)(w * (double)r.a0);
+  // theta is kept in FP32 turns: the FP32 arctangent of the FP64 sum
+  // (rounded to FP32) is within a few FP32 ulps of the rounded FP64 one
+  r.th = atan2f((float)v.y, (float)v.x) * 0.15915494309189535f;
+  *w_out = w;
+  return true;
+}
+// Sum of a per-thread value over the block in a fixed order: within each
+// wave, then the waves in order.
+__device__ __forceinline__ double block_sum_fixed(double x, double* wsum) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = x;
+  __syncthreads();
+  double total = wsum[0];
+  for (int w = 1; w < kWaves; ++w) total += wsum[w];
+  return total;
 }
 
 // Every group is complete: V_n = total / 2^shift / |Omega| (the total row is
@@ -96,12 +143,21 @@ __device__ void tail_final(const PassCtx& a, double* wsum) {
   const int N = a.N;
   const double inv = ldexp(1.0, -a.plan.shift) * a.inv_count;
   double magsum = 0.0;
+  unsigned long long* tot = a.acc + (int64_t)a.tot_row * N * kAccSpotWords;
   for (int n = threadIdx.x; n < N; n += kBlock) {
-    const long long re = (long long)take_dev(a.acc + (int64_t)n * kAccSpotWords);
-    const long long im = (long long)take_dev(a.acc + (int64_t)n * kAccSpotWords + 1);
+    const long long re = (long long)take_dev(tot + (int64_t)n * kAccSpotWords);
+    const long long im = (long long)take_dev(tot + (int64_t)n * kAccSpotWords + 1);
     const double2 t = make_double2((double)re * inv, (double)im * inv);
     a.V[n] = t;
-    magsum += sqrt(t.x * t.x + t.y * t.y);
+    magsum += field_mag(t);
+  }
+  // the previous pass's total, which every block of this pass has read
+  // before counting its tiles, is cleared
+  if (a.pend_row >= 0) {
+    HG_GLOBAL unsigned long long* q =
+        as_global_mut(a.acc + (int64_t)a.pend_row * N * kAccSpotWords);
+    for (int k = threadIdx.x; k < N * kAccSpotWords; k += kBlock)
+      __hip_atomic_store(q + k, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   // the counters are ready for the next pass (kernel end orders these
   // writes; in a chained launch, the generation word)
@@ -113,32 +169,82 @@ __device__ void tail_final(const PassCtx& a, double* wsum) {
   }
   if (!a.update) return;
   // sum of |V_n| in a fixed order: per thread, within each wave, then the waves
-  for (int off = 32; off > 0; off >>= 1) magsum += __shfl_xor(magsum, off);
-  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = magsum;
-  __syncthreads();
-  double total = wsum[0];
-  for (int w = 1; w < kWaves; ++w) total += wsum[w];
-  const double mean = total / (double)N;
+  const double mean = block_sum_fixed(magsum, wsum) / (double)N;
   for (int n = threadIdx.x; n < N; n += kBlock) {
     const double2 v = a.V[n];  // written above by this same thread
-    const double mag = sqrt(v.x * v.x + v.y * v.y);
-    SpotRec r = a.chain ? a.recs[n] : a.sp[n];
-    const double w = (double)r.w * (mean / mag);
-    if (!(mag > 0.0) || !isfinite(w)) {
+    const double mag = field_mag(v);
+    SpotRec r = a.recs ? a.recs[n] : a.sp[n];
+    double w;
+    if (!update_rec(r, v, mag, mean, &w)) {
       a.status[0] = 4;  // HG_ENUMERIC
+      if (a.recs && !a.chain) a.sp[n] = r;  // the state this pass used
       continue;
     }
-    r.w = (float)w;
-    r.A = (float)(w * (double)r.a0);
-    // theta is kept in FP32 turns: the FP32 arctangent of the FP64 sum
-    // (rounded to FP32) is within a few FP32 ulps of the rounded FP64 one
-    r.th = atan2f((float)v.y, (float)v.x) * 0.15915494309189535f;
     if (a.chain) store_rec_dev(a.sp + n, r);
     else a.sp[n] = r;
     // C_n = A_n e^{i theta_n} = A_n V_n / |V_n|
     const double Am = w * (double)r.a0 / mag;
     a.coef[n] = make_float2((float)(Am * v.x), (float)(Am * v.y));
   }
+}
+
+// Pending pass: every block applies the previous pass's update to the state
+// before it (d.st_in) and keeps the result in recs (LDS), with the
+// arithmetic and summation order of tail_final.  Block 0 (lead) also
+// clears the total row two passes back, stores the state for the next pass
+// when this pass defers in turn, the previous V when traced, and the status.
+// N <= kPendMaxSpots <= kBlock: one spot per thread.
+__device__ void apply_pending(const JobDev& jb, const PassDesc& d, bool lead, SpotRec* recs,
+                              double* wsum) {
+  const int N = jb.N;
+  const int n = threadIdx.x;
+  if (lead && d.clear_row >= 0) {
+    HG_GLOBAL unsigned long long* q =
+        as_global_mut(jb.acc + (int64_t)d.clear_row * N * kAccSpotWords);
+    for (int k = threadIdx.x; k < N * kAccSpotWords; k += kBlock)
+      __hip_atomic_store(q + k, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  double2 t = make_double2(0.0, 0.0);
+  double magsum = 0.0;
+  // the record as eight words (a struct copy through a generic pointer
+  // would go through the stack)
+  constexpr int kWords = (int)(sizeof(SpotRec) / sizeof(float));
+  float f[kWords];
+#pragma unroll
+  for (int k = 0; k < kWords; ++k) f[k] = 0.f;
+  if (n < N) {
+    const HG_GLOBAL unsigned long long* tot =
+        as_global(jb.acc + ((int64_t)d.prev_row * N + n) * kAccSpotWords);
+    const long long re = (long long)__hip_atomic_load(tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const long long im = (long long)__hip_atomic_load(tot + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    t = make_double2((double)re * d.prev_inv, (double)im * d.prev_inv);
+    magsum += field_mag(t);
+    const HG_GLOBAL float* src = as_global(reinterpret_cast<const float*>(d.st_in + n));
+#pragma unroll
+    for (int k = 0; k < kWords; ++k) f[k] = src[k];
+  }
+  const double mean = block_sum_fixed(magsum, wsum) / (double)N;
+  if (n < N) {
+    if (lead && d.prev_V) {
+      HG_GLOBAL double* v = as_global_mut(reinterpret_cast<double*>(d.prev_V + n));
+      v[0] = t.x;
+      v[1] = t.y;
+    }
+    SpotRec r;
+    __builtin_memcpy(&r, f, sizeof(r));
+    double w;
+    if (!update_rec(r, t, field_mag(t), mean, &w) && lead) jb.status[0] = 4;  // HG_ENUMERIC
+    __builtin_memcpy(f, &r, sizeof(r));
+    float* dst = reinterpret_cast<float*>(recs + n);
+#pragma unroll
+    for (int k = 0; k < kWords; ++k) dst[k] = f[k];
+    if (lead && d.st_out) {
+      HG_GLOBAL float* out = as_global_mut(reinterpret_cast<float*>(d.st_out + n));
+#pragma unroll
+      for (int k = 0; k < kWords; ++k) out[k] = f[k];
+    }
+  }
+  __syncthreads();
 }
 
 // Chained launch: the update of this pass is complete (this block's state

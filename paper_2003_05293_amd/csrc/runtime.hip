@@ -366,6 +366,7 @@ JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev
   L.raw_inline = raw_inline && !s.spots_on_device;
   L.off_raw = L.raw_inline ? take(sizeof(double) * 4 * (size_t)s.N) : 0;
   L.off_sp = take(sizeof(SpotRec) * (size_t)s.N);
+  if (!j.mixed) L.off_sp_alt = take(sizeof(SpotRec) * (size_t)s.N);
   L.off_coef = take(sizeof(float2) * (size_t)s.N);
   L.off_tab = j.compressed ? take(sizeof(uint32_t) * ((size_t)kFeistelRoundsHost << j.h)) : 0;
   L.off_perm = j.compressed ? take(sizeof(int32_t) * (size_t)j.P) : 0;
@@ -382,7 +383,7 @@ JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev
     L.off_partial = take(sizeof(float2) * (size_t)max_rows * s.N);
     L.off_gpart = take(sizeof(double2) * (size_t)max_groups * s.N);
   } else {        // exact fixed-point sums of the FP32 passes
-    j.acc_len = (int64_t)(max_groups + 1) * s.N * kAccSpotWords;
+    j.acc_len = (int64_t)(max_groups + kAccTotalRows) * s.N * kAccSpotWords;
     L.off_acc = take(sizeof(unsigned long long) * (size_t)j.acc_len);
   }
   L.off_counters = take(sizeof(unsigned) * (size_t)j.counters_len);
@@ -408,6 +409,10 @@ JobDev bind_job(const JobLayout& L, const JobSpec& s, char* base, const double* 
     j.in = SpotPtrs{r, r + s.N, r + 2 * s.N, r + 3 * s.N};
   }
   j.sp = reinterpret_cast<SpotRec*>(base + L.off_sp);
+  j.sp_alt = j.mixed ? nullptr : reinterpret_cast<SpotRec*>(base + L.off_sp_alt);
+  // jobs of one spot unit per wave run in the one-unit pass launch of each
+  // round, whose kernel applies deferred updates
+  j.defer_ok = (!j.mixed && pass_units_per_wave(s.N) == 1) ? 1 : 0;
   j.coef = reinterpret_cast<float2*>(base + L.off_coef);
   j.tab = j.compressed ? reinterpret_cast<uint32_t*>(base + L.off_tab) : nullptr;
   j.perm = j.compressed ? reinterpret_cast<int32_t*>(base + L.off_perm) : nullptr;
@@ -453,6 +458,24 @@ PassDesc iteration_desc(const JobDev& j, const JobLayout& L, int it, int index, 
   d.grab_slot = it;
   d.inv_count = 1.0 / (double)(sub ? j.m : j.P);  // eq. (3): the mean over the set
   d.V = j.V + (j.trace ? (size_t)(it - 1) * j.N : 0);
+  // Deferred updates: compressed passes 1..I-1 in the per-pixel FP32 form
+  // follow one another; each but the last leaves its update to the next.
+  // State X_k (after k updates) lives in buffer k mod 2 (0: sp, 1: sp_alt):
+  // pass it reads X_{it-2} and, when it defers, stores X_{it-1}.
+  if (sub && j.defer_ok && !j.mixed && !j.shared_e && j.N <= kPendMaxSpots && j.sp_alt) {
+    SpotRec* const buf[2] = {j.sp, j.sp_alt};
+    d.tot_row = it % kAccTotalRows;
+    d.defer = it + 1 < j.iterations ? 1 : 0;
+    if (it >= 2) {
+      d.pending = 1;
+      d.prev_row = (it - 1) % kAccTotalRows;
+      d.clear_row = (it + 1) % kAccTotalRows;
+      d.prev_inv = std::ldexp(1.0, -L.plan_sub.shift) * (1.0 / (double)j.m);  // as the tail forms it
+      d.st_in = buf[(it - 2) % 2];
+      d.st_out = d.defer ? buf[(it - 1) % 2] : nullptr;
+      d.prev_V = j.trace ? j.V + (size_t)(it - 2) * j.N : nullptr;
+    }
+  }
   return d;
 }
 
@@ -525,11 +548,18 @@ void LaunchSet::add_iteration(const JobDev& j, const JobLayout& L, int it, int i
     sep_steps = std::max(sep_steps, j.mx_steps);
     return;
   }
+  const int u = j.shared_e ? 1 : pass_units_per_wave(j.N);
+  if (u > 1) {
+    const PassDesc d = iteration_desc(j, L, it, index, wide_blocks);
+    wide.push_back(d);
+    wide_blocks += d.plan.blocks;
+    wide_units = std::max(wide_units, u);
+    return;
+  }
   const PassDesc d = iteration_desc(j, L, it, index, pass_blocks);
   pass.push_back(d);
   pass_blocks += d.plan.blocks;
   if (j.shared_e) e_width = std::max(e_width, pass_e_width(j.N));
-  else units = std::max(units, pass_units_per_wave(j.N));
 }
 
 void LaunchSet::add_final(const JobDev& j, const JobLayout& L, int index) {
@@ -561,7 +591,8 @@ void LaunchSet::add_final(const JobDev& j, const JobLayout& L, int index) {
 }
 
 size_t LaunchSet::bytes() const {
-  return align_up(sizeof(PassDesc) * pass.size(), 256) + align_up(sizeof(SepDesc) * sep.size(), 256) +
+  return align_up(sizeof(PassDesc) * pass.size(), 256) + align_up(sizeof(PassDesc) * wide.size(), 256) +
+         align_up(sizeof(SepDesc) * sep.size(), 256) +
          align_up(sizeof(BackDesc) * back.size(), 256) + align_up(sizeof(MxDesc) * mx.size(), 256);
 }
 
@@ -574,17 +605,25 @@ size_t LaunchSet::stage(char* host, char* dev) {
     return dev + at;
   };
   d_pass = reinterpret_cast<const PassDesc*>(put(pass.data(), sizeof(PassDesc) * pass.size()));
+  d_wide = reinterpret_cast<const PassDesc*>(put(wide.data(), sizeof(PassDesc) * wide.size()));
   d_sep = reinterpret_cast<const SepDesc*>(put(sep.data(), sizeof(SepDesc) * sep.size()));
   d_back = reinterpret_cast<const BackDesc*>(put(back.data(), sizeof(BackDesc) * back.size()));
   d_mx = reinterpret_cast<const MxDesc*>(put(mx.data(), sizeof(MxDesc) * mx.size()));
   return o;
 }
 
-const char* LaunchSet::pass_only_name() const {
-  if (pass.empty() || !sep.empty() || !back.empty() || !mx.empty()) return nullptr;
+namespace {
+const char* pass_name(const std::vector<PassDesc>& a, const std::vector<PassDesc>& b) {
   bool any_full = false, any_sub = false;
-  for (const PassDesc& d : pass) (d.ps.count == d.ps.M && !d.ps.perm ? any_full : any_sub) = true;
+  for (const auto* v : {&a, &b})
+    for (const PassDesc& d : *v) (d.ps.count == d.ps.M && !d.ps.perm ? any_full : any_sub) = true;
   return any_full && any_sub ? "k_pass_mixed" : any_sub ? "k_pass_subset" : "k_pass_full";
+}
+}  // namespace
+
+const char* LaunchSet::pass_only_name() const {
+  if ((pass.empty() && wide.empty()) || !sep.empty() || !back.empty() || !mx.empty()) return nullptr;
+  return pass_name(pass, wide);
 }
 
 void LaunchSet::launch(const JobDev* jobs, hipStream_t s, bool capture) const {
@@ -596,12 +635,13 @@ void LaunchSet::launch(const JobDev* jobs, hipStream_t s, bool capture) const {
     run(sep_final ? "k_sep_final" : "k_sep_pass", [&] {
       launch_sep_pass(jobs, d_sep, (int)sep.size(), sep_blocks, sep_final, sep_steps, s);
     });
-  if (!pass.empty()) {
-    bool any_full = false, any_sub = false;
-    for (const PassDesc& d : pass) (d.ps.count == d.ps.M && !d.ps.perm ? any_full : any_sub) = true;
-    run(any_full && any_sub ? "k_pass_mixed" : any_sub ? "k_pass_subset" : "k_pass_full",
-        [&] { launch_pass_batch(jobs, d_pass, (int)pass.size(), pass_blocks, units, e_width, s); });
-  }
+  if (!pass.empty())
+    run(pass_name(pass, {}),
+        [&] { launch_pass_batch(jobs, d_pass, (int)pass.size(), pass_blocks, 1, e_width, s); });
+  if (!wide.empty())
+    run(pass_name(wide, {}), [&] {
+      launch_pass_batch(jobs, d_wide, (int)wide.size(), wide_blocks, wide_units, 0, s);
+    });
   if (!back.empty())
     run("k_backprop_phi",
         [&] { launch_backprop_batch(jobs, d_back, (int)back.size(), back_blocks, s); });
@@ -688,7 +728,16 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
     const int units = pass_units_per_wave(j.N);
     if (j.compressed && !j.mixed && !j.shared_e && j.N <= kChainMaxSpots && passes >= 2 &&
         layouts_[0].plan_sub.blocks <= pass_chain_capacity(units)) {
-      for (int r = 0; r < passes; ++r) chain_descs_.push_back(rounds_[r].pass.at(0));
+      for (int r = 0; r < passes; ++r) {
+        // a chained launch hands the state over inside the launch
+        PassDesc d = rounds_[r].pass.at(0);
+        d.defer = d.pending = d.tot_row = d.prev_row = 0;
+        d.clear_row = -1;
+        d.st_in = nullptr;
+        d.st_out = nullptr;
+        d.prev_V = nullptr;
+        chain_descs_.push_back(d);
+      }
       chain_rounds_ = passes;
       chain_blocks_ = layouts_[0].plan_sub.blocks;
       chain_units_ = units;

@@ -128,7 +128,7 @@ struct JobLayout {
   JobDev dev;  // every field but the pointers
   PassPlan plan_all, plan_sub, plan_sep, plan_mx;
   bool separable = false;
-  size_t off_raw = 0, off_sp = 0, off_coef = 0, off_tab = 0, off_perm = 0, off_partial = 0,
+  size_t off_raw = 0, off_sp = 0, off_sp_alt = 0, off_coef = 0, off_tab = 0, off_perm = 0, off_partial = 0,
          off_gpart = 0, off_acc = 0, off_counters = 0, off_V = 0, off_sepFc = 0, off_sepFn = 0,
          off_sepGa = 0, off_sepGv = 0, off_mxFc = 0, off_mxFn = 0, off_mxGa = 0, off_mxGv = 0,
          off_rank = 0, off_rows = 0;
@@ -152,9 +152,14 @@ PixelSet all_pixels(int32_t M);
 // (k_sep_pass, on the factor tables built by the prologue), direct full-grid final phases (k_backprop_batch) and the
 // passes of mixed-precision jobs (k_mx_pass).
 struct LaunchSet {
+  // per-pixel passes in two launches: jobs of one spot unit per wave (and
+  // the shared-exponential form) in `pass`, wider jobs in `wide`, so that
+  // every job runs in the same kernel form alone and in any batch
   std::vector<PassDesc> pass;
-  int pass_blocks = 0, units = 1;
+  int pass_blocks = 0;
   int e_width = 0;  // widest shared-exponential form among the passes (0: none)
+  std::vector<PassDesc> wide;
+  int wide_blocks = 0, wide_units = 1;
   std::vector<SepDesc> sep;
   int sep_blocks = 0, sep_steps = 0;
   bool sep_final = false;
@@ -165,6 +170,7 @@ struct LaunchSet {
   int mx_mode = kMxIterate;
   // device copies, set by stage()
   const PassDesc* d_pass = nullptr;
+  const PassDesc* d_wide = nullptr;
   const SepDesc* d_sep = nullptr;
   const BackDesc* d_back = nullptr;
   const MxDesc* d_mx = nullptr;
@@ -174,7 +180,9 @@ struct LaunchSet {
   // Forward projection of the job's stored hologram (mixed precision, all
   // pixels, no update).
   void add_forward_mx(const JobDev& j, const JobLayout& L, int index);
-  bool empty() const { return pass.empty() && sep.empty() && back.empty() && mx.empty(); }
+  bool empty() const {
+    return pass.empty() && wide.empty() && sep.empty() && back.empty() && mx.empty();
+  }
   // Timing name of the set's per-pixel pass launch when that is all the set
   // launches, else nullptr.
   const char* pass_only_name() const;
