@@ -205,8 +205,17 @@ __device__ void mx_tail(const JobDev& jb, const MxDesc& d, int lb) {
   }
   if (!arrive_last(&jb.counters[d.plan.ngroups * kCounterStride], (unsigned)d.plan.ngroups, &last))
     return;
-  SpotRec pre{};
-  if (d.update && s == 0 && c < N) pre = jb.sp[c];
+  // this thread's first record, requested before the sums are read (as
+  // eight words: a record copied whole into a local would take a stack slot)
+  constexpr int kRecWords = (int)(sizeof(SpotRec) / sizeof(float));
+  float pre[kRecWords];
+#pragma unroll
+  for (int k = 0; k < kRecWords; ++k) pre[k] = 0.f;
+  if (d.update && s == 0 && c < N) {
+    const HG_GLOBAL float* q = as_global(reinterpret_cast<const float*>(jb.sp + c));
+#pragma unroll
+    for (int k = 0; k < kRecWords; ++k) pre[k] = q[k];
+  }
   const ColumnSrc gsrc = column_src(gsum, d.plan.ngroups, N);
   float msum = 0.f;
   for (int n0 = 0; n0 < N; n0 += Npad) {
@@ -237,7 +246,17 @@ __device__ void mx_tail(const JobDev& jb, const MxDesc& d, int lb) {
     const double2 vd = d.V[n];  // written above by this same thread
     const float vr = (float)vd.x, vi = (float)vd.y;
     const float mag = sqrtf(vr * vr + vi * vi);
-    SpotRec r = n == c ? pre : jb.sp[n];
+    float f[kRecWords];
+    if (n == c) {
+#pragma unroll
+      for (int k = 0; k < kRecWords; ++k) f[k] = pre[k];
+    } else {
+      const HG_GLOBAL float* q = as_global(reinterpret_cast<const float*>(jb.sp + n));
+#pragma unroll
+      for (int k = 0; k < kRecWords; ++k) f[k] = q[k];
+    }
+    SpotRec r;
+    __builtin_memcpy(&r, f, sizeof(r));
     const float w = r.w * (mean / mag);
     if (!(mag > 0.f) || !isfinite(w)) {
       jb.status[0] = 4;  // HG_ENUMERIC
