@@ -13,7 +13,9 @@ unchanged, so the bars are bit-identity:
   start each hologram at zero);
 - a hologram alone against the same hologram in a batch beside a hologram
   of 300 spots (four spot units per wave): holograms of one unit per wave
-  run in their own launch of each round, so they sum in the same order.
+  run in their own launch of each round, so they sum in the same order;
+  likewise for requests of 5, 100, 256 and 300 spots served together by
+  the engine.
 Parity of the results with the FP64 oracle is covered by the parity suites.
 """
 import numpy as np
@@ -93,3 +95,31 @@ def test_back_to_back_holograms():
     assert np.array_equal(a.cpu().numpy(), ref1)
     assert np.array_equal(b.cpu().numpy(), ref2)
     assert np.array_equal(c.cpu().numpy(), ref1)
+
+
+def test_engine_mix_of_unit_widths_equals_alone():
+    import torch
+    say("engine 100 + 300 + 5 spots")
+    specs = [(100, 6, 1), (300, 4, 2), (5, 7, 3), (256, 5, 4)]
+    alone = [hg.cswgs(G, OPTICS, spot_cloud(40 + k, n, G), it, 0.25, seed).cpu().numpy()
+             for k, (n, it, seed) in enumerate(specs)]
+    e = hg.Engine(1 << 28, 8)
+    st = torch.cuda.Stream()
+    phis, tickets = [], []
+    for k, (n, it, seed) in enumerate(specs):
+        p = torch.empty(G.M, dtype=torch.float32, device="cuda")
+        phis.append(p)
+        tickets.append(e.submit(G, OPTICS, spot_cloud(40 + k, n, G), it, 0.25, seed, p))
+    done = set()
+    for _ in range(100):
+        e.step(stream=st)
+        for t in tickets:
+            if t not in done and e.poll(t):
+                done.add(t)
+        if len(done) == len(tickets):
+            break
+    st.synchronize()
+    e.close()
+    assert len(done) == len(tickets)
+    for k in range(len(specs)):
+        assert np.array_equal(phis[k].cpu().numpy(), alone[k]), specs[k]
