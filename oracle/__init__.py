@@ -14,7 +14,8 @@ Parity status of each function is stated in the module headers:
                (tests/test_oracle_*.py); the full CS-WGS trajectory has no
                printed worked example in the paper and is pinned only
                through those pieces.
-  slm.py     - phase-to-gray lookup, pinned by exact arithmetic on the bins
+  slm.py     - phase-to-gray lookup from the bin definition (FP64, exact at
+               bin edges), pinned by 60-digit arithmetic on the bins
 """
 from .philox import philox4x64_10, PHILOX_M, PHILOX_W  # noqa: F401
 from .sampler import (  # noqa: F401
@@ -22,6 +23,6 @@ from .sampler import (  # noqa: F401
 )
 from .hg import (  # noqa: F401
     pixel_offsets_mm, spot_phase, backward, forward, update, rs, wgs, cswgs,
-    metrics, Trace, pupil_pixels, illumination,
+    metrics, Trace, pupil_pixels, illumination, efficiency, uniformity,
 )
-from .slm import gray_index, gray_levels  # noqa: F401
+from .slm import gray_index, gray_levels, gray_bin, fp32_edge_tolerance  # noqa: F401

@@ -47,7 +47,9 @@ arg(0) is 0.  Pixel sets are processed in fixed chunks only to bound memory.
 
 Pins: tests/test_oracle_hg.py (mpmath brute force of eq. 2, one- and two-spot
 closed forms, the theta-shift invariant, an FFT pin of the forward sum,
-I=0 == RS, c=1 == WGS, stationarity of a single spot, e=u=1 for one spot).
+I=0 == RS, c=1 == WGS, stationarity of a single spot, e=u=1 for one spot,
+e and u of eq. 7 on hand-worked intensities and on a sinusoidal phase
+grating, whose diffraction orders carry Bessel-function amplitudes).
 """
 from __future__ import annotations
 
@@ -205,6 +207,21 @@ def cswgs(grid, optics, spots, iterations: int, compression: float, seed: int,
     return _iterate(grid, optics, spots, iterations, seed, compression, trace)
 
 
+def efficiency(I, power: float = 1.0) -> float:
+    """The fraction of the SLM's power that lands in the spots (section 2,
+    last paragraph): sum_n I_n over the power on the SLM, mean_Omega(A^2)
+    (1 under uniform illumination)."""
+    return float(np.sum(np.asarray(I, dtype=np.float64))) / float(power)
+
+
+def uniformity(I) -> float:
+    """eq. (7): u = 1 - (max_n I_n - min_n I_n) / (max_n I_n + min_n I_n),
+    with I_n the spot intensities |V*_n|^2."""
+    I = np.asarray(I, dtype=np.float64)
+    hi, lo = float(I.max()), float(I.min())
+    return 1.0 - (hi - lo) / (hi + lo)
+
+
 def metrics(grid, optics, spots, Phi):
     """Efficiency e, uniformity u (eq. 7) and spot intensities I_n of the
     hologram Phi (all pixels, index order), over Omega."""
@@ -212,6 +229,4 @@ def metrics(grid, optics, spots, Phi):
     V = forward(grid, optics, spots, np.asarray(Phi, dtype=np.float64)[pupil], pupil)
     I = np.abs(V) ** 2
     power = float(np.mean(illumination(grid, optics, pupil) ** 2))
-    e = float(I.sum()) / power
-    u = float(1.0 - (I.max() - I.min()) / (I.max() + I.min()))
-    return e, u, I
+    return efficiency(I, power), uniformity(I), I

@@ -1,8 +1,11 @@
 """SLM output: the phase-to-gray lookup on the GPU against the oracle's
 (oracle/slm.py), through the C ABI.
 
-The gray level is an integer decided by FP32 arithmetic, so both sides take
-it in FP32 with the same rounded steps and the bar is bit-exact:
+The gray level is the table entry of the phase's bin (oracle/slm.py: the
+exact bin of the phase value the device holds).  The device decides the bin
+in FP32, so its gray level must be that of the exact bin, except for a phase
+within the FP32 rounding of a bin edge (oracle.fp32_edge_tolerance), where
+the bin on the other side of the edge is accepted too:
 * hg_phase_to_gray on random and adversarial phases (bin edges, whole
   turns, negative phases), for 8- and 16-bit tables of several sizes, ragged
   counts and an image that is not 4-byte aligned;
@@ -51,6 +54,22 @@ def slm_table(levels, bits, gamma=0.8):
     return np.rint(G * k ** gamma).astype(np.uint16)
 
 
+def assert_gray_matches(got, phi, table):
+    """got[p] is table[k] for the exact bin k of phi[p], or a neighbouring
+    bin's entry where phi[p] lies within FP32 rounding of the edge between
+    them."""
+    L = table.shape[0]
+    phi = np.asarray(phi, dtype=np.float32)
+    k, d = oracle.gray_bin(phi, L)
+    tab = table.astype(np.int64)
+    exact = got == tab[k]
+    near = d <= oracle.fp32_edge_tolerance(phi, L)
+    nb = near & ((got == tab[(k + 1) % L]) | (got == tab[(k - 1) % L]))
+    bad = np.flatnonzero(~(exact | nb))
+    assert bad.size == 0, [(float(phi[i]), int(got[i]), int(k[i]), float(d[i])) for i in bad[:5]]
+    return int(np.count_nonzero(~exact))
+
+
 def adversarial_phases(n, seed):
     rng = np.random.default_rng(seed)
     parts = [rng.uniform(-math.pi, math.pi, n), rng.uniform(-60, 60, n // 4)]
@@ -76,16 +95,17 @@ def test_phase_to_gray_bit_exact(levels, bits, count_off):
         d_phi = torch.as_tensor(phi, device="cuda")
         gray = hg.phase_to_gray(lut, d_phi)
         got = to_np(gray).astype(np.int64) & (0xFF if bits == 8 else 0xFFFF)
-        want = oracle.gray_levels(phi, table).astype(np.int64)
-        assert np.array_equal(got, want)
+        off = assert_gray_matches(got, phi, table)
+        print(f"  {phi.shape[0]} phases, {off} in the neighbouring bin of an edge", flush=True)
         if bits == 8:
-            # an image one byte off 4-byte alignment, and a tiny count
+            # an image one byte off 4-byte alignment, and a tiny count: the
+            # same levels as the aligned image
             buf = torch.zeros(phi.shape[0] + 1, dtype=torch.uint8, device="cuda")
             hg.phase_to_gray(lut, d_phi, gray=buf[1:])
-            assert np.array_equal(to_np(buf[1:]).astype(np.int64), want)
+            assert np.array_equal(to_np(buf[1:]).astype(np.int64), got)
             assert to_np(buf)[0] == 0
             g3 = hg.phase_to_gray(lut, d_phi[:3])
-            assert np.array_equal(to_np(g3).astype(np.int64), want[:3])
+            assert np.array_equal(to_np(g3).astype(np.int64), got[:3])
     finally:
         lut.close()
 
@@ -112,8 +132,9 @@ def test_final_pass_writes_gray_image(form, bits):
         ref = hg.cswgs(g, opt, s, 8, 0.1, 11, **kw)
         torch.cuda.synchronize()
         assert torch.equal(phi, ref)
-        want = oracle.gray_levels(to_np(phi), table).astype(np.int64)
-        assert np.array_equal(_gray_of(gray, bits), want)
+        assert_gray_matches(_gray_of(gray, bits), to_np(phi), table)
+        # the fused epilogue and the standalone conversion agree bit for bit
+        assert np.array_equal(_gray_of(gray, bits), _gray_of(hg.phase_to_gray(lut, phi), bits))
     finally:
         lut.close()
 

@@ -14,6 +14,9 @@ mathematics fix, independently of the oracle's own code:
 * schedule identities: I = 0 is RS, c = 1 is WGS, CS-WGS with I = 1 is WGS;
 * efficiency: e <= 1 for distinct lattice spots (Parseval), two equal spots
   give the binary-grating value 8/pi^2, many random spots give pi/4;
+* eq. (7) and the efficiency on hand-worked intensities, and on a sinusoidal
+  phase grating whose orders carry Bessel-function amplitudes J_m(a)
+  (Jacobi-Anger), which fixes unequal intensities in closed form;
 * the paper's qualitative claims (RS e,u > 0.2; converged WGS on a regular
   grid e,u > 0.9) as smoke checks.
 
@@ -249,9 +252,42 @@ def pin_efficiency_many_spots():
     assert abs(e - math.pi / 4) < 0.02
 
 
+def pin_metrics_hand_worked():
+    """eq. (7) and the efficiency on intensities worked out by hand."""
+    assert abs(H.uniformity([1.0, 4.0, 2.0]) - 0.4) < 1e-15       # 1 - 3/5
+    assert abs(H.uniformity([1.0, 9.0]) - 0.2) < 1e-15            # 1 - 8/10
+    assert abs(H.uniformity([0.25, 0.25, 0.25]) - 1.0) < 1e-15
+    assert abs(H.uniformity([0.5, 0.3, 0.1, 0.3]) - (1.0 - 0.4 / 0.6)) < 1e-15
+    assert abs(H.efficiency([1.0, 4.0, 2.0]) - 7.0) < 1e-15
+    assert abs(H.efficiency([0.1, 0.2, 0.3], power=0.5) - 1.2) < 1e-15
+
+
+def pin_metrics_bessel_grating():
+    """e and u of a hologram with unequal spot intensities known in closed
+    form: the sinusoidal phase grating Phi = a cos(2 pi k i / W) diffracts
+    into orders m k with amplitudes J_m(a) (Jacobi-Anger expansion), so spots
+    on the lattice at orders m = 0..3 have I_m = J_m(a)^2 (aliased orders
+    m + 32 q contribute J_32(a) ~ 1e-36)."""
+    from scipy.special import jv
+    g = Grid(256, 8)
+    k = 8
+    orders = np.array([0, 1, 2, 3])
+    s = lattice_spots(g, OPTICS, orders * k, np.zeros(4), amp=np.full(4, 0.5))
+    i = np.arange(g.M) % g.W
+    for a in (1.5, 2.0):
+        Phi = a * np.cos(2 * math.pi * k * i / g.W)
+        e, u, I = oracle.metrics(g, OPTICS, s, Phi)
+        want = jv(orders, a) ** 2
+        assert np.abs(I - want).max() < 1e-13, (a, I, want)
+        assert abs(e - want.sum()) < 1e-13
+        u_want = 1.0 - (want.max() - want.min()) / (want.max() + want.min())
+        assert abs(u - u_want) < 1e-12, (a, u, u_want)
+
+
 PINS = [pin_phase_mpmath, pin_phase_structure, pin_bruteforce_tiny, pin_one_spot_closed_form,
         pin_two_spot_closed_form, pin_invariants, pin_forward_fft, pin_update,
-        pin_single_spot_stationary, pin_schedules, pin_efficiency, pin_efficiency_many_spots]
+        pin_single_spot_stationary, pin_schedules, pin_efficiency, pin_efficiency_many_spots,
+        pin_metrics_hand_worked, pin_metrics_bessel_grating]
 
 
 @pytest.mark.parametrize("pin", PINS, ids=[p.__name__ for p in PINS])
@@ -345,6 +381,29 @@ def _mut_backward_amp_squared(grid, optics, spots, w, theta, p=None):
     return _orig_backward(grid, optics, spots, np.asarray(w) ** 2, theta, p)
 
 
+def _mut_uniformity_over_max(I):
+    I = np.asarray(I)
+    return 1.0 - (I.max() - I.min()) / I.max()
+
+
+def _mut_uniformity_of_magnitudes(I):
+    A = np.sqrt(np.asarray(I))
+    return 1.0 - (A.max() - A.min()) / (A.max() + A.min())
+
+
+def _mut_uniformity_min_over_max(I):
+    I = np.asarray(I)
+    return I.min() / I.max()
+
+
+def _mut_efficiency_mean(I, power=1.0):
+    return float(np.mean(I)) / power
+
+
+def _mut_efficiency_of_magnitudes(I, power=1.0):
+    return float(np.sum(np.sqrt(np.asarray(I)))) / power
+
+
 _orig_backward = H.backward
 
 MUTANTS = {
@@ -355,6 +414,11 @@ MUTANTS = {
     "update_inverted": ("update", _mut_update_inverted),
     "backward_no_theta": ("backward", _mut_backward_no_theta),
     "backward_w_squared": ("backward", _mut_backward_amp_squared),
+    "uniformity_over_max": ("uniformity", _mut_uniformity_over_max),
+    "uniformity_of_magnitudes": ("uniformity", _mut_uniformity_of_magnitudes),
+    "uniformity_min_over_max": ("uniformity", _mut_uniformity_min_over_max),
+    "efficiency_mean": ("efficiency", _mut_efficiency_mean),
+    "efficiency_of_magnitudes": ("efficiency", _mut_efficiency_of_magnitudes),
 }
 
 
