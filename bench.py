@@ -25,6 +25,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -43,29 +45,25 @@ CLOUDS = 10
 # per (pixel, spot) pair.
 FLOPS_BACK = 10
 FLOPS_FWD = 14
-# Issue-limited ALU peak of the per-pixel passes, from the chip's unit
-# counts and clock: the FP32 vector peak of 157.3 TFLOP/s is 256 CU x 2.4 GHz
-# x 128 FMA lanes per clock per CU = 78.65 T FMA/s.  Transcendentals
-# (v_sin_f32, v_cos_f32) issue at a quarter of that rate (19.7 T/s; the
-# microbenchmark paper_2003_05293_amd/bench_alu measures 19.0 and 19.4 T/s).
+# Roofline of the per-pixel passes: plain FP32 vector ALU work (phases,
+# v_fract_f32, v_sin_f32 / v_cos_f32, FMAs), reported against MI355X's
+# published FP32 vector peak, 157.3 TFLOP/s = 256 CU x 2.4 GHz x 128 FMA
+# lanes per clock per CU = 78.65 T FMA/s.  The microbenchmark
+# paper_2003_05293_amd/bench_alu (built without packed FP32 instructions)
+# measures non-packed FP32 operations at up to 0.89 of that issue rate
+# (v_fract_f32 + v_add_f32: 70.3 T/s; v_fmamk_f32 chains: 55.3 T/s), so the
+# published rate is the ceiling of this code as it is, and the transcendentals
+# at a quarter of it (19.0 and 19.4 T/s).
+PEAK_FP32_TFLOPS = 157.3
+ISSUE_T_PER_S = 256 * 2.4e9 * 128 / 1e12
+# Side figure: the issue-limited peak of the algorithm's own instruction mix.
 # A (pixel, spot) pair of the two-sincos pass issues 3 FMA + fract + sin +
 # cos + 2 FMA (back-propagation) and 3 FMA + fract + sin + cos + 4 FMA
-# (forward): 12 FMA + 2 fract + 4 transcendentals = 30 full-rate issue
-# slots, so the chip completes at most 78.65 / 30 = 2.62 T pairs/s, i.e.
-# 62.9 TFLOP/s at 24 algorithmic flops per pair.
-ISSUE_T_PER_S = 256 * 2.4e9 * 128 / 1e12
+# (forward): 12 FMA + 2 fract + 4 transcendentals at four slots each = 30
+# full-rate slots, so at most 78.65 / 30 = 2.62 T pairs/s, i.e. 62.9 TFLOP/s
+# at 24 algorithmic flops per pair.
 SLOTS_PER_PAIR = 12 + 2 + 4 * 4
-PEAK_ALU_TFLOPS = round(ISSUE_T_PER_S / SLOTS_PER_PAIR * (FLOPS_BACK + FLOPS_FWD), 1)
-PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector peak (packed FMA), for reference
-# The library is built without packed FP32 instructions, so its FMAs issue
-# at the non-packed rate, 64 lanes per clock per CU (39.3 T/s), against which
-# a transcendental costs two slots (19.7 T/s): 12 FMA + 2 fract + 4 x 2 =
-# 22 slots per pair, 1.79 T pairs/s, 42.9 TFLOP/s.  Reported beside the
-# packed-rate peak, which stays the `peak` of the roofline.
-ISSUE_NONPACKED_T_PER_S = 256 * 2.4e9 * 64 / 1e12
-SLOTS_PER_PAIR_NONPACKED = 12 + 2 + 4 * 2
-PEAK_ALU_NONPACKED_TFLOPS = round(ISSUE_NONPACKED_T_PER_S / SLOTS_PER_PAIR_NONPACKED
-                                  * (FLOPS_BACK + FLOPS_FWD), 1)
+PEAK_ISSUE_TFLOPS = round(ISSUE_T_PER_S / SLOTS_PER_PAIR * (FLOPS_BACK + FLOPS_FWD), 1)
 # Launch tags of the library's kernel timing (hg_timing_read).
 KERNELS = ("k_setup", "k_perm", "k_sep_tables", "k_sep_pass", "k_sep_final", "k_pass_subset",
            "k_pass_full", "k_pass_mixed", "k_backprop_phi", "k_mx_tables", "k_mx_subset",
@@ -104,43 +102,159 @@ def profiled_traffic(kernel: str):
     return None
 
 
-def cpu_baseline(grid, optics, spots, seed):
-    """Times the FP64 oracle (single thread) on a bounded sample of one
-    hologram: one full-grid back-propagation, one full-grid forward
-    projection and two compressed iterations; scales to a whole hologram
-    (2 full back-propagations + 1 full forward + 29 compressed iterations)."""
-    import numpy as np
-    import oracle
+# ------------------------------------------------- CPU baseline (oracle) ---
+# The FP64 oracle on the host cores, as it stands: one process, and a pool of
+# worker processes over a fixed partition of the pixel set into blocks of
+# CPU_BLOCK consecutive entries, whose results are combined in block order
+# (the same numbers whatever the number of workers).  Workers are forked
+# before the GPU is touched and use one BLAS thread each.
+CPU_BLOCK = 4096
+CPU_MAX_WORKERS = 16  # the host share of one GPU
+_CPU_CTX = None  # (grid, optics, spots) of the current job, inherited by the workers
+
+
+def _one_thread():
     try:
         from threadpoolctl import threadpool_limits
-        limiter = threadpool_limits(1)
+        return threadpool_limits(1)
     except Exception:  # pragma: no cover
-        limiter = None
-    w = np.ones(spots.n)
-    th = oracle.theta0(seed, spots.n)
-    t0 = time.perf_counter()
-    Phi = oracle.backward(grid, optics, spots, w, th)
-    t_fb = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    V = oracle.forward(grid, optics, spots, Phi)
-    t_ff = time.perf_counter() - t0
-    t_sub = []
-    for j in (1, 2):
+        return None
+
+
+def _cpu_back_block(args):
+    import oracle
+    w, th, p = args
+    g, o, s = _CPU_CTX
+    return oracle.backward(g, o, s, w, th, p)
+
+
+def _cpu_fwd_block(args):
+    import oracle
+    phi, p = args
+    g, o, s = _CPU_CTX
+    return oracle.forward(g, o, s, phi, p) * p.shape[0]  # the block's sum
+
+
+class _OracleRunner:
+    """eq. (1) and eq. (3) of the oracle on a pixel set, in one process
+    (pool None) or over the fixed blocks of a pool."""
+
+    def __init__(self, pool):
+        self.pool = pool
+
+    def backward(self, w, th, p):
+        import oracle
+        g, o, s = _CPU_CTX
+        if self.pool is None:
+            return oracle.backward(g, o, s, w, th, p)
+        parts = self.pool.map(_cpu_back_block, [(w, th, p[k:k + CPU_BLOCK])
+                                                for k in range(0, p.shape[0], CPU_BLOCK)])
+        return np.concatenate(parts)
+
+    def forward(self, phi, p):
+        import oracle
+        g, o, s = _CPU_CTX
+        if self.pool is None:
+            return oracle.forward(g, o, s, phi, p)
+        parts = self.pool.map(_cpu_fwd_block, [(phi[k:k + CPU_BLOCK], p[k:k + CPU_BLOCK])
+                                               for k in range(0, p.shape[0], CPU_BLOCK)])
+        V = parts[0].copy()
+        for v in parts[1:]:
+            V += v
+        return V / p.shape[0]
+
+    def wgs(self, grid, spots, iterations, seed):
+        """RS, then `iterations` full iterations: the oracle's WGS steps."""
+        import oracle
+        allp = np.arange(grid.M, dtype=np.int64)
+        w, th = np.ones(spots.n), oracle.theta0(seed, spots.n)
+        Phi = self.backward(w, th, allp)
+        for _ in range(iterations):
+            w, th = oracle.update(w, self.forward(Phi, allp))
+            Phi = self.backward(w, th, allp)
+        return Phi
+
+    def cswgs_sample(self, grid, spots, seed):
+        """The bounded sample of one headline hologram: one full-grid
+        back-propagation, one full-grid forward projection and two compressed
+        iterations; returns the seconds of each part."""
+        import oracle
+        allp = np.arange(grid.M, dtype=np.int64)
+        w, th = np.ones(spots.n), oracle.theta0(seed, spots.n)
         t0 = time.perf_counter()
-        p = oracle.sampler.subset(grid.M, seed, j, COMP)
-        Phi_p = oracle.backward(grid, optics, spots, w, th, p)
-        V = oracle.forward(grid, optics, spots, Phi_p, p)
-        w, th = oracle.update(w, V)
-        t_sub.append(time.perf_counter() - t0)
+        Phi = self.backward(w, th, allp)
+        t_fb = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        self.forward(Phi, allp)
+        t_ff = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for j in (1, 2):
+            p = oracle.sampler.subset(grid.M, seed, j, COMP)
+            V = self.forward(self.backward(w, th, p), p)
+            w, th = oracle.update(w, V)
+        t_sub = (time.perf_counter() - t0) / 2
+        return t_fb, t_ff, t_sub
+
+
+def cpu_baseline(grid, optics, spots, seed):
+    """Times the FP64 oracle on the host cores, single-process and across a
+    pool of workers: on a bounded sample of one headline hologram (scaled to
+    the whole hologram: the oracle computes the phase on all pixels for the
+    last two iterations and on the next window otherwise, so a hologram is
+    2 full back-propagations + 1 full forward projection + 29 compressed
+    iterations), and on the small WGS workload (256^2, N = 16, 20 iterations)
+    in full.  Runs before the GPU is touched (the workers are forked)."""
+    global _CPU_CTX
+    import multiprocessing as mp
+    from workload import Grid, spot_cloud
+    affinity = len(os.sched_getaffinity(0))
+    workers = max(1, min(affinity, CPU_MAX_WORKERS))
+    small = Grid(256, 256)
+    small_spots = spot_cloud(0, 16, small)
+    legs = {}
+    limiter = _one_thread()
+    ctx = mp.get_context("fork")
+
+    def timed(job, nproc, fn):
+        # the workers are forked after the job's context is set
+        global _CPU_CTX
+        _CPU_CTX = job
+        pool = None if nproc == 1 else ctx.Pool(nproc, initializer=_one_thread)
+        try:
+            return fn(_OracleRunner(pool))
+        finally:
+            if pool is not None:
+                pool.close()
+                pool.join()
+
+    def run_small(run):
+        t0 = time.perf_counter()
+        run.wgs(small, small_spots, 20, 0)
+        return time.perf_counter() - t0
+
+    for name, nproc in (("one_core", 1), ("all_cores", workers)):
+        t_fb, t_ff, t_sub = timed((grid, optics, spots), nproc,
+                                  lambda run: run.cswgs_sample(grid, spots, seed))
+        per_holo = 2 * t_fb + t_ff + (ITER - 1) * t_sub
+        t_small = timed((small, optics, small_spots), nproc, run_small)
+        legs[name] = {"holograms_per_s": 1.0 / per_holo, "s_per_hologram": round(per_holo, 3),
+                      "processes": nproc, "full_back_s": round(t_fb, 3),
+                      "full_forward_s": round(t_ff, 3), "compressed_iteration_s": round(t_sub, 4),
+                      "wgs_256x256_n16_i20_s": round(t_small, 3)}
+        print(f"[bench] oracle {name} ({nproc} processes): {per_holo:.2f} s per headline "
+              f"hologram, 256^2 WGS in {t_small:.2f} s", file=sys.stderr, flush=True)
+    _CPU_CTX = None
     if limiter is not None:
         limiter.unregister()
-    per_holo = 2 * t_fb + t_ff + (ITER - 1) * (sum(t_sub) / len(t_sub))
+    best = legs["all_cores"]
     return {
-        "value": 1.0 / per_holo, "unit": "holograms/s", "cores": 1, "kind": "oracle",
-        "sample": (f"1 full back-propagation ({t_fb:.1f} s), 1 full forward ({t_ff:.1f} s) and "
-                   f"2 compressed iterations ({sum(t_sub):.1f} s) of the seed-{seed} hologram, "
-                   f"scaled to 2 full back + 1 full forward + {ITER - 1} compressed iterations "
-                   f"= {per_holo:.1f} s per hologram"),
+        "value": best["holograms_per_s"], "unit": "holograms/s", "cores": workers,
+        "affinity_cores": affinity, "kind": "oracle",
+        "sample": (f"seed-{seed} headline hologram: 1 full back-propagation, 1 full forward and "
+                   f"2 compressed iterations, scaled to 2 full back + 1 full forward + "
+                   f"{ITER - 1} compressed iterations; {workers} worker processes over fixed "
+                   f"blocks of {CPU_BLOCK} pixels; plus WGS on 256^2, N=16, 20 iterations in full"),
+        "legs": legs,
     }
 
 
@@ -392,13 +506,16 @@ def main():
               "path has no multi-GPU form in this build", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
-    import torch
-    import paper_2003_05293_amd as hg
     from workload import Grid, OPTICS, spot_cloud
-
     grid = Grid(W, H)
     clouds = [spot_cloud(s, N, grid) for s in range(CLOUDS)]
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] timing the FP64 oracle on the host cores", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(grid, OPTICS, clouds[0], 0)
+
+    import torch
+    import paper_2003_05293_amd as hg
     spots_dev = [torch.tensor(np.stack([c.x_mm, c.y_mm, c.z_mm, c.amp]), dtype=torch.float64,
                               device="cuda") for c in clouds]
     phis = [torch.empty(W * H, dtype=torch.float32, device="cuda") for _ in range(CLOUDS)]
@@ -468,14 +585,15 @@ def main():
     flops = px * N * fl
     achieved = flops / (kern[dominant]["avg_us"] * 1e-6) / 1e12
     roofline = {
-        "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_ALU_TFLOPS,
-        "unit": "TFLOP/s", "frac": round(achieved / PEAK_ALU_TFLOPS, 4),
+        "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+        "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
         "traffic": profiled_traffic(dominant),
-        "peak_basis": f"{SLOTS_PER_PAIR} full-rate issue slots per (pixel, spot) pair "
-                      f"(12 FMA, 2 fract, 4 sin/cos at quarter rate) at {ISSUE_T_PER_S:.2f} T/s",
-        "frac_of_fp32_vector_peak": round(achieved / PEAK_FP32_TFLOPS, 4),
-        "peak_nonpacked_issue": PEAK_ALU_NONPACKED_TFLOPS,
-        "frac_of_nonpacked_issue_peak": round(achieved / PEAK_ALU_NONPACKED_TFLOPS, 4),
+        "peak_basis": "MI355X published FP32 vector peak",
+        "peak_issue_derived": PEAK_ISSUE_TFLOPS,
+        "frac_of_issue_derived": round(achieved / PEAK_ISSUE_TFLOPS, 4),
+        "issue_derived_basis": f"{SLOTS_PER_PAIR} full-rate issue slots per (pixel, spot) pair "
+                               f"(12 FMA, 2 fract, 4 sin/cos at quarter rate) at "
+                               f"{ISSUE_T_PER_S:.2f} T slots/s",
         "kernel": dominant, "avg_launch_us": round(kern[dominant]["avg_us"], 3),
         "flops_per_launch": flops,
         "kernels": {k: {"avg_us": round(v["avg_us"], 3),
@@ -529,11 +647,6 @@ def main():
     sweep = None
     if not args.no_budget_sweep:
         sweep = budget_sweep(hg)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        print("[bench] timing the FP64 oracle on a sample", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(grid, OPTICS, clouds[0], 0)
 
     line = {
         "metric": METRIC, "value": round(value, 3), "unit": "holograms/s", "n_gpus": 1,

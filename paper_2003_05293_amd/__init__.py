@@ -16,8 +16,10 @@ works (for example the classes of the workload package).
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from typing import Optional, Tuple
 
 import numpy as np
@@ -142,7 +144,30 @@ def load():
     lib.hg_version.restype = c.c_char_p
     lib.hg_version.argtypes = []
     _lib = lib
+    atexit.register(_release_at_exit)
     return lib
+
+
+# Library objects (batches with their graphs, engines, tables) still open;
+# closed at interpreter exit, before the HIP runtime's own teardown.
+_OPEN = weakref.WeakSet()
+
+
+def _release_at_exit():
+    """Closes the open batches, engines and tables, then frees the library's
+    per-stream scratch (hg_release synchronises the device first), so that
+    nothing of the library is left for the process's exit-time teardown."""
+    if _lib is None:
+        return
+    for obj in list(_OPEN):
+        try:
+            obj.close()
+        except Exception:
+            pass
+    try:
+        _lib.hg_release()
+    except Exception:
+        pass
 
 
 def version() -> str:
@@ -302,6 +327,7 @@ class Lut:
         _check(lib.hg_lut_create(arr.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),
                                  int(arr.shape[0]), int(bits), ctypes.byref(h)))
         self._h, self.levels, self.bits = h, int(arr.shape[0]), int(bits)
+        _OPEN.add(self)
 
     @property
     def handle(self):
@@ -553,6 +579,7 @@ class Batch:
         _check(lib.hg_batch_create(len(self.jobs), arr, ctypes.byref(t) if t else None,
                                    1 if use_graph else 0, ctypes.byref(h)))
         self._h = h
+        _OPEN.add(self)
 
     def run(self, stream=None):
         _check(load().hg_batch_run(self._h, _stream(stream)))
@@ -584,6 +611,7 @@ class Engine:
         h = ctypes.c_void_p()
         _check(lib.hg_engine_create(ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h
+        _OPEN.add(self)
         self._keep = {}
 
     def submit(self, grid, optics, spots, iterations: int, compression: float, seed: int,

@@ -6,8 +6,10 @@ workload/; nothing here touches the GPU library.
     python tests/golden/make_golden.py [name ...]
 
 Each case writes tests/golden/<name>.json holding e, u, the spot
-intensities of the final hologram, the spot field V^1 of the first
-iteration, and the final hologram Phi^I at a fixed sample of pixels.
+intensities of the final hologram, the trajectory of the iterations (the
+spot field V^j of every iteration j, and the weights w^j and phases theta^j
+its update produces; V1 repeats V^1), and the final hologram Phi^I at a
+fixed sample of pixels.
 """
 from __future__ import annotations
 
@@ -59,6 +61,9 @@ def run(name: str, W, H, n, I, c, seed, z_half_mm=0.05, pupil=False):
         cloud="workload.spot_cloud(seed, n, Grid(W, H), z_half_mm=z_half_mm)",
         e=e, u=u, intensities=inten.tolist(),
         V1=[[float(v.real), float(v.imag)] for v in tr.V[0]],
+        V=[[[float(v.real), float(v.imag)] for v in Vj] for Vj in tr.V],
+        w=[[float(x) for x in wj] for wj in tr.w],
+        theta=[[float(x) for x in tj] for tj in tr.theta],
         sample_pixels=pix.tolist(), sample_phi=Phi[pix].tolist(),
         oracle_seconds=time.time() - t0,
     )
