@@ -211,6 +211,40 @@ hg_status hg_cswgs_ex(const hg_grid *grid, const hg_optics *optics,
                       const hg_spots *spots, const hg_params *params,
                       float *phi_dev, void *stream);
 
+/* Size of the static device scratch of hg_cswgs_static, per GPU. */
+#define HG_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* hg_cswgs_ex for callers that cannot allocate memory: tight serving loops
+ * and harnesses that forbid hipMalloc after start-up.  (It stages launch
+ * descriptors through host memory and waits for the previous upload, so it
+ * is not meant to be recorded into a HIP graph; hg_batch_create is.)
+ * Computes the same hologram as hg_cswgs_ex with the same arguments (the
+ * same kernels, bit-identical results) without allocating: no hipMalloc,
+ * hipHostMalloc or hipFree and no torch allocation.  Its device scratch
+ * (spot state, random order, factor tables, sums and counters, launch
+ * descriptors) is a file-scope static array of HG_STATIC_SCRATCH_BYTES,
+ * of which each GPU the library runs on holds its own copy until the
+ * process ends; the descriptors are staged through a static host area of
+ * 1 MiB.  The first call on a device sets that device up (looks up its
+ * copy of the array and creates one event).  Host-side planning still uses
+ * ordinary C++ containers.
+ * Arguments: as hg_cswgs_ex, with these restrictions, each rejected with
+ * HG_EINVAL before anything runs: params->flags must have
+ * HG_SPOTS_ON_DEVICE (spot arrays in HBM) and params->trace_V must be NULL.
+ * A hologram whose scratch or descriptors do not fit is rejected with
+ * HG_ENOMEM and a message giving the bytes it needs.  The 64 MiB hold, for
+ * example, an FP32 CS-WGS hologram of 1152 x 1152 pixels with N <= 1200 or
+ * of 1920 x 1152 with N <= 900 (mixed precision: N <= 1600 and 1100), and
+ * the descriptors of up to 4000 iterations.
+ * Every call on one GPU uses that GPU's one array and leaves its contents
+ * behind; the kernels clear what must start at zero.  Calls that overlap on
+ * one GPU (two streams, or two host threads) race on the array and give
+ * undefined results: serialise them.  Device-side numeric flags are not
+ * reported by this call.  Asynchronous. */
+hg_status hg_cswgs_static(const hg_grid *grid, const hg_optics *optics,
+                          const hg_spots *spots, const hg_params *params,
+                          float *phi_dev, void *stream);
+
 /* Efficiency and uniformity of a hologram (section 2, last paragraph, and
  * eq. 7), in FP64: V*_n = mean over the pupil Omega of
  * A(p) e^{i(Phi - phi_n)}, I_n = |V*_n|^2, e = sum_n I_n / mean_Omega(A^2),

@@ -27,7 +27,7 @@ import numpy as np
 __all__ = [
     "HGError", "lib_path", "load", "version", "last_error", "release",
     "rs", "wgs", "cswgs", "metrics", "theta0", "subset", "forward", "backward", "step",
-    "PREC_FP32", "PREC_MIXED", "cswgs_device", "timing_enable", "timing_reset", "timing_read",
+    "PREC_FP32", "PREC_MIXED", "cswgs_device", "cswgs_static", "timing_enable", "timing_reset", "timing_read",
     "DeviceJob", "cswgs_batch", "Batch", "Engine", "Lut", "phase_to_gray",
 ]
 
@@ -112,6 +112,7 @@ def load():
         "hg_wgs": [G, O, S, i32, u64, vp, vp],
         "hg_cswgs": [G, O, S, i32, dbl, u64, vp, vp],
         "hg_cswgs_ex": [G, O, S, c.POINTER(_Params), vp, vp],
+        "hg_cswgs_static": [G, O, S, c.POINTER(_Params), vp, vp],
         "hg_metrics": [G, O, S, vp, _DP, _DP, _DP, vp],
         "hg_theta0": [u64, i32, _DP],
         "hg_subset": [G, O, u64, i32, dbl, vp, c.POINTER(i32), vp],
@@ -488,6 +489,33 @@ def cswgs_device(grid, optics, spots_dev, iterations: int, compression: float, s
                      lp, gp)
     _check(lib.hg_cswgs_ex(_grid(grid), _optics(optics), sp, ctypes.byref(params),
                            _dev_f32(phi, grid.W * grid.H, "phi"), _stream(stream)))
+    return phi
+
+
+def cswgs_static(grid, optics, spots_dev, iterations: int, compression: float, seed: int, phi,
+                 stream=None, precision: str = "fp32", tune=None, lut=None, gray=None):
+    """cswgs_device through hg_cswgs_static: the library allocates nothing
+    and works in its static per-GPU scratch (calls that overlap on one GPU
+    race).  phi (float32 GPU tensor of W*H) and, with lut, gray are the
+    caller's; spots_dev as in cswgs_device."""
+    import torch
+    lib = load()
+    if (not isinstance(spots_dev, torch.Tensor) or spots_dev.dtype != torch.float64
+            or not spots_dev.is_cuda or spots_dev.dim() != 2 or spots_dev.shape[0] != 4
+            or not spots_dev.is_contiguous()):
+        raise TypeError("spots_dev must be a contiguous float64 GPU tensor of shape (4, N)")
+    if phi is None:
+        raise TypeError("phi must be given: cswgs_static allocates nothing")
+    n = int(spots_dev.shape[1])
+    base = spots_dev.data_ptr()
+    ptrs = [ctypes.cast(ctypes.c_void_p(base + 8 * n * k), _DP) for k in range(4)]
+    sp = _Spots(n, *ptrs)
+    lp, gp = _lut_args(lut, gray, grid)
+    params = _Params(int(iterations), float(compression), int(seed),
+                     _flags(precision) | SPOTS_ON_DEVICE, None, _tune(tune) or _Tune(0, 0, 0, 0),
+                     lp, gp)
+    _check(lib.hg_cswgs_static(_grid(grid), _optics(optics), sp, ctypes.byref(params),
+                               _dev_f32(phi, grid.W * grid.H, "phi"), _stream(stream)))
     return phi
 
 

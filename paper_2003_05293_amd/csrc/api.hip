@@ -15,6 +15,13 @@
 #include "kernels.hpp"
 #include "runtime.hpp"
 
+// Device memory of hg_cswgs_static, which works in this array instead of
+// allocated memory (zero at load; each GPU holds its own copy).  In host
+// code `scratch` names a host-side stand-in, not the device array: the
+// device address of each GPU's copy comes from hipGetSymbolAddress, taken
+// once per device with that device current, and only that address is used.
+static __device__ __align__(256) char scratch[HG_STATIC_SCRATCH_BYTES];
+
 namespace {
 
 using hg::set_error;
@@ -134,6 +141,65 @@ hg_status run_one(const hg_grid* g, const hg_optics* o, const hg_spots* s, int32
     HG_HIP(hipStreamSynchronize(ws->stream));
     HG_TRY(ws->take_status());
   }
+  return HG_OK;
+}
+
+hg_status check_params(const hg_params* params) {
+  if (!params) return set_error(HG_EINVAL, "params must be non-NULL");
+  HG_TRY(check_compression(params->compression));
+  HG_TRY(validate_flags(params->flags, HG_SPOTS_ON_DEVICE | HG_FULL_DIRECT));
+  if (params->tune.full_block_cap < 0 || params->tune.subset_block_cap < 0 ||
+      params->tune.pass_form < 0 || params->tune.pass_form > 1 ||
+      params->tune.chain_passes < 0 || params->tune.chain_passes > 1)
+    return set_error(HG_EINVAL, "tune caps must be >= 0, pass_form and chain_passes 0 or 1");
+  return HG_OK;
+}
+
+// ------------------------------------------------ static scratch (no alloc) --
+// Layout of one copy of `scratch`: [0, 256) the status word, then the job
+// scratch, and the descriptor tables in the last kStaticTableBytes.
+constexpr size_t kStaticTableBytes = size_t(1) << 20;
+constexpr size_t kStaticArenaOffset = 256;
+constexpr int kStaticMaxDevices = 64;
+static_assert(HG_STATIC_SCRATCH_BYTES > kStaticArenaOffset + kStaticTableBytes, "scratch layout");
+
+struct StaticScratch {
+  std::mutex mu;
+  bool ready = false;
+  char* dev = nullptr;          // this device's copy of `scratch`
+  hipEvent_t copied = nullptr;  // the last descriptor upload has read `host`
+  hg::Batch batch;
+  char host[kStaticTableBytes];  // descriptor staging
+};
+
+std::mutex g_static_mu;
+StaticScratch* g_static[kStaticMaxDevices] = {};
+
+// Set-up of the current device (first call on it): the address of its copy
+// of the array and the upload event.  The status word is zero from load;
+// no call of this path reads it.
+hg_status static_scratch(StaticScratch** out) {
+  int dev = 0;
+  HG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kStaticMaxDevices)
+    return set_error(HG_EINVAL, "hg_cswgs_static supports devices 0.." +
+                                    std::to_string(kStaticMaxDevices - 1));
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (!g_static[dev]) g_static[dev] = new StaticScratch();
+  StaticScratch* st = g_static[dev];
+  if (!st->ready) {
+    void* p = nullptr;
+    HG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return set_error(HG_EDEVICE, "hipGetSymbolAddress gave no address for the scratch");
+    HG_HIP(hipEventCreateWithFlags(&st->copied, hipEventDisableTiming));
+    st->dev = static_cast<char*>(p);
+    st->batch.adopt(st->dev + kStaticArenaOffset,
+                    HG_STATIC_SCRATCH_BYTES - kStaticArenaOffset - kStaticTableBytes,
+                    st->dev + HG_STATIC_SCRATCH_BYTES - kStaticTableBytes, kStaticTableBytes,
+                    st->host, kStaticTableBytes, st->copied);
+    st->ready = true;
+  }
+  *out = st;
   return HG_OK;
 }
 
@@ -282,16 +348,31 @@ hg_status hg_cswgs(const hg_grid* grid, const hg_optics* optics, const hg_spots*
 
 hg_status hg_cswgs_ex(const hg_grid* grid, const hg_optics* optics, const hg_spots* spots,
                       const hg_params* params, float* phi_dev, void* stream) {
-  if (!params) return set_error(HG_EINVAL, "params must be non-NULL");
-  HG_TRY(check_compression(params->compression));
-  HG_TRY(validate_flags(params->flags, HG_SPOTS_ON_DEVICE | HG_FULL_DIRECT));
-  if (params->tune.full_block_cap < 0 || params->tune.subset_block_cap < 0 ||
-      params->tune.pass_form < 0 || params->tune.pass_form > 1 ||
-      params->tune.chain_passes < 0 || params->tune.chain_passes > 1)
-    return set_error(HG_EINVAL, "tune caps must be >= 0, pass_form and chain_passes 0 or 1");
+  HG_TRY(check_params(params));
   return run_one(grid, optics, spots, params->iterations, params->compression, params->seed,
                  params->flags, phi_dev, params->trace_V, stream, tune_params(&params->tune),
                  params->lut, params->gray_dev);
+}
+
+hg_status hg_cswgs_static(const hg_grid* grid, const hg_optics* optics, const hg_spots* spots,
+                          const hg_params* params, float* phi_dev, void* stream) {
+  HG_TRY(check_params(params));
+  if (!(params->flags & HG_SPOTS_ON_DEVICE))
+    return set_error(HG_EINVAL, "hg_cswgs_static takes device-resident spots: params->flags "
+                                "must have HG_SPOTS_ON_DEVICE");
+  if (params->trace_V)
+    return set_error(HG_EINVAL, "hg_cswgs_static takes no trace: params->trace_V must be NULL");
+  hg::JobSpec spec;
+  HG_TRY(hg::make_spec(grid, optics, spots, params->iterations, params->compression,
+                       params->seed, params->flags, phi_dev, nullptr, &spec));
+  HG_TRY(hg::apply_lut(params->lut, params->gray_dev, &spec));
+  if (!phi_dev) return set_error(HG_EINVAL, "phi_dev must be non-NULL");
+  StaticScratch* st = nullptr;
+  HG_TRY(static_scratch(&st));
+  std::lock_guard<std::mutex> lk(st->mu);
+  HG_TRY(st->batch.build(&spec, 1, tune_params(&params->tune), reinterpret_cast<int32_t*>(st->dev),
+                         /*allow_chain=*/true));
+  return st->batch.enqueue(static_cast<hipStream_t>(stream));
 }
 
 hg_status hg_metrics(const hg_grid* grid, const hg_optics* optics, const hg_spots* spots,

@@ -31,6 +31,10 @@ hg_status Staging::acquire(size_t bytes) {
     HG_HIP(hipEventSynchronize(done));
     pending = false;
   }
+  if (bytes > cap && adopted)
+    return set_error(HG_ENOMEM, "the request needs " + std::to_string(bytes) +
+                                    " bytes of descriptor staging, more than the " +
+                                    std::to_string(cap) + " of the static area");
   if (bytes > cap) {
     if (p) HG_HIP(hipHostFree(p));
     p = nullptr;
@@ -48,14 +52,23 @@ hg_status Staging::mark_copied(hipStream_t s) {
   return HG_OK;
 }
 
+void Staging::adopt(char* q, size_t n, hipEvent_t ev) {
+  p = q;
+  cap = n;
+  done = ev;
+  pending = false;
+  adopted = true;
+}
+
 void Staging::release() {
   if (pending && done) (void)hipEventSynchronize(done);
-  if (p) (void)hipHostFree(p);
-  if (done) (void)hipEventDestroy(done);
+  if (p && !adopted) (void)hipHostFree(p);
+  if (done && !adopted) (void)hipEventDestroy(done);
   p = nullptr;
   cap = 0;
   done = nullptr;
   pending = false;
+  adopted = false;
 }
 
 // -------------------------------------------------------------- validation --
@@ -795,8 +808,9 @@ hg_status Batch::enqueue_prologue(hipStream_t s, bool capture) {
     HG_HIP(hipMemcpyAsync(arena_.p + raw_base_, staging_.p + table_bytes_, host_spot_bytes_,
                           hipMemcpyHostToDevice, s));
   if (!capture) HG_TRY(staging_.mark_copied(s));
+  const bool quiet = capture || untimed_;
   auto run = [&](const char* name, auto&& launch) {
-    if (capture) launch();
+    if (quiet) launch();
     else timed(s, name, launch);
   };
   run("k_setup", [&] { launch_setup_batch(jobs_dev_, count(), max_h_, s); });
@@ -818,11 +832,14 @@ hg_status Batch::enqueue_prologue(hipStream_t s, bool capture) {
 hg_status Batch::enqueue(hipStream_t s, bool capture) {
   HG_TRY(enqueue_prologue(s, capture));
   size_t r0 = 0;
+  const bool quiet = capture || untimed_;
   if (chain_rounds_ > 0 && !capture) {
     hipError_t ce = hipSuccess;
-    timed(s, "k_pass_chain", [&] {
+    auto chain = [&] {
       ce = launch_pass_chain(jobs_dev_, chain_dev_, chain_rounds_, chain_blocks_, chain_units_, s);
-    });
+    };
+    if (quiet) chain();
+    else timed(s, "k_pass_chain", chain);
     if (ce == hipSuccess) r0 = (size_t)chain_rounds_;
     else (void)hipGetLastError();  // not launched: one launch per pass instead
   }
@@ -832,8 +849,8 @@ hg_status Batch::enqueue(hipStream_t s, bool capture) {
   size_t r = r0;
   while (r < rounds_.size()) {
     const char* kind = rounds_[r].pass_only_name();
-    if (capture || !timing_enabled() || !kind) {
-      rounds_[r].launch(jobs_dev_, s, capture);
+    if (quiet || !timing_enabled() || !kind) {
+      rounds_[r].launch(jobs_dev_, s, quiet);
       ++r;
       continue;
     }
@@ -846,7 +863,7 @@ hg_status Batch::enqueue(hipStream_t s, bool capture) {
     timing_stop(s, kind, a, (int)(r1 - r));
     r = r1;
   }
-  final_.launch(jobs_dev_, s, capture);
+  final_.launch(jobs_dev_, s, quiet);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess)
     return set_error(HG_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
@@ -883,7 +900,17 @@ hg_status Batch::custom_device(size_t size, char** dev) {
   return HG_OK;
 }
 
+void Batch::adopt(char* arena, size_t arena_bytes, char* table, size_t table_bytes, char* host,
+                  size_t host_bytes, hipEvent_t copied) {
+  release();
+  arena_.adopt(arena, arena_bytes);
+  table_.adopt(table, table_bytes);
+  staging_.adopt(host, host_bytes, copied);
+  untimed_ = true;
+}
+
 void Batch::release() {
+  untimed_ = false;
   staging_.release();
   custom_staging_.release();
   arena_.release();

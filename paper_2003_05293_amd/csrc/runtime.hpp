@@ -40,33 +40,51 @@ const char* last_error();
 
 // Device buffer that grows on demand and is never shrunk.  Growing waits for
 // the device first: queued kernels may still be reading the old buffer.
+// An adopted buffer is memory the library does not own (a fixed region of
+// static device memory): it never grows, and a request beyond it fails with
+// HG_ENOMEM instead of allocating.
 template <typename T>
 struct DevBuf {
   T* p = nullptr;
   size_t cap = 0;
+  bool adopted = false;
   hg_status reserve(size_t n) {
     if (n <= cap) return HG_OK;
+    if (adopted)
+      return set_error(HG_ENOMEM, "the request needs " + std::to_string(n * sizeof(T)) +
+                                      " bytes of static scratch in one region, which holds " +
+                                      std::to_string(cap * sizeof(T)));
     if (p) HG_HIP(hipDeviceSynchronize());
     release();
     HG_HIP(hipMalloc((void**)&p, n * sizeof(T)));
     cap = n;
     return HG_OK;
   }
+  void adopt(T* q, size_t n) {
+    p = q;
+    cap = n;
+    adopted = true;
+  }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && !adopted) (void)hipFree(p);
     p = nullptr;
     cap = 0;
+    adopted = false;
   }
 };
 
-// Pinned host staging area whose refill waits for the copy that last read it.
+// Host staging area whose refill waits for the copy that last read it:
+// pinned memory that grows on demand, or an adopted fixed host region with
+// its event (which then never grows).
 struct Staging {
   char* p = nullptr;
   size_t cap = 0;
   hipEvent_t done = nullptr;
   bool pending = false;
+  bool adopted = false;
   hg_status acquire(size_t bytes);             // waits for the previous copy, grows
   hg_status mark_copied(hipStream_t s);        // records the event after the copies
+  void adopt(char* q, size_t n, hipEvent_t ev);
   void release();
 };
 
@@ -241,6 +259,14 @@ class Batch {
   hg_status upload_custom(const void* bytes, size_t size, hipStream_t s, void** dev);
   // Reserves the custom area and returns its device address.
   hg_status custom_device(size_t size, char** dev);
+  // Makes the batch work in fixed memory that it does not own: job scratch
+  // in [arena, arena + arena_bytes), descriptor tables in [table, table +
+  // table_bytes) on the device, their host staging in [host, host +
+  // host_bytes) guarded by `copied`.  Later builds allocate nothing (a
+  // schedule that does not fit fails with HG_ENOMEM) and launches are
+  // never timed.  Not for batches that use upload_custom.
+  void adopt(char* arena, size_t arena_bytes, char* table, size_t table_bytes, char* host,
+             size_t host_bytes, hipEvent_t copied);
   void release();
 
  private:
@@ -274,6 +300,7 @@ class Batch {
   size_t table_bytes_ = 0;
   Staging staging_;
   Staging custom_staging_;
+  bool untimed_ = false;  // adopted memory: no timing events
 };
 
 

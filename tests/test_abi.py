@@ -102,6 +102,32 @@ def test_iteration_and_compression_limits(lib):
     assert lib.hg_cswgs_ex(G, O, S, None, p, None) == 1
 
 
+def test_static_entry_point_validation(lib):
+    """hg_cswgs_static takes device-resident spots and no trace; both, and
+    every check of hg_cswgs_ex, are rejected before any HIP call."""
+    g, o, s, keep = _args()
+    G, O, S = ctypes.byref(g), ctypes.byref(o), ctypes.byref(s)
+    p = ctypes.c_void_p(1)
+    params = hg._Params(10, 0.5, 1, hg.PREC_FP32, None)
+    assert lib.hg_cswgs_static(G, O, S, ctypes.byref(params), p, None) == 1
+    assert "HG_SPOTS_ON_DEVICE" in hg.last_error()
+    trace = np.zeros(10 * 3 * 2)
+    params = hg._Params(10, 0.5, 1, hg.PREC_FP32 | hg.SPOTS_ON_DEVICE,
+                        trace.ctypes.data_as(hg._DP))
+    assert lib.hg_cswgs_static(G, O, S, ctypes.byref(params), p, None) == 1
+    assert "trace" in hg.last_error()
+    params = hg._Params(10, 1.5, 1, hg.PREC_FP32 | hg.SPOTS_ON_DEVICE, None)
+    assert lib.hg_cswgs_static(G, O, S, ctypes.byref(params), p, None) == 1
+    assert "compression" in hg.last_error()
+    params = hg._Params(10, 0.5, 1, 7 | hg.SPOTS_ON_DEVICE, None)
+    assert lib.hg_cswgs_static(G, O, S, ctypes.byref(params), p, None) == 1
+    assert "flags" in hg.last_error()
+    assert lib.hg_cswgs_static(G, O, S, None, p, None) == 1
+    params = hg._Params(10, 0.5, 1, hg.PREC_FP32 | hg.SPOTS_ON_DEVICE, None)
+    assert lib.hg_cswgs_static(G, O, S, ctypes.byref(params), None, None) == 1
+    assert "phi" in hg.last_error()
+
+
 def test_test_hook_validation(lib):
     g, o, s, keep = _args()
     G, O, S = ctypes.byref(g), ctypes.byref(o), ctypes.byref(s)
