@@ -348,13 +348,16 @@ __global__ void k_gather(PixelSet ps, int32_t* __restrict__ out) {
 //  phase 2  forward projection (eq. 3): lanes map to spots (groups of Lg
 //           lanes, R = 64/Lg replicas each taking every R-th pixel), waves
 //           to (spot chunk, pixel slice) units;
-//  partial  the tile's per-spot sums go to partial[tile] (FP32);
-//  tail     the block that completes a group of tiles adds the group's
-//           partials (tile order, FP64); the block that completes the last
-//           group adds the group sums (group order), divides by |Omega|
-//           and, when asked, applies the weight update of eqs. (4)-(6).
-// A tile's sums do not depend on which block computed it, and every sum is
-// taken in an order fixed by the pass alone, so results depend neither on
+//  sums     the tile's per-spot sums (FP32, in a fixed order) are rounded
+//           once to 64-bit fixed point and added into the row of the
+//           tile's group with integer atomics;
+//  tail     the block that completes a group moves the group row into the
+//           pass total; the block that completes the last group scales the
+//           total by 2^-shift / |Omega| and, when asked, applies the weight
+//           update of eqs. (4)-(6).  A deferring pass stops after the group
+//           moves and the next pass applies the update at its start.
+// A tile's sums do not depend on which block computed it, and integer
+// addition does not depend on order, so results depend neither on
 // scheduling nor on the other jobs of the batch.
 
 __device__ __forceinline__ void forward_term(float cx, float cy, float cz, const float4& a,
@@ -391,7 +394,8 @@ __host__ __device__ inline LaneMap lane_map(int N) {
 // thread in the block's first sub-tile may come prefetched (has_pre, pre_p),
 // and the block that completes the pass publishes the generation word after
 // the update.  PEND: the records come from LDS too (a.recs: the state after
-// the previous pass's deferred update).  With a.defer the pass ends after
+// the previous pass's deferred update), and the first pixel index may come
+// prefetched as in CHAIN.  With a.defer the pass ends after
 // its groups have added into its total row.
 template <int MAXU, bool CHAIN = false, bool PEND = false>
 __device__ void pass_block(const PassCtx& a, unsigned* grab, bool has_pre = false,
@@ -403,7 +407,6 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab, bool has_pre = fals
   __shared__ int done[kDoneList];
   __shared__ int owned[kMaxGroups];
   __shared__ int ndone, nowned, next_tile, flag;
-  __shared__ double wsum[kWaves];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int N = a.N;
@@ -469,7 +472,7 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab, bool has_pre = fals
         }
         __syncthreads();
       } else {
-        const int32_t p = (CHAIN && has_pre && tile == a.lb && st == 0)
+        const int32_t p = ((CHAIN || PEND) && has_pre && tile == a.lb && st == 0)
                               ? pre_p
                               : (valid ? pixel_of(a.ps, q) : 0);
         // the next tile is asked for now; the answer is first needed after phase 1
@@ -601,7 +604,7 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab, bool has_pre = fals
   for (int i = 0; i < nowned; ++i)
     if (tail_group(a, owned[i], &flag)) last = true;
   if (last) {
-    tail_final(a, wsum);
+    tail_final(a);
     if (CHAIN) publish_gen(a);
   }
 }
@@ -652,7 +655,6 @@ __device__ void pass_block_e(const PassCtx& a, unsigned* grab) {
   __shared__ int done[kDoneList];
   __shared__ int owned[kMaxGroups];
   __shared__ int ndone, nowned, next_tile, flag;
-  __shared__ double wsum[kWaves];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int N = a.N;
@@ -748,7 +750,7 @@ __device__ void pass_block_e(const PassCtx& a, unsigned* grab) {
   bool last = false;  // (at most once, with this block's last group)
   for (int i = 0; i < nowned; ++i)
     if (tail_group(a, owned[i], &flag)) last = true;
-  if (last) tail_final(a, wsum);
+  if (last) tail_final(a);
 }
 
 static_assert(kPendMaxSpots <= kBlock, "a pending update takes one spot per thread");
@@ -803,11 +805,20 @@ __global__ __launch_bounds__(kBlock, MAXU > 4 ? 2 : (MAXE > 16 ? 6 : 8)) void k_
   if (d.pending) {
     if constexpr (MAXU == 1) {
       __shared__ SpotRec recs[kPendMaxSpots];
-      __shared__ double wsum[kWaves];
-      apply_pending(jb, d, a.lb == 0, recs, wsum);
+      __shared__ float2 sv[kPendMaxSpots];
+      // the pixel index of this thread in the block's first sub-tile is
+      // requested before the update, so that the two reads overlap
+      bool has_pre = false;
+      int32_t pre_p = 0;
+      if (!d.from_phi && a.lb < a.plan.tiles) {
+        const int32_t q = a.lb * a.plan.sub * kTile + (int)(threadIdx.x & 63);
+        pre_p = q < a.ps.count ? pixel_of(a.ps, q) : 0;
+        has_pre = true;
+      }
+      apply_pending(jb, d, a.lb == 0, recs, sv);
       a.recs = recs;
       if (!d.defer) a.pend_row = d.prev_row;
-      pass_block<MAXU, false, true>(a, jb.grab + d.grab_slot);
+      pass_block<MAXU, false, true>(a, jb.grab + d.grab_slot, has_pre, pre_p);
       return;
     } else {
       if (a.lb == 0 && threadIdx.x == 0) jb.status[0] = 5;  // HG_EDEVICE

@@ -202,7 +202,7 @@ struct PassDesc {
   // added into total row tot_row: the pass counter, the read of the total
   // and the update leave its critical path.  The next pass is pending:
   // every block applies that update to the state st_in at its start (the
-  // same FP64 operations in the same order, so the same bits) and keeps the
+  // same FP32 operations in the same order, so the same bits) and keeps the
   // result in LDS; its block 0 stores it to st_out when the pass defers in
   // turn, and clears total row clear_row.  A pending pass that does not
   // defer updates from its LDS state as usual and clears prev_row at the end.

@@ -218,7 +218,6 @@ __global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ 
   __shared__ float2 us[kWaves][16][kSepTileW + 1];    // u of each wave's rows
   __shared__ float2 red[kWaves][64];
   __shared__ int flag;
-  __shared__ double wsum[kWaves];
   const int di = find_desc(descs, ndesc, blockIdx.x);
   const SepDesc& d = descs[di];
   const JobDev& jb = jobs[d.job];
@@ -354,7 +353,7 @@ __global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ 
   const int size = min(d.plan.group_size, d.plan.tiles - g * d.plan.group_size);
   if (arrive_last(&jb.counters[g * kCounterStride], (unsigned)size, &flag) &&
       tail_group(a, g, &flag))
-    tail_final(a, wsum);
+    tail_final(a);
 }
 
 }  // namespace

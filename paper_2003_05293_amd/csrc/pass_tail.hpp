@@ -109,47 +109,40 @@ __device__ void tail_group_deferred(const PassCtx& a, int g) {
     __hip_atomic_store(a.counters + g * kCounterStride, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// |V_n| and the new record of eqs. (4)-(6): the one place that does this
+// The weight update of eqs. (4)-(6) in FP32: the one place that does this
 // arithmetic, so that a deferred update gives the bits of an immediate one.
-__device__ __forceinline__ double field_mag(double2 t) { return sqrt(t.x * t.x + t.y * t.y); }
-// false (record unchanged) where the weight would come out zero or not finite
-__device__ __forceinline__ bool update_rec(SpotRec& r, double2 v, double mag, double mean,
-                                           double* w_out) {
-  const double w = (double)r.w * (mean / mag);
-  if (!(mag > 0.0) || !isfinite(w)) return false;
-  r.w = (float)w;
-  r.A = (float)(w * (double)r.a0);
-  // theta is kept in FP32 turns: the FP32 arctangent of the FP64 sum
-  // (rounded to FP32) is within a few FP32 ulps of the rounded FP64 one
-  r.th = atan2f((float)v.y, (float)v.x) * 0.15915494309189535f;
-  *w_out = w;
-  return true;
+// A spot field enters as the FP64 mean of the exact sums rounded to FP32.
+__device__ __forceinline__ float2 field32(double2 t) { return make_float2((float)t.x, (float)t.y); }
+__device__ __forceinline__ float mag32(float2 v) { return sqrtf(fmaf(v.x, v.x, v.y * v.y)); }
+// mean_n |V_n| (eq. 4), uniform across the calling wave and the same in
+// every wave: lane l adds |V_n| for n = l, l + 64, ... in that order,
+// starting from 0 (s is that lane sum), then the lane sums are added in a
+// fixed tree.  All 64 lanes must call it.
+__device__ __forceinline__ float wave_mean_of(float s, int N) {
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off);
+  return __shfl(s, 0) / (float)N;
 }
-// Sum of a per-thread value over the block in a fixed order: within each
-// wave, then the waves in order.
-__device__ __forceinline__ double block_sum_fixed(double x, double* wsum) {
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
-  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = x;
-  __syncthreads();
-  double total = wsum[0];
-  for (int w = 1; w < kWaves; ++w) total += wsum[w];
-  return total;
+// false (record unchanged) where the weight would come out zero or not finite
+__device__ __forceinline__ bool update_rec(SpotRec& r, float2 v, float mag, float mean) {
+  const float w = r.w * (mean / mag);
+  if (!(mag > 0.f) || !isfinite(w)) return false;
+  r.w = w;
+  r.A = w * r.a0;
+  r.th = atan2f(v.y, v.x) * 0.15915494309189535f;
+  return true;
 }
 
 // Every group is complete: V_n = total / 2^shift / |Omega| (the total row is
 // cleared for the next pass, and so are the counters); with a.update,
 // eqs. (4)-(6): w_n <- w_n mean/|V_n|, theta_n <- arg V_n, A_n = a_n^0 w_n.
-__device__ void tail_final(const PassCtx& a, double* wsum) {
+__device__ void tail_final(const PassCtx& a) {
   const int N = a.N;
   const double inv = ldexp(1.0, -a.plan.shift) * a.inv_count;
-  double magsum = 0.0;
   unsigned long long* tot = a.acc + (int64_t)a.tot_row * N * kAccSpotWords;
   for (int n = threadIdx.x; n < N; n += kBlock) {
     const long long re = (long long)take_dev(tot + (int64_t)n * kAccSpotWords);
     const long long im = (long long)take_dev(tot + (int64_t)n * kAccSpotWords + 1);
-    const double2 t = make_double2((double)re * inv, (double)im * inv);
-    a.V[n] = t;
-    magsum += field_mag(t);
+    a.V[n] = make_double2((double)re * inv, (double)im * inv);
   }
   // the previous pass's total, which every block of this pass has read
   // before counting its tiles, is cleared
@@ -168,14 +161,15 @@ __device__ void tail_final(const PassCtx& a, double* wsum) {
       a.counters[k * kCounterStride] = 0u;
   }
   if (!a.update) return;
-  // sum of |V_n| in a fixed order: per thread, within each wave, then the waves
-  const double mean = block_sum_fixed(magsum, wsum) / (double)N;
+  __syncthreads();  // every V_n of the block is stored
+  float msum = 0.f;
+  for (int n = threadIdx.x & 63; n < N; n += 64) msum += mag32(field32(a.V[n]));
+  const float mean = wave_mean_of(msum, N);
   for (int n = threadIdx.x; n < N; n += kBlock) {
-    const double2 v = a.V[n];  // written above by this same thread
-    const double mag = field_mag(v);
+    const float2 v = field32(a.V[n]);
+    const float mag = mag32(v);
     SpotRec r = a.recs ? a.recs[n] : a.sp[n];
-    double w;
-    if (!update_rec(r, v, mag, mean, &w)) {
+    if (!update_rec(r, v, mag, mean)) {
       a.status[0] = 4;  // HG_ENUMERIC
       if (a.recs && !a.chain) a.sp[n] = r;  // the state this pass used
       continue;
@@ -183,19 +177,20 @@ __device__ void tail_final(const PassCtx& a, double* wsum) {
     if (a.chain) store_rec_dev(a.sp + n, r);
     else a.sp[n] = r;
     // C_n = A_n e^{i theta_n} = A_n V_n / |V_n|
-    const double Am = w * (double)r.a0 / mag;
-    a.coef[n] = make_float2((float)(Am * v.x), (float)(Am * v.y));
+    const float Am = r.A / mag;
+    a.coef[n] = make_float2(Am * v.x, Am * v.y);
   }
 }
 
 // Pending pass: every block applies the previous pass's update to the state
 // before it (d.st_in) and keeps the result in recs (LDS), with the
-// arithmetic and summation order of tail_final.  Block 0 (lead) also
-// clears the total row two passes back, stores the state for the next pass
-// when this pass defers in turn, the previous V when traced, and the status.
-// N <= kPendMaxSpots <= kBlock: one spot per thread.
+// arithmetic and the mean of tail_final (one spot per thread; each wave
+// takes the mean itself from the FP32 fields in sv, LDS).  Block 0 (lead)
+// also clears the total row two passes back, stores the state for the next
+// pass when this pass defers in turn, the previous V when traced, and the
+// status.  N <= kPendMaxSpots <= kBlock.
 __device__ void apply_pending(const JobDev& jb, const PassDesc& d, bool lead, SpotRec* recs,
-                              double* wsum) {
+                              float2* sv) {
   const int N = jb.N;
   const int n = threadIdx.x;
   if (lead && d.clear_row >= 0) {
@@ -205,7 +200,6 @@ __device__ void apply_pending(const JobDev& jb, const PassDesc& d, bool lead, Sp
       __hip_atomic_store(q + k, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   double2 t = make_double2(0.0, 0.0);
-  double magsum = 0.0;
   // the record as eight words (a struct copy through a generic pointer
   // would go through the stack)
   constexpr int kWords = (int)(sizeof(SpotRec) / sizeof(float));
@@ -218,12 +212,15 @@ __device__ void apply_pending(const JobDev& jb, const PassDesc& d, bool lead, Sp
     const long long re = (long long)__hip_atomic_load(tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const long long im = (long long)__hip_atomic_load(tot + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     t = make_double2((double)re * d.prev_inv, (double)im * d.prev_inv);
-    magsum += field_mag(t);
+    sv[n] = field32(t);
     const HG_GLOBAL float* src = as_global(reinterpret_cast<const float*>(d.st_in + n));
 #pragma unroll
     for (int k = 0; k < kWords; ++k) f[k] = src[k];
   }
-  const double mean = block_sum_fixed(magsum, wsum) / (double)N;
+  __syncthreads();
+  float msum = 0.f;
+  for (int m = threadIdx.x & 63; m < N; m += 64) msum += mag32(sv[m]);
+  const float mean = wave_mean_of(msum, N);
   if (n < N) {
     if (lead && d.prev_V) {
       HG_GLOBAL double* v = as_global_mut(reinterpret_cast<double*>(d.prev_V + n));
@@ -232,8 +229,8 @@ __device__ void apply_pending(const JobDev& jb, const PassDesc& d, bool lead, Sp
     }
     SpotRec r;
     __builtin_memcpy(&r, f, sizeof(r));
-    double w;
-    if (!update_rec(r, t, field_mag(t), mean, &w) && lead) jb.status[0] = 4;  // HG_ENUMERIC
+    const float2 v = field32(t);
+    if (!update_rec(r, v, mag32(v), mean) && lead) jb.status[0] = 4;  // HG_ENUMERIC
     __builtin_memcpy(f, &r, sizeof(r));
     float* dst = reinterpret_cast<float*>(recs + n);
 #pragma unroll
