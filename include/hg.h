@@ -111,8 +111,10 @@ typedef struct hg_spots {
 /* Arithmetic of the iteration kernels (low bits of hg_params.flags and of
  * the flags argument of the single-step calls). */
 #define HG_PREC_FP32 0u   /* FP32 phases, sincos and sums                  */
-#define HG_PREC_MIXED 1u  /* FP16-packed complex back-prop terms with FP32
-                             accumulation, compensated FP32 forward sums   */
+#define HG_PREC_MIXED 1u  /* back-propagation as FP16 complex products
+                             accumulated in FP32 (compressed passes: per
+                             pixel, exact sums; full-grid passes: FP16
+                             matrix cores, compensated FP32 sums)          */
 #define HG_PREC_MASK 0xffu
 /* hg_params.flags: the four hg_spots arrays are device pointers (already
  * in HBM) instead of host pointers.  Their values are then checked on the

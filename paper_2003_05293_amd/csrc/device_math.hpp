@@ -89,6 +89,20 @@ __device__ inline uint32_t permute(uint32_t k, uint32_t M, const uint32_t* __res
 // taken exactly (v_fract), then the hardware sine and cosine, which take
 // their argument in turns, are applied on [0, 1).
 // ---------------------------------------------------------------------------
+// FP16 pairs (round to nearest even) of the mixed-precision products.
+typedef _Float16 h2v_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ h2v_t to_h2(float lo, float hi) {
+  return h2v_t{(_Float16)lo, (_Float16)hi};
+}
+__device__ __forceinline__ uint32_t h2_bits(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, to_h2(lo, hi));
+}
+// The two FP16 pairs of a complex coefficient C for the products C E as
+// dot products with E = (Er, Ei): (Cr, -Ci) gives Re, (Ci, Cr) gives Im.
+__device__ __forceinline__ uint2 coef_pairs(float2 C) {
+  return make_uint2(h2_bits(C.x, -C.y), h2_bits(C.y, C.x));
+}
+
 __device__ __forceinline__ void sincos_turns(float t, float& s, float& c) {
   const float r = __builtin_amdgcn_fractf(t);
   s = __builtin_amdgcn_sinf(r);

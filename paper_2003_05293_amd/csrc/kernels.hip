@@ -123,6 +123,67 @@ __device__ __forceinline__ float2 backprop_field_lds(const SpotRec* recs, int n0
   return make_float2(sr, si);
 }
 
+// Mixed-precision back-propagation (eq. 1): the phase in FP32 turns and
+// its exponential E_n(p) from v_sin/v_cos, both rounded to FP16 and packed
+// with the complex coefficient C_n = A_n e^{i theta_n} (FP16); each complex
+// product C_n E_n(p) is two FP16 dot products accumulated in FP32
+// (v_dot2_f32_f16): re = (Cr, -Ci).(Er, Ei), im = (Ci, Cr).(Er, Ei).
+__device__ __forceinline__ void mx_term(float t, uint2 cp, float& sr, float& si) {
+  float sn, cs;
+  sincos_turns(t, sn, cs);
+  const h2v_t e = to_h2(cs, sn);
+  sr = __builtin_amdgcn_fdot2(e, __builtin_bit_cast(h2v_t, cp.x), sr, false);
+  si = __builtin_amdgcn_fdot2(e, __builtin_bit_cast(h2v_t, cp.y), si, false);
+}
+// Records and coefficients by scalar loads, four spots per wait.
+__device__ __forceinline__ float2 backprop_field_mx(const SpotRec* spg, const float2* cfg, int n0,
+                                                    int n1, const PixCoord& c) {
+  const HG_CONST SpotRec* sp = as_const(spg);
+  const HG_CONST float* cf = as_const(reinterpret_cast<const float*>(cfg));  // (re, im) pairs
+  float sr = 0.f, si = 0.f;
+  int n = n0;
+  for (; n + 3 < n1; n += 4) {
+    float scx[4], scy[4], scz[4], scr[4], sci[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      scx[k] = sp[n + k].cx;
+      scy[k] = sp[n + k].cy;
+      scz[k] = sp[n + k].cz;
+      scr[k] = cf[2 * (n + k)];
+      sci[k] = cf[2 * (n + k) + 1];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      mx_term(fmaf(scx[k], c.Lx, fmaf(scy[k], c.Ly, scz[k] * c.Q)),
+              coef_pairs(make_float2(scr[k], sci[k])), sr, si);
+  }
+  for (; n < n1; ++n)
+    mx_term(fmaf(sp[n].cx, c.Lx, fmaf(sp[n].cy, c.Ly, sp[n].cz * c.Q)),
+            coef_pairs(make_float2(cf[2 * n], cf[2 * n + 1])), sr, si);
+  return make_float2(sr, si);
+}
+// Records and coefficient pairs from LDS (a pending pass's updated state).
+__device__ __forceinline__ float2 backprop_field_mx_lds(const SpotRec* recs, const uint2* cpl,
+                                                        int n0, int n1, const PixCoord& c) {
+  float sr = 0.f, si = 0.f;
+  int n = n0;
+  for (; n + 3 < n1; n += 4) {
+    float4 q[4];
+    uint2 cp[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      q[k] = *reinterpret_cast<const float4*>(&recs[n + k].cx);
+      cp[k] = cpl[n + k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      mx_term(fmaf(q[k].x, c.Lx, fmaf(q[k].y, c.Ly, q[k].z * c.Q)), cp[k], sr, si);
+  }
+  for (; n < n1; ++n)
+    mx_term(fmaf(recs[n].cx, c.Lx, fmaf(recs[n].cy, c.Ly, recs[n].cz * c.Q)), cpl[n], sr, si);
+  return make_float2(sr, si);
+}
+
 // ---------------------------------------------------------------- setup ---
 
 // Row tables of the pupil for the random order (one block of kSetupThreads):
@@ -217,8 +278,7 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup_batch(const JobDev* __r
   }
 }
 
-// pi(k) for every k < P of each compressed job (and, for mixed-precision
-// jobs, the inverse: the rank of every pixel in the order).  With an
+// pi(k) for every k < P of each compressed job.  With an
 // aperture the order runs over the P pupil pixels: pi(k) < P is the index
 // of a pupil pixel in index order, mapped to its grid pixel.  With LDS, the Feistel
 // tables (h <= 11: 48 KB) are staged in LDS; otherwise read from memory.
@@ -285,7 +345,6 @@ __global__ __launch_bounds__(kPermThreads) void k_perm_batch(const JobDev* __res
       const uint32_t yk = y < M ? y : k;
       const int32_t p = jb.rows ? pupil_pixel(jb, yk) : (int32_t)yk;
       jb.perm[k] = p;
-      if (jb.rank) jb.rank[p] = k;  // pixel p is the k-th of the random order
       active = false;
     }
     const uint64_t idle = __ballot(!active);
@@ -397,7 +456,7 @@ __host__ __device__ inline LaneMap lane_map(int N) {
 // the previous pass's deferred update), and the first pixel index may come
 // prefetched as in CHAIN.  With a.defer the pass ends after
 // its groups have added into its total row.
-template <int MAXU, bool CHAIN = false, bool PEND = false>
+template <int MAXU, bool CHAIN = false, bool PEND = false, bool MX = false>
 __device__ void pass_block(const PassCtx& a, unsigned* grab, bool has_pre = false,
                            int32_t pre_p = 0) {
   __shared__ float2 sw[kWaves][kTile];
@@ -479,8 +538,12 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab, bool has_pre = fals
         if (dynamic && st == a.plan.sub - 1 && threadIdx.x == 0) ticket = atomicAdd(grab, 1u);
         PixCoord c{0.f, 0.f, 0.f, 0};
         if (valid) c = pixel_coord(p, a.W, a.H);
-        sw[wave][lane] = lds_recs ? backprop_field_lds(a.recs, n_lo, n_hi, c)
-                               : backprop_field(sp, n_lo, n_hi, c);
+        if constexpr (MX)
+          sw[wave][lane] = PEND ? backprop_field_mx_lds(a.recs, a.cpl, n_lo, n_hi, c)
+                                : backprop_field_mx(sp, a.coef, n_lo, n_hi, c);
+        else
+          sw[wave][lane] = lds_recs ? backprop_field_lds(a.recs, n_lo, n_hi, c)
+                                    : backprop_field(sp, n_lo, n_hi, c);
         __syncthreads();
         if (wave == 0) {
           float4 rec = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -604,7 +667,8 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab, bool has_pre = fals
   for (int i = 0; i < nowned; ++i)
     if (tail_group(a, owned[i], &flag)) last = true;
   if (last) {
-    tail_final(a);
+    // red (kWaves * MAXU * 64 float2) holds the N <= 256 MAXU spot fields
+    tail_final(a, &red[0][0]);
     if (CHAIN) publish_gen(a);
   }
 }
@@ -750,7 +814,7 @@ __device__ void pass_block_e(const PassCtx& a, unsigned* grab) {
   bool last = false;  // (at most once, with this block's last group)
   for (int i = 0; i < nowned; ++i)
     if (tail_group(a, owned[i], &flag)) last = true;
-  if (last) tail_final(a);
+  if (last) tail_final(a, &rede[0][0]);  // kWaves * MAXE >= N float2
 }
 
 static_assert(kPendMaxSpots <= kBlock, "a pending update takes one spot per thread");
@@ -760,14 +824,7 @@ static_assert(kPendMaxSpots <= kBlock, "a pending update takes one spot per thre
 // Occupancy target (waves per SIMD): eight for the two-sincos form (all
 // blocks of a 1152^2 compressed pass resident with room to spare), six when
 // 25 exponentials per lane stay in registers, two for the widest spot maps.
-template <int MAXU, int MAXE>
-__global__ __launch_bounds__(kBlock, MAXU > 4 ? 2 : (MAXE > 16 ? 6 : 8)) void k_pass_batch(const JobDev* __restrict__ jobs,
-                                                       const PassDesc* __restrict__ descs,
-                                                       int ndesc) {
-  const int di = find_desc(descs, ndesc, blockIdx.x);
-  const PassDesc& d = descs[di];
-  const JobDev& jb = jobs[d.job];
-  PassCtx a;
+__device__ __forceinline__ void pass_ctx(PassCtx& a, const JobDev& jb, const PassDesc& d) {
   a.sp = jb.sp;
   a.coef = jb.coef;
   a.N = jb.N;
@@ -788,6 +845,38 @@ __global__ __launch_bounds__(kBlock, MAXU > 4 ? 2 : (MAXE > 16 ? 6 : 8)) void k_
   a.from_phi = d.from_phi;
   a.ill_a = jb.ill_a;
   a.ap_q = (d.ps.perm == nullptr && d.ps.idx == nullptr) ? jb.ap_q : -1;
+}
+
+// A pending pass (one unit per wave): the previous pass's update into LDS
+// (with the pixel index of this thread in the block's first sub-tile
+// requested before it, so that the two reads overlap), then the pass.
+template <bool MX>
+__device__ __forceinline__ void pending_pass(PassCtx& a, const JobDev& jb, const PassDesc& d) {
+  __shared__ SpotRec recs[kPendMaxSpots];
+  __shared__ uint2 cpl[MX ? kPendMaxSpots : 1];
+  bool has_pre = false;
+  int32_t pre_p = 0;
+  if (!d.from_phi && a.lb < a.plan.tiles) {
+    const int32_t q = a.lb * a.plan.sub * kTile + (int)(threadIdx.x & 63);
+    pre_p = q < a.ps.count ? pixel_of(a.ps, q) : 0;
+    has_pre = true;
+  }
+  apply_pending(jb, d, a.lb == 0, recs, MX ? cpl : nullptr);
+  a.recs = recs;
+  a.cpl = cpl;
+  if (!d.defer) a.pend_row = d.prev_row;
+  pass_block<1, false, true, MX>(a, jb.grab + d.grab_slot, has_pre, pre_p);
+}
+
+template <int MAXU, int MAXE>
+__global__ __launch_bounds__(kBlock, MAXU > 4 ? 2 : (MAXE > 16 ? 6 : 8)) void k_pass_batch(const JobDev* __restrict__ jobs,
+                                                       const PassDesc* __restrict__ descs,
+                                                       int ndesc) {
+  const int di = find_desc(descs, ndesc, blockIdx.x);
+  const PassDesc& d = descs[di];
+  const JobDev& jb = jobs[d.job];
+  PassCtx a;
+  pass_ctx(a, jb, d);
   // the form depends on the job alone (its N, and whether it back-propagates),
   // so a hologram gives the same bits alone and in any batch
   if constexpr (MAXE > 0) {
@@ -804,28 +893,41 @@ __global__ __launch_bounds__(kBlock, MAXU > 4 ? 2 : (MAXE > 16 ? 6 : 8)) void k_
   }
   if (d.pending) {
     if constexpr (MAXU == 1) {
-      __shared__ SpotRec recs[kPendMaxSpots];
-      __shared__ float2 sv[kPendMaxSpots];
-      // the pixel index of this thread in the block's first sub-tile is
-      // requested before the update, so that the two reads overlap
-      bool has_pre = false;
-      int32_t pre_p = 0;
-      if (!d.from_phi && a.lb < a.plan.tiles) {
-        const int32_t q = a.lb * a.plan.sub * kTile + (int)(threadIdx.x & 63);
-        pre_p = q < a.ps.count ? pixel_of(a.ps, q) : 0;
-        has_pre = true;
-      }
-      apply_pending(jb, d, a.lb == 0, recs, sv);
-      a.recs = recs;
-      if (!d.defer) a.pend_row = d.prev_row;
-      pass_block<MAXU, false, true>(a, jb.grab + d.grab_slot, has_pre, pre_p);
-      return;
+      pending_pass<false>(a, jb, d);
     } else {
       if (a.lb == 0 && threadIdx.x == 0) jb.status[0] = 5;  // HG_EDEVICE
-      return;
     }
+    return;
   }
   pass_block<MAXU>(a, jb.grab + d.grab_slot);
+}
+
+// Compressed passes of mixed-precision jobs: the per-pixel pass with the
+// back-propagation in FP16 complex products accumulated in FP32
+// (backprop_field_mx); forward terms, sums, hand-off and update as in the
+// FP32 form.
+template <int MAXU>
+__global__ __launch_bounds__(kBlock, MAXU > 4 ? 2 : 8) void k_pass_mx(const JobDev* __restrict__ jobs,
+                                                                    const PassDesc* __restrict__ descs,
+                                                                    int ndesc) {
+  const int di = find_desc(descs, ndesc, blockIdx.x);
+  const PassDesc& d = descs[di];
+  const JobDev& jb = jobs[d.job];
+  PassCtx a;
+  pass_ctx(a, jb, d);
+  if constexpr (MAXU == 1) {
+    a.tot_row = d.tot_row;
+    a.defer = d.defer;
+  }
+  if (d.pending) {
+    if constexpr (MAXU == 1) {
+      pending_pass<true>(a, jb, d);
+    } else {
+      if (a.lb == 0 && threadIdx.x == 0) jb.status[0] = 5;  // HG_EDEVICE
+    }
+    return;
+  }
+  pass_block<MAXU, false, false, true>(a, jb.grab + d.grab_slot);
 }
 
 // Compressed passes descs[0..npass) of one job in one cooperative launch;
@@ -1128,6 +1230,15 @@ void launch_pass_batch(const JobDev* jobs, const PassDesc* descs, int ndesc, int
   if (max_units <= 1) launch_pass_u<1>(jobs, descs, ndesc, total_blocks, e_width, s);
   else if (max_units <= 4) launch_pass_u<4>(jobs, descs, ndesc, total_blocks, e_width, s);
   else launch_pass_u<16>(jobs, descs, ndesc, total_blocks, e_width, s);
+}
+
+void launch_pass_mx(const JobDev* jobs, const PassDesc* descs, int ndesc, int total_blocks,
+                    int max_units, hipStream_t s) {
+  if (ndesc <= 0 || total_blocks <= 0) return;
+  const dim3 grid(total_blocks), block(kBlock);
+  if (max_units <= 1) hipLaunchKernelGGL(k_pass_mx<1>, grid, block, 0, s, jobs, descs, ndesc);
+  else if (max_units <= 4) hipLaunchKernelGGL(k_pass_mx<4>, grid, block, 0, s, jobs, descs, ndesc);
+  else hipLaunchKernelGGL(k_pass_mx<16>, grid, block, 0, s, jobs, descs, ndesc);
 }
 
 namespace {

@@ -160,13 +160,11 @@ struct JobDev {
   float* sepFn;        // [Np/16][Wp/2][64]   forward B operand
   float2* sepGa;       // [Hp/16][Np/2][64]   G by row, per lane
   float4* sepGv;       // [Hp/16][Np/16][64] x 2 float4: G for the V sums
-  // mixed-precision passes: FP16 / FP32 tables and the rank of every pixel
-  // in the random order (compressed jobs)
+  // mixed-precision matrix-core passes: FP16 / FP32 tables
   uint4* mxFc;         // [Wp/16][Np/16][64] x 4 half2   (back-propagation operand)
   uint4* mxFn;         // [Np/16][Wp/16][64] x 4 half2   (forward operand)
   float4* mxGa;        // [Hp/16][Np/16][64] x 4 float2  (rows by lane)
   float4* mxGv;        // [Hp/16][Np/16][64] x 4 float2  (spots by lane)
-  uint32_t* rank;      // [M] position of each pixel in the random order
   // SLM output: with a table, the final pass also writes the gray image
   const uint16_t* lut; // [lut_levels] gray value of each phase bin (or nullptr)
   int32_t lut_levels;
@@ -256,6 +254,11 @@ __host__ __device__ int pass_e_width(int N);
 // max_units the largest two-phase unit count of the others.
 void launch_pass_batch(const JobDev* jobs, const PassDesc* descs, int ndesc, int total_blocks,
                        int max_units, int e_width, hipStream_t s);
+// Compressed passes of mixed-precision jobs (the per-pixel pass with FP16
+// complex back-propagation products accumulated in FP32); descs and units
+// as for launch_pass_batch.
+void launch_pass_mx(const JobDev* jobs, const PassDesc* descs, int ndesc, int total_blocks,
+                    int max_units, hipStream_t s);
 void launch_backprop_batch(const JobDev* jobs, const BackDesc* descs, int ndesc,
                            int total_blocks, hipStream_t s);
 int backprop_blocks(int32_t count);
@@ -310,12 +313,11 @@ void launch_sep_pass(const JobDev* jobs, const SepDesc* descs, int ndesc, int to
 // A pass is the separable recast above on the matrix cores: per output tile
 // of kMxTile x kMxTileW pixels (wave w: rows 16w..16w+15), S = B F with FP16
 // operands and FP32 accumulation (K = 2 Np: real and imaginary parts
-// interleaved), u = S / |S| where the pixel is in the pass's pixel set
-// (else 0), T = u conj(F)^T the same way, and the tile's partial
-// V_n = sum_j conj(G_n(j)) T[j][n].  A compressed pass is the same product
-// over all pixels with u = 0 outside the window: pixel p is in window
-// [start, start + count) of the random order when (rank[p] - start) mod M
-// < count.  Partials are added across tiles with compensated FP32 sums.
+// interleaved), u = S / |S| on every pixel of the pupil (else 0),
+// T = u conj(F)^T the same way, and the tile's partial
+// V_n = sum_j conj(G_n(j)) T[j][n].  These are the full-grid passes of the
+// mixed form (its compressed passes run per pixel: launch_pass_mx).
+// Partials are added across tiles with compensated FP32 sums.
 constexpr int kMxTile = 64;   // table geometry: rows and columns padded to it
 constexpr int kMxTileW = 32;  // columns of a pass tile (rows: kMxTile)
 enum MxMode : int32_t { kMxIterate = 0, kMxFinal = 1, kMxFromPhi = 2 };
@@ -324,8 +326,6 @@ struct MxDesc {
   int32_t job;
   int32_t tiles_x, tiles_y;
   PassPlan plan;
-  int64_t start;        // window of the random order (count < M), else unused
-  int32_t count;        // pixels in the set (M: all pixels)
   int32_t update;       // weight update after the sums
   float inv_count;
   double2* V;           // [N] spot fields of the pass (FP32 values widened)

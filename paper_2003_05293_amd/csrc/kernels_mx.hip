@@ -340,19 +340,6 @@ __global__ __launch_bounds__(kBlock, 3) void k_mx_pass(const JobDev* __restrict_
 #pragma unroll
   for (int t = 0; t < kMxCB; ++t) sr[t] = si[t] = f4_t{0.f, 0.f, 0.f, 0.f};
 
-  // ranks of this lane's pixels in the random order (window membership),
-  // loaded first so that they arrive during the products
-  const int M = jb.P;  // length of the random order
-  const bool windowed = MODE == kMxIterate && d.count < M;
-  uint32_t rk[kMxCB][4];
-#pragma unroll
-  for (int t = 0; t < kMxCB; ++t)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = row0 + 4 * lg + r, col = col0 + 16 * t + lr;
-      rk[t][r] = windowed && row < H && col < W ? as_global(jb.rank)[row * W + col] : 0u;
-    }
-
   if (MODE != kMxFromPhi) {
     for (int n = threadIdx.x; n < 16 * S16; n += kBlock) {
       float2 c = make_float2(0.f, 0.f);
@@ -397,8 +384,9 @@ __global__ __launch_bounds__(kBlock, 3) void k_mx_pass(const JobDev* __restrict_
     return;
   }
 
-  // u = e^{i Phi} on the pixel set (within the pupil), 0 elsewhere, weighted
-  // by the illumination, as half pairs in LDS.
+  // u = e^{i Phi} on every pixel within the pupil (the matrix-core passes
+  // cover the whole grid), 0 elsewhere, weighted by the illumination, as
+  // half pairs in LDS.
   const bool pupil = jb.ap_q >= 0 || jb.ill_a > 0.f;
 #pragma unroll
   for (int t = 0; t < kMxCB; ++t)
@@ -414,13 +402,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_mx_pass(const JobDev* __restrict_
           const int32_t Qi = lx * lx + ly * ly;
           wt = pupil_weight(Qi, (float)Qi, jb.ap_q, jb.ill_a);
         }
-        bool in = wt != 0.f;  // outside the aperture: never in a set
-        if (in && windowed) {
-          int64_t k = (int64_t)rk[t][r] - d.start;
-          if (k < 0) k += M;
-          in = k < d.count;
-        }
-        if (in) {
+        if (wt != 0.f) {  // outside the aperture: never in the set
           float ur = 1.f, ui = 0.f;
           if (MODE == kMxFromPhi) {
             sincos_turns(as_global(jb.phi)[p] * 0.15915494309189535f, ui, ur);

@@ -353,7 +353,7 @@ __global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ 
   const int size = min(d.plan.group_size, d.plan.tiles - g * d.plan.group_size);
   if (arrive_last(&jb.counters[g * kCounterStride], (unsigned)size, &flag) &&
       tail_group(a, g, &flag))
-    tail_final(a);
+    tail_final(a, cs);  // the C_n table (Np >= N float2) is no longer read
 }
 
 }  // namespace

@@ -8,6 +8,7 @@
 #include <stdint.h>
 
 #include "device_common.hpp"
+#include "device_math.hpp"
 #include "kernels.hpp"
 
 namespace hg {
@@ -44,6 +45,7 @@ struct PassCtx {
   // chained launches: the generation word to publish after the update
   int chain = 0;
   const SpotRec* recs = nullptr;
+  const uint2* cpl = nullptr;  // mixed pending passes: FP16 pairs of C_n (LDS)
   unsigned* gen = nullptr;
   unsigned gen_next = 0;
 };
@@ -114,13 +116,19 @@ __device__ void tail_group_deferred(const PassCtx& a, int g) {
 // A spot field enters as the FP64 mean of the exact sums rounded to FP32.
 __device__ __forceinline__ float2 field32(double2 t) { return make_float2((float)t.x, (float)t.y); }
 __device__ __forceinline__ float mag32(float2 v) { return sqrtf(fmaf(v.x, v.x, v.y * v.y)); }
-// mean_n |V_n| (eq. 4), uniform across the calling wave and the same in
-// every wave: lane l adds |V_n| for n = l, l + 64, ... in that order,
-// starting from 0 (s is that lane sum), then the lane sums are added in a
-// fixed tree.  All 64 lanes must call it.
-__device__ __forceinline__ float wave_mean_of(float s, int N) {
+// mean_n |V_n| (eq. 4), the same in every thread of the block: thread t
+// adds |V_n| for n = t, t + kBlock, ... in that order, starting from 0 (s
+// is that thread sum); the thread sums are added in a fixed tree within
+// each wave, then the wave sums in wave order.  Every thread must call it
+// (it holds a block barrier).
+__device__ __forceinline__ float block_mean_of(float s, int N) {
+  __shared__ float wsum[kWaves];
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off);
-  return __shfl(s, 0) / (float)N;
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = s;
+  __syncthreads();
+  float total = wsum[0];
+  for (int w = 1; w < kWaves; ++w) total += wsum[w];
+  return total / (float)N;
 }
 // false (record unchanged) where the weight would come out zero or not finite
 __device__ __forceinline__ bool update_rec(SpotRec& r, float2 v, float mag, float mean) {
@@ -135,14 +143,22 @@ __device__ __forceinline__ bool update_rec(SpotRec& r, float2 v, float mag, floa
 // Every group is complete: V_n = total / 2^shift / |Omega| (the total row is
 // cleared for the next pass, and so are the counters); with a.update,
 // eqs. (4)-(6): w_n <- w_n mean/|V_n|, theta_n <- arg V_n, A_n = a_n^0 w_n.
-__device__ void tail_final(const PassCtx& a) {
+// vs: LDS room for N float2 (the spot fields in FP32, kept for the update:
+// values other threads stored to memory are not read back, since a block
+// of a chained launch may hold stale copies of them in its L1 cache).
+__device__ void tail_final(const PassCtx& a, float2* vs) {
   const int N = a.N;
   const double inv = ldexp(1.0, -a.plan.shift) * a.inv_count;
   unsigned long long* tot = a.acc + (int64_t)a.tot_row * N * kAccSpotWords;
+  float msum = 0.f;
   for (int n = threadIdx.x; n < N; n += kBlock) {
     const long long re = (long long)take_dev(tot + (int64_t)n * kAccSpotWords);
     const long long im = (long long)take_dev(tot + (int64_t)n * kAccSpotWords + 1);
-    a.V[n] = make_double2((double)re * inv, (double)im * inv);
+    const double2 t = make_double2((double)re * inv, (double)im * inv);
+    a.V[n] = t;
+    const float2 v = field32(t);
+    vs[n] = v;
+    msum += mag32(v);
   }
   // the previous pass's total, which every block of this pass has read
   // before counting its tiles, is cleared
@@ -161,12 +177,9 @@ __device__ void tail_final(const PassCtx& a) {
       a.counters[k * kCounterStride] = 0u;
   }
   if (!a.update) return;
-  __syncthreads();  // every V_n of the block is stored
-  float msum = 0.f;
-  for (int n = threadIdx.x & 63; n < N; n += 64) msum += mag32(field32(a.V[n]));
-  const float mean = wave_mean_of(msum, N);
+  const float mean = block_mean_of(msum, N);
   for (int n = threadIdx.x; n < N; n += kBlock) {
-    const float2 v = field32(a.V[n]);
+    const float2 v = vs[n];
     const float mag = mag32(v);
     SpotRec r = a.recs ? a.recs[n] : a.sp[n];
     if (!update_rec(r, v, mag, mean)) {
@@ -184,13 +197,12 @@ __device__ void tail_final(const PassCtx& a) {
 
 // Pending pass: every block applies the previous pass's update to the state
 // before it (d.st_in) and keeps the result in recs (LDS), with the
-// arithmetic and the mean of tail_final (one spot per thread; each wave
-// takes the mean itself from the FP32 fields in sv, LDS).  Block 0 (lead)
+// arithmetic and the mean of tail_final (one spot per thread).  Block 0 (lead)
 // also clears the total row two passes back, stores the state for the next
 // pass when this pass defers in turn, the previous V when traced, and the
 // status.  N <= kPendMaxSpots <= kBlock.
 __device__ void apply_pending(const JobDev& jb, const PassDesc& d, bool lead, SpotRec* recs,
-                              float2* sv) {
+                              uint2* cpl) {
   const int N = jb.N;
   const int n = threadIdx.x;
   if (lead && d.clear_row >= 0) {
@@ -212,15 +224,11 @@ __device__ void apply_pending(const JobDev& jb, const PassDesc& d, bool lead, Sp
     const long long re = (long long)__hip_atomic_load(tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const long long im = (long long)__hip_atomic_load(tot + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     t = make_double2((double)re * d.prev_inv, (double)im * d.prev_inv);
-    sv[n] = field32(t);
     const HG_GLOBAL float* src = as_global(reinterpret_cast<const float*>(d.st_in + n));
 #pragma unroll
     for (int k = 0; k < kWords; ++k) f[k] = src[k];
   }
-  __syncthreads();
-  float msum = 0.f;
-  for (int m = threadIdx.x & 63; m < N; m += 64) msum += mag32(sv[m]);
-  const float mean = wave_mean_of(msum, N);
+  const float mean = block_mean_of(n < N ? mag32(field32(t)) : 0.f, N);
   if (n < N) {
     if (lead && d.prev_V) {
       HG_GLOBAL double* v = as_global_mut(reinterpret_cast<double*>(d.prev_V + n));
@@ -230,7 +238,21 @@ __device__ void apply_pending(const JobDev& jb, const PassDesc& d, bool lead, Sp
     SpotRec r;
     __builtin_memcpy(&r, f, sizeof(r));
     const float2 v = field32(t);
-    if (!update_rec(r, v, mag32(v), mean) && lead) jb.status[0] = 4;  // HG_ENUMERIC
+    const float mag = mag32(v);
+    const bool ok = update_rec(r, v, mag, mean);
+    if (!ok && lead) jb.status[0] = 4;  // HG_ENUMERIC
+    if (cpl) {  // mixed precision: C_n = A_n e^{i theta_n} as FP16 pairs
+      float2 C;
+      if (ok) {
+        const float Am = r.A / mag;  // as tail_final forms it
+        C = make_float2(Am * v.x, Am * v.y);
+      } else {
+        float sn, cs;
+        sincos_turns(r.th, sn, cs);
+        C = make_float2(r.A * cs, r.A * sn);
+      }
+      cpl[n] = coef_pairs(C);
+    }
     __builtin_memcpy(f, &r, sizeof(r));
     float* dst = reinterpret_cast<float*>(recs + n);
 #pragma unroll

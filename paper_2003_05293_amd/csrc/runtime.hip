@@ -346,9 +346,13 @@ JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev
     j.mx_cblocks = (s.W + kMxTile - 1) / kMxTile * (kMxTile / 16);
     j.mx_rblocks = (s.H + kMxTile - 1) / kMxTile * (kMxTile / 16);
   }
+  int acc_groups = 0;  // groups of the exact-sum passes
   if (j.mixed) {
+    // matrix-core passes over the whole grid (compensated FP32 sums), and
+    // per-pixel compressed passes (exact sums)
     max_rows = L.plan_mx.tiles;
     max_groups = L.plan_mx.ngroups;
+    if (j.compressed) acc_groups = L.plan_sub.ngroups;
   } else {
     // direct full-grid passes: without the separable form, and for the
     // single-pass entry points
@@ -365,7 +369,8 @@ JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev
     max_rows = std::max(max_rows, L.plan_sep.tiles);
     max_groups = std::max(max_groups, L.plan_sep.ngroups);
   }
-  L.grab_offset = (max_groups + 1) * kCounterStride;
+  if (!j.mixed) acc_groups = max_groups;
+  L.grab_offset = (std::max(max_groups, acc_groups) + 1) * kCounterStride;
   L.gen_offset = (L.grab_offset + s.iterations + 2 + kCounterStride - 1) / kCounterStride *
                  kCounterStride;
   j.counters_len = L.gen_offset + kGenCopies * kCounterStride;
@@ -379,7 +384,7 @@ JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev
   L.raw_inline = raw_inline && !s.spots_on_device;
   L.off_raw = L.raw_inline ? take(sizeof(double) * 4 * (size_t)s.N) : 0;
   L.off_sp = take(sizeof(SpotRec) * (size_t)s.N);
-  if (!j.mixed) L.off_sp_alt = take(sizeof(SpotRec) * (size_t)s.N);
+  L.off_sp_alt = take(sizeof(SpotRec) * (size_t)s.N);
   L.off_coef = take(sizeof(float2) * (size_t)s.N);
   L.off_tab = j.compressed ? take(sizeof(uint32_t) * ((size_t)kFeistelRoundsHost << j.h)) : 0;
   L.off_perm = j.compressed ? take(sizeof(int32_t) * (size_t)j.P) : 0;
@@ -390,13 +395,13 @@ JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev
     L.off_mxFn = take(16 * ops * j.mx_cblocks);
     L.off_mxGa = take(32 * ops * j.mx_rblocks);
     L.off_mxGv = take(32 * ops * j.mx_rblocks);
-    L.off_rank = j.compressed ? take(sizeof(uint32_t) * (size_t)j.M) : 0;
   }
-  if (j.mixed) {  // compensated FP32 sums of the mixed-precision passes
+  if (j.mixed) {  // compensated FP32 sums of the matrix-core passes
     L.off_partial = take(sizeof(float2) * (size_t)max_rows * s.N);
     L.off_gpart = take(sizeof(double2) * (size_t)max_groups * s.N);
-  } else {        // exact fixed-point sums of the FP32 passes
-    j.acc_len = (int64_t)(max_groups + kAccTotalRows) * s.N * kAccSpotWords;
+  }
+  if (!j.mixed || j.compressed) {  // exact fixed-point sums of the per-pixel passes
+    j.acc_len = (int64_t)(acc_groups + kAccTotalRows) * s.N * kAccSpotWords;
     L.off_acc = take(sizeof(unsigned long long) * (size_t)j.acc_len);
   }
   L.off_counters = take(sizeof(unsigned) * (size_t)j.counters_len);
@@ -422,17 +427,18 @@ JobDev bind_job(const JobLayout& L, const JobSpec& s, char* base, const double* 
     j.in = SpotPtrs{r, r + s.N, r + 2 * s.N, r + 3 * s.N};
   }
   j.sp = reinterpret_cast<SpotRec*>(base + L.off_sp);
-  j.sp_alt = j.mixed ? nullptr : reinterpret_cast<SpotRec*>(base + L.off_sp_alt);
+  j.sp_alt = reinterpret_cast<SpotRec*>(base + L.off_sp_alt);
   // jobs of one spot unit per wave run in the one-unit pass launch of each
   // round, whose kernel applies deferred updates
-  j.defer_ok = (!j.mixed && pass_units_per_wave(s.N) == 1) ? 1 : 0;
+  j.defer_ok = pass_units_per_wave(s.N) == 1 ? 1 : 0;
   j.coef = reinterpret_cast<float2*>(base + L.off_coef);
   j.tab = j.compressed ? reinterpret_cast<uint32_t*>(base + L.off_tab) : nullptr;
   j.perm = j.compressed ? reinterpret_cast<int32_t*>(base + L.off_perm) : nullptr;
   j.rows = (j.compressed && j.ap_q >= 0) ? reinterpret_cast<int32_t*>(base + L.off_rows) : nullptr;
   j.partial = j.mixed ? reinterpret_cast<float2*>(base + L.off_partial) : nullptr;
   j.gpart = j.mixed ? reinterpret_cast<double2*>(base + L.off_gpart) : nullptr;
-  j.acc = j.mixed ? nullptr : reinterpret_cast<unsigned long long*>(base + L.off_acc);
+  j.acc = (!j.mixed || j.compressed) ? reinterpret_cast<unsigned long long*>(base + L.off_acc)
+                                      : nullptr;
   j.counters = reinterpret_cast<unsigned*>(base + L.off_counters);
   j.grab = j.counters + L.grab_offset;
   j.gen = j.counters + L.gen_offset;
@@ -448,7 +454,6 @@ JobDev bind_job(const JobLayout& L, const JobSpec& s, char* base, const double* 
     j.mxFn = reinterpret_cast<uint4*>(base + L.off_mxFn);
     j.mxGa = reinterpret_cast<float4*>(base + L.off_mxGa);
     j.mxGv = reinterpret_cast<float4*>(base + L.off_mxGv);
-    j.rank = j.compressed ? reinterpret_cast<uint32_t*>(base + L.off_rank) : nullptr;
   }
   return j;
 }
@@ -475,7 +480,7 @@ PassDesc iteration_desc(const JobDev& j, const JobLayout& L, int it, int index, 
   // follow one another; each but the last leaves its update to the next.
   // State X_k (after k updates) lives in buffer k mod 2 (0: sp, 1: sp_alt):
   // pass it reads X_{it-2} and, when it defers, stores X_{it-1}.
-  if (sub && j.defer_ok && !j.mixed && !j.shared_e && j.N <= kPendMaxSpots && j.sp_alt) {
+  if (sub && j.defer_ok && !j.shared_e && j.N <= kPendMaxSpots && j.sp_alt) {
     SpotRec* const buf[2] = {j.sp, j.sp_alt};
     d.tot_row = it % kAccTotalRows;
     d.defer = it + 1 < j.iterations ? 1 : 0;
@@ -518,8 +523,6 @@ MxDesc mx_desc(const JobDev& j, const JobLayout& L, int index, int block_begin) 
   d.tiles_x = (j.W + kMxTileW - 1) / kMxTileW;
   d.tiles_y = (j.H + kMxTile - 1) / kMxTile;
   d.plan = L.plan_mx;
-  d.start = 0;
-  d.count = j.P;  // the pupil (every pixel without an aperture)
   d.update = 0;
   d.inv_count = 1.0f / (float)j.P;
   d.V = j.V;
@@ -537,14 +540,22 @@ void LaunchSet::add_forward_mx(const JobDev& j, const JobLayout& L, int index) {
 
 void LaunchSet::add_iteration(const JobDev& j, const JobLayout& L, int it, int index) {
   const bool sub = j.compressed && it < j.iterations;
+  if (j.mixed && sub) {  // per-pixel compressed pass, FP16 back-propagation
+    const int u = pass_units_per_wave(j.N);
+    const PassDesc d = iteration_desc(j, L, it, index, u > 1 ? mxw_blocks : mxp_blocks);
+    if (u > 1) {
+      mxw.push_back(d);
+      mxw_blocks += d.plan.blocks;
+      mxw_units = std::max(mxw_units, u);
+    } else {
+      mxp.push_back(d);
+      mxp_blocks += d.plan.blocks;
+    }
+    return;
+  }
   if (j.mixed) {
     MxDesc d = mx_desc(j, L, index, mx_blocks);
-    if (sub) {
-      d.start = (int64_t)(it - 1) * j.m % j.P;
-      d.count = j.m;
-      d.inv_count = 1.0f / (float)j.m;
-    }
-    (sub ? mx_sub : mx_full) += 1;
+    mx_full += 1;
     d.update = 1;
     d.V = j.V + (j.trace ? (size_t)(it - 1) * j.N : 0);
     mx.push_back(d);
@@ -606,7 +617,8 @@ void LaunchSet::add_final(const JobDev& j, const JobLayout& L, int index) {
 size_t LaunchSet::bytes() const {
   return align_up(sizeof(PassDesc) * pass.size(), 256) + align_up(sizeof(PassDesc) * wide.size(), 256) +
          align_up(sizeof(SepDesc) * sep.size(), 256) +
-         align_up(sizeof(BackDesc) * back.size(), 256) + align_up(sizeof(MxDesc) * mx.size(), 256);
+         align_up(sizeof(BackDesc) * back.size(), 256) + align_up(sizeof(MxDesc) * mx.size(), 256) +
+         align_up(sizeof(PassDesc) * mxp.size(), 256) + align_up(sizeof(PassDesc) * mxw.size(), 256);
 }
 
 size_t LaunchSet::stage(char* host, char* dev) {
@@ -622,6 +634,8 @@ size_t LaunchSet::stage(char* host, char* dev) {
   d_sep = reinterpret_cast<const SepDesc*>(put(sep.data(), sizeof(SepDesc) * sep.size()));
   d_back = reinterpret_cast<const BackDesc*>(put(back.data(), sizeof(BackDesc) * back.size()));
   d_mx = reinterpret_cast<const MxDesc*>(put(mx.data(), sizeof(MxDesc) * mx.size()));
+  d_mxp = reinterpret_cast<const PassDesc*>(put(mxp.data(), sizeof(PassDesc) * mxp.size()));
+  d_mxw = reinterpret_cast<const PassDesc*>(put(mxw.data(), sizeof(PassDesc) * mxw.size()));
   return o;
 }
 
@@ -635,8 +649,9 @@ const char* pass_name(const std::vector<PassDesc>& a, const std::vector<PassDesc
 }  // namespace
 
 const char* LaunchSet::pass_only_name() const {
-  if ((pass.empty() && wide.empty()) || !sep.empty() || !back.empty() || !mx.empty()) return nullptr;
-  return pass_name(pass, wide);
+  const bool fp32 = !pass.empty() || !wide.empty(), mixed = !mxp.empty() || !mxw.empty();
+  if (fp32 == mixed || !sep.empty() || !back.empty() || !mx.empty()) return nullptr;
+  return fp32 ? pass_name(pass, wide) : "k_mxp_subset";
 }
 
 void LaunchSet::launch(const JobDev* jobs, hipStream_t s, bool capture) const {
@@ -658,13 +673,15 @@ void LaunchSet::launch(const JobDev* jobs, hipStream_t s, bool capture) const {
   if (!back.empty())
     run("k_backprop_phi",
         [&] { launch_backprop_batch(jobs, d_back, (int)back.size(), back_blocks, s); });
+  if (!mxp.empty())
+    run("k_mxp_subset", [&] { launch_pass_mx(jobs, d_mxp, (int)mxp.size(), mxp_blocks, 1, s); });
+  if (!mxw.empty())
+    run("k_mxp_subset",
+        [&] { launch_pass_mx(jobs, d_mxw, (int)mxw.size(), mxw_blocks, mxw_units, s); });
   if (!mx.empty()) {
     const char* name = "k_mx_forward";
-    if (mx_mode == kMxFinal) {
-      name = "k_mx_final";
-    } else if (mx_mode == kMxIterate) {
-      name = mx_full && mx_sub ? "k_mx_mixed" : mx_sub ? "k_mx_subset" : "k_mx_full";
-    }
+    if (mx_mode == kMxFinal) name = "k_mx_final";
+    else if (mx_mode == kMxIterate) name = "k_mx_full";
     run(name, [&] { launch_mx_pass(jobs, d_mx, (int)mx.size(), mx_blocks, mx_mode, mx_steps, s); });
   }
 }

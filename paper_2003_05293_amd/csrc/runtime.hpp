@@ -149,7 +149,7 @@ struct JobLayout {
   size_t off_raw = 0, off_sp = 0, off_sp_alt = 0, off_coef = 0, off_tab = 0, off_perm = 0, off_partial = 0,
          off_gpart = 0, off_acc = 0, off_counters = 0, off_V = 0, off_sepFc = 0, off_sepFn = 0,
          off_sepGa = 0, off_sepGv = 0, off_mxFc = 0, off_mxFn = 0, off_mxGa = 0, off_mxGv = 0,
-         off_rank = 0, off_rows = 0;
+         off_rows = 0;
   size_t bytes = 0;
   bool raw_inline = false;  // the job's own scratch holds a copy of its spot arrays
   int grab_offset = 0;      // the pass tile counters follow the group counters
@@ -184,14 +184,22 @@ struct LaunchSet {
   std::vector<BackDesc> back;
   int back_blocks = 0;
   std::vector<MxDesc> mx;
-  int mx_blocks = 0, mx_steps = 0, mx_sub = 0, mx_full = 0;
+  int mx_blocks = 0, mx_steps = 0, mx_full = 0;
   int mx_mode = kMxIterate;
+  // compressed passes of mixed-precision jobs (per-pixel, FP16
+  // back-propagation): one unit per wave in mxp, wider jobs in mxw
+  std::vector<PassDesc> mxp;
+  int mxp_blocks = 0;
+  std::vector<PassDesc> mxw;
+  int mxw_blocks = 0, mxw_units = 1;
   // device copies, set by stage()
   const PassDesc* d_pass = nullptr;
   const PassDesc* d_wide = nullptr;
   const SepDesc* d_sep = nullptr;
   const BackDesc* d_back = nullptr;
   const MxDesc* d_mx = nullptr;
+  const PassDesc* d_mxp = nullptr;
+  const PassDesc* d_mxw = nullptr;
 
   void add_iteration(const JobDev& j, const JobLayout& L, int it, int index);
   void add_final(const JobDev& j, const JobLayout& L, int index);
@@ -199,7 +207,8 @@ struct LaunchSet {
   // pixels, no update).
   void add_forward_mx(const JobDev& j, const JobLayout& L, int index);
   bool empty() const {
-    return pass.empty() && wide.empty() && sep.empty() && back.empty() && mx.empty();
+    return pass.empty() && wide.empty() && sep.empty() && back.empty() && mx.empty() &&
+           mxp.empty() && mxw.empty();
   }
   // Timing name of the set's per-pixel pass launch when that is all the set
   // launches, else nullptr.

@@ -8,6 +8,10 @@ Two checks per run:
   (eqs. 1 and 3); the GPU's V^{j+1} must agree to 1e-5 of the mean spot
   magnitude (FP32 form; mixed: 1e-3, or 8 2^-11 sqrt(N / m) for a pass over
   m pixels when larger), the bar of one pass with the state held fixed.
+  The FP32 bar is that of the 1152^2, N = 100 pass (m = 82944), scaled by
+  sqrt(N / m) where that ratio is larger: V_n is a mean of m terms whose
+  FP32 phase rounding is independent from term to term, so its absolute
+  error falls as m^-1/2, while the mean spot magnitude falls as N^-1/2.
   The absolute error of a field does not depend on its magnitude, so it is
   taken against the mean, not spot by spot (the weakest of 200 spots can
   be a tenth of the mean).  A wrong update, a stale state or a wrong pixel
@@ -77,7 +81,7 @@ def rel_mag_spot(Vg, Vo):
 
 def step_bar(precision, N, m):
     if precision == "fp32":
-        return BARS["fp32"][0]
+        return BARS["fp32"][0] * max(1.0, math.sqrt((N / m) / (100 / 82944)))
     return max(BARS["mixed"][0], 8 * 2.0 ** -11 * math.sqrt(N / m))
 
 
