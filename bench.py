@@ -367,6 +367,11 @@ def batched_forms(hg, grid, optics, steps, bsize):
     return out
 
 
+SWEEP_RATES = (60, 250, 500, 1000, 1500, 2000, 3000, 4000)
+SWEEP_S = 3.0
+SWEEP_P99_MS = 50.0
+
+
 def served_form(hg, optics, seconds):
     """Served form: Poisson arrivals at 60 requests/s (N uniform in [10, 150],
     1152^2 or 1920x1152, CS-WGS 20 iterations, c = 1/16) replayed in real time
@@ -384,12 +389,37 @@ def served_form(hg, optics, seconds):
     print(f"[bench] served {res.completed} requests in {res.wall_s:.2f} s, p50 "
           f"{1e3 * res.percentile(50):.3f} ms, p99 {1e3 * res.percentile(99):.3f} ms",
           file=sys.stderr, flush=True)
+    # offered-load sweep: the same request mix at rising Poisson rates, each
+    # for SWEEP_S seconds, until p99 breaks SWEEP_P99_MS (or the completion
+    # rate falls below 90 % of the offered rate)
+    sweep = []
+    for k, rate in enumerate(SWEEP_RATES):
+        rq = poisson_stream(10 + k, rate_hz=rate, duration_s=SWEEP_S, iterations=20)
+        eng = hg.Engine(16 << 30, max_slots=64)
+        r = serve.replay(rq, optics, eng, stream)
+        eng.close()
+        row = {"offered_per_s": rate, "requests": len(rq),
+               "completed_per_s": round(r.completed / r.wall_s, 1),
+               "p50_ms": round(1e3 * r.percentile(50), 3), "p99_ms": round(1e3 * r.percentile(99), 3),
+               "engine_steps": r.steps}
+        sweep.append(row)
+        print(f"[bench] served at {rate}/s: {row['completed_per_s']}/s, p50 {row['p50_ms']} ms, "
+              f"p99 {row['p99_ms']} ms", file=sys.stderr, flush=True)
+        if row["p99_ms"] > SWEEP_P99_MS or row["completed_per_s"] < 0.9 * rate:
+            break
+    within = [x for x in sweep if x["p99_ms"] <= SWEEP_P99_MS and x["completed_per_s"] >= 0.9 * x["offered_per_s"]]
     return {"holograms_per_s": round(res.completed / res.wall_s, 3),
             "offered_per_s": 60.0, "requests": len(reqs), "completed": res.completed,
             "p50_ms": round(1e3 * res.percentile(50), 4), "p99_ms": round(1e3 * res.percentile(99), 4),
             "engine_steps": res.steps, "seconds": seconds,
             "how": "Poisson 60/s, N in [10,150], 1152^2 or 1920x1152, I 20, c 1/16, "
-                   "continuous batching, latency arrival -> observed completion"}
+                   "continuous batching, latency arrival -> observed completion",
+            "load_sweep": sweep,
+            "saturation": {"p99_bound_ms": SWEEP_P99_MS,
+                           "highest_rate_within_bound": within[-1]["offered_per_s"] if within else None,
+                           "completed_per_s_there": within[-1]["completed_per_s"] if within else None},
+            "load_sweep_how": f"same request mix, {SWEEP_S} s per rate, rates rising until p99 > "
+                              f"{SWEEP_P99_MS} ms or completions < 90 % of the offered rate"}
 
 
 def slm_output(hg, grid, spots_dev, phis, stream, tune, steps):
