@@ -189,7 +189,7 @@ class _OracleRunner:
         t_ff = time.perf_counter() - t0
         t0 = time.perf_counter()
         for j in (1, 2):
-            p = oracle.sampler.subset(grid.M, seed, j, COMP)
+            p = oracle.sampler.subset(grid.M, oracle.sampler.ORDER_KEY, j, COMP)
             V = self.forward(self.backward(w, th, p), p)
             w, th = oracle.update(w, V)
         t_sub = (time.perf_counter() - t0) / 2

@@ -19,12 +19,13 @@
  *   (eq. 3, read with the + sign and as a mean over the pixel set with
  *   uniform illumination), weight update (eqs. 4-6) and metrics (eq. 7)
  *   are as in the paper.
- * Random draws: theta_n^0 and the pixel subsets of the compressed
- *   iterations come from the 64-bit `seed` through Philox4x64-10 and a keyed
- *   six-round Feistel permutation of [0, W*H) (one random pixel order at
- *   start-up, as in the paper's compressed-sensing subsection; iteration j
- *   uses the window of m = ceil(c*W*H) consecutive entries starting at
- *   (j-1)*m, wrapping at W*H).
+ * Random draws: theta_n^0 comes from the 64-bit `seed` through
+ *   Philox4x64-10; the pixel subsets of the compressed iterations come from
+ *   one keyed six-round Feistel permutation of [0, W*H) per grid and pupil
+ *   (key HG_ORDER_KEY: one random pixel order of the SLM, as in the paper's
+ *   compressed-sensing subsection; iteration j uses the window of
+ *   m = ceil(c*W*H) consecutive entries starting at (j-1)*m, wrapping at
+ *   W*H).
  *
  * Ownership: the caller owns every buffer.  Host arrays are read during the
  *   call only.  Device buffers (`*_dev`) are caller allocations on the
@@ -55,6 +56,14 @@ extern "C" {
 
 #define HG_MAX_SPOTS 4096
 #define HG_MAX_ITERATIONS 100000
+/* Key of the random pixel order of the compressed iterations.  As in the
+ * paper's compressed-sensing subsection (one random order of the SLM's
+ * pixels, made at start-up), every hologram of one grid and pupil uses the
+ * same order: the algorithms key it with HG_ORDER_KEY, the library builds
+ * it once per device, grid and pupil on first use (that call blocks until
+ * it is complete) and keeps it until hg_release.  The hologram's seed
+ * draws theta^0 only.  hg_subset takes the key as an argument. */
+#define HG_ORDER_KEY 0ull
 
 typedef enum hg_status {
   HG_OK = 0,
@@ -356,9 +365,10 @@ hg_status hg_engine_destroy(hg_engine *engine);
 /* theta_n^0 (radians, FP64) for n < count, computed on the device.  Blocks. */
 hg_status hg_theta0(uint64_t seed, int32_t count, double *out_host);
 
-/* Pixel indices of Omega^j (j >= 1) for compression c: writes
- * m = ceil(c*|Omega|) int32 indices, in order, to idx_dev (capacity >= m)
- * and m to *m_out.  optics: NULL or its aperture_px alone is read (the
+/* Pixel indices of Omega^j (j >= 1) for compression c in the random order
+ * keyed by `seed` (the algorithms' order is the one of seed = HG_ORDER_KEY):
+ * writes m = ceil(c*|Omega|) int32 indices, in order, to idx_dev (capacity
+ * >= m) and m to *m_out.  optics: NULL or its aperture_px alone is read (the
  * random order runs over the pupil pixels; |Omega| = W*H without an
  * aperture).  Blocks until *m_out is set. */
 hg_status hg_subset(const hg_grid *grid, const hg_optics *optics, uint64_t seed,

@@ -19,7 +19,7 @@ Parity status of each function is stated in the module headers:
 """
 from .philox import philox4x64_10, PHILOX_M, PHILOX_W  # noqa: F401
 from .sampler import (  # noqa: F401
-    half_bits, round_tables, feistel, permute, subset_size, subset, theta0,
+    half_bits, round_tables, feistel, permute, subset_size, subset, theta0, ORDER_KEY,
 )
 from .hg import (  # noqa: F401
     pixel_offsets_mm, spot_phase, backward, forward, update, rs, wgs, cswgs,

@@ -173,8 +173,8 @@ def _iterate(grid, optics, spots, iterations: int, seed: int, c: Optional[float]
     compressed = c is not None
 
     def forward_set(j):  # pixel set of the forward sum of iteration j
-        if compressed and j < I:
-            return pupil[sampler.subset(pupil.shape[0], seed, j, c)]
+        if compressed and j < I:  # the SLM's one random order (made at start-up)
+            return pupil[sampler.subset(pupil.shape[0], sampler.ORDER_KEY, j, c)]
         return pupil  # Omega
 
     w = np.ones(spots.n)

@@ -22,6 +22,9 @@ one counter-based construction, defined here:
 * m = ceil(c * M) in FP64; the subset of iteration j (j >= 1) is
   Omega^j = [ pi(((j - 1) * m + q) mod M) for q in 0..m-1 ], in q order: a
   window sliding along the one fixed order, wrapping at M.
+* The order is made once, at start-up, for the SLM (its grid and pupil) and
+  serves every hologram: the algorithms key it with ORDER_KEY, not with the
+  hologram's seed, which draws theta^0 alone.
 
 Pins: bijectivity of pi by brute force, the partition of [0, M) by
 consecutive windows when m divides M, and uniformity of the subsets
@@ -37,6 +40,7 @@ import numpy as np
 from .philox import philox4x64_10
 
 FEISTEL_ROUNDS = 6
+ORDER_KEY = 0  # key of the one random pixel order that the algorithms use
 
 
 def theta0(seed: int, n: int) -> np.ndarray:

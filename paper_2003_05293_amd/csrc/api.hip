@@ -130,6 +130,7 @@ hg_status run_one(const hg_grid* g, const hg_optics* o, const hg_spots* s, int32
   HG_TRY(hg::make_spec(g, o, s, iterations, c, seed, flags, phi, trace_host, &spec));
   HG_TRY(hg::apply_lut(lut, gray, &spec));
   if (!phi) return set_error(HG_EINVAL, "phi_dev must be non-NULL");
+  HG_TRY(hg::attach_shared_order(&spec));
   Workspace* ws = nullptr;
   HG_TRY(get_workspace(stream, &ws));
   std::lock_guard<std::mutex> lk(ws->mu);
@@ -304,6 +305,7 @@ hg_status job_specs(int32_t count, const hg_job* jobs, const hg_tune* tune,
                          j.flags, j.phi_dev, j.trace_V, &(*out)[i]);
     if (st == HG_OK && !j.phi_dev) st = set_error(HG_EINVAL, "phi_dev must be non-NULL");
     if (st == HG_OK) st = hg::apply_lut(j.lut, j.gray_dev, &(*out)[i]);
+    if (st == HG_OK) st = hg::attach_shared_order(&(*out)[i]);
     if (st != HG_OK) return set_error(st, "job " + std::to_string(i) + ": " + hg::last_error());
   }
   return HG_OK;
@@ -507,6 +509,7 @@ hg_status hg_subset(const hg_grid* grid, const hg_optics* optics, uint64_t seed,
   const hg_optics o{1.0, 1.0, 0.0, optics ? optics->aperture_px : 0.0};
   hg::JobSpec spec;
   HG_TRY(hg::make_spec(grid, &o, &s, 2, compression, seed, 0, nullptr, nullptr, &spec));
+  spec.order_key = seed;
   Workspace* ws = nullptr;
   HG_TRY(get_workspace(stream, &ws));
   std::lock_guard<std::mutex> lk(ws->mu);
@@ -739,6 +742,7 @@ hg_status hg_release(void) {
   }
   g_ws.clear();
   if (have_cur) (void)hipSetDevice(cur);
+  hg::release_shared_orders();
   return HG_OK;
 }
 

@@ -97,7 +97,8 @@ hg_status spec_from_job(const hg_job& j, hg::JobSpec* out) {
   if (!j.phi_dev) return set_error(HG_EINVAL, "phi_dev must be non-NULL");
   HG_TRY(hg::make_spec(&j.grid, &j.optics, &j.spots, j.iterations, j.compression, j.seed,
                        j.flags, j.phi_dev, nullptr, out));
-  return hg::apply_lut(j.lut, j.gray_dev, out);
+  HG_TRY(hg::apply_lut(j.lut, j.gray_dev, out));
+  return hg::attach_shared_order(out);
 }
 
 }  // namespace
@@ -251,7 +252,7 @@ hg_status hg_engine_step(hg_engine* e, void* stream, int32_t* pending_out) {
   bool perm_lds = true;
   for (int si : fresh) {
     const hg::JobDev& j = e->slots[si].dev;
-    if (j.compressed) {
+    if (j.compressed && !j.order_shared) {
       perm.push_back(hg::JobSlice{perm_blocks, (int32_t)newjobs.size()});
       perm_blocks += hg::perm_blocks(j.P);
       max_h = std::max(max_h, j.h);

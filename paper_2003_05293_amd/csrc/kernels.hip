@@ -238,7 +238,9 @@ __device__ __forceinline__ int32_t pupil_pixel(const JobDev& jb, uint32_t r) {
 // w = 1; pass counters cleared.  Spot values that are not finite, or
 // amplitudes that are not positive, raise the argument status flag
 // (device-resident inputs cannot be checked on the host).  Blocks with
-// blockIdx.y > 0 fill the Feistel round tables of compressed jobs.
+// blockIdx.y > 0 fill the Feistel round tables of compressed jobs whose
+// order is their own (a job of N = 0 builds a shared order's tables and
+// pupil rows).
 __global__ __launch_bounds__(kSetupThreads) void k_setup_batch(const JobDev* __restrict__ jobs) {
   const JobDev& jb = jobs[blockIdx.x];
   if (blockIdx.y == 0) {
@@ -263,18 +265,19 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup_batch(const JobDev* __r
       jb.coef[n] = make_float2((float)(amp * cn), (float)(amp * sn));
     }
     for (int k = threadIdx.x; k < jb.counters_len; k += blockDim.x) jb.counters[k] = 0u;
-    if (jb.rows) pupil_rows(jb);
+    if (jb.rows && !jb.order_shared) pupil_rows(jb);
   }
   // the exact sums start at zero (every block of the job takes a share)
   for (int64_t k = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; k < jb.acc_len;
        k += (int64_t)gridDim.y * blockDim.x)
     jb.acc[k] = 0ull;
   if (blockIdx.y == 0) {
-  } else if (jb.compressed) {
+  } else if (jb.compressed && !jb.order_shared) {
     const int total = kFeistelRounds << jb.h;
     const int stride = (gridDim.y - 1) * blockDim.x;
     for (int k = (blockIdx.y - 1) * blockDim.x + threadIdx.x; k < total; k += stride)
-      jb.tab[k] = feistel_table_entry(jb.seed, k >> jb.h, (uint32_t)k & ((1u << jb.h) - 1u), jb.h);
+      jb.tab[k] = feistel_table_entry(jb.order_key, k >> jb.h, (uint32_t)k & ((1u << jb.h) - 1u),
+                                      jb.h);
   }
 }
 

@@ -120,7 +120,11 @@ struct JobDev {
   int32_t m;           // pixels of a compressed pass (M if not compressed)
   int32_t compressed;  // 1: passes 1..I-1 use windows of the random order
   int32_t h;           // Feistel half width (compressed only)
-  uint64_t seed;
+  uint64_t seed;       // theta^0
+  uint64_t order_key;  // key of the random order's Feistel tables
+  int32_t order_shared;  // tab, perm and rows belong to an order shared by
+                         // the holograms of this grid (built once): the
+                         // setup leaves them alone and no permutation runs
   double pitch_mm, lambda_mm, focal_mm;
   SpotPtrs in;         // spot inputs (device)
   SpotRec* sp;         // [N] iteration state

@@ -7,7 +7,9 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
+#include <tuple>
 
 namespace hg {
 
@@ -288,9 +290,117 @@ int half_bits(int64_t M) {
   return h;
 }
 
+bool job_compressed(const JobSpec& s) { return s.compression > 0.0 && s.iterations >= 2; }
+
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 }  // namespace
+
+// ---------------------------------------------------- shared random orders --
+
+namespace {
+struct OrderId {
+  int dev;
+  int32_t W, H, ap_q;
+  uint64_t key;
+  bool operator<(const OrderId& o) const {
+    return std::tie(dev, W, H, ap_q, key) < std::tie(o.dev, o.W, o.H, o.ap_q, o.key);
+  }
+};
+// Device memory of one order: [JobDev][JobSlice][tables][perm][rows].
+struct OrderEntry {
+  int dev = 0;
+  DevBuf<char> mem;
+  uint32_t* tab = nullptr;
+  int32_t* perm = nullptr;
+  int32_t* rows = nullptr;
+};
+std::mutex g_order_mu;
+std::map<OrderId, std::unique_ptr<OrderEntry>> g_orders;
+std::map<int, hipStream_t> g_order_streams;  // per device, default priority
+
+// Builds the order with the setup and permutation kernels of the jobs (a
+// job of no spots whose tables, pupil rows and permutation are the order's)
+// on the device's own stream, and waits for it.
+hg_status build_order(OrderEntry& e, const JobSpec& s, int dev) {
+  JobDev od = JobDev{};
+  od.W = s.W;
+  od.H = s.H;
+  od.M = s.W * s.H;
+  od.P = s.pupil_n > 0 ? s.pupil_n : od.M;
+  od.ap_q = s.ap_q;
+  od.compressed = 1;
+  od.h = half_bits(od.P);
+  od.order_key = s.order_key;
+  const size_t o_slice = align_up(sizeof(JobDev), 256);
+  const size_t o_tab = align_up(o_slice + sizeof(JobSlice), 256);
+  const size_t o_perm = align_up(o_tab + sizeof(uint32_t) * ((size_t)kFeistelRoundsHost << od.h), 256);
+  const size_t o_rows = align_up(o_perm + sizeof(int32_t) * (size_t)od.P, 256);
+  const size_t total = o_rows + (s.ap_q >= 0 ? sizeof(int32_t) * (2 * (size_t)s.H + 1) : 0);
+  HG_TRY(e.mem.reserve(total));
+  e.dev = dev;
+  e.tab = reinterpret_cast<uint32_t*>(e.mem.p + o_tab);
+  e.perm = reinterpret_cast<int32_t*>(e.mem.p + o_perm);
+  e.rows = s.ap_q >= 0 ? reinterpret_cast<int32_t*>(e.mem.p + o_rows) : nullptr;
+  od.tab = e.tab;
+  od.perm = e.perm;
+  od.rows = e.rows;
+  const JobSlice slice{0, 0};
+  HG_HIP(hipMemcpy(e.mem.p, &od, sizeof(JobDev), hipMemcpyHostToDevice));
+  HG_HIP(hipMemcpy(e.mem.p + o_slice, &slice, sizeof(JobSlice), hipMemcpyHostToDevice));
+  hipStream_t& st = g_order_streams[dev];
+  if (!st) HG_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  const JobDev* jd = reinterpret_cast<const JobDev*>(e.mem.p);
+  launch_setup_batch(jd, 1, od.h, st);
+  launch_perm_batch(jd, reinterpret_cast<const JobSlice*>(e.mem.p + o_slice), 1, perm_blocks(od.P),
+                    od.h <= 11, st);
+  const hipError_t le = hipGetLastError();
+  if (le != hipSuccess)
+    return set_error(HG_EDEVICE, std::string("kernel launch failed: ") + hipGetErrorString(le));
+  HG_HIP(hipStreamSynchronize(st));
+  return HG_OK;
+}
+}  // namespace
+
+hg_status attach_shared_order(JobSpec* s) {
+  if (!job_compressed(*s)) return HG_OK;
+  int dev = 0;
+  HG_HIP(hipGetDevice(&dev));
+  const OrderId id{dev, s->W, s->H, s->ap_q, s->order_key};
+  std::lock_guard<std::mutex> lk(g_order_mu);
+  auto it = g_orders.find(id);
+  if (it == g_orders.end()) {
+    auto e = std::make_unique<OrderEntry>();
+    const hg_status st = build_order(*e, *s, dev);
+    if (st != HG_OK) {
+      e->mem.release();
+      return st;
+    }
+    it = g_orders.emplace(id, std::move(e)).first;
+  }
+  s->shared_tab = it->second->tab;
+  s->shared_perm = it->second->perm;
+  s->shared_rows = it->second->rows;
+  return HG_OK;
+}
+
+void release_shared_orders() {
+  std::lock_guard<std::mutex> lk(g_order_mu);
+  int cur = 0;
+  const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+  for (auto& kv : g_orders) {
+    (void)hipSetDevice(kv.second->dev);
+    (void)hipDeviceSynchronize();
+    kv.second->mem.release();
+  }
+  g_orders.clear();
+  for (auto& kv : g_order_streams) {
+    (void)hipSetDevice(kv.first);
+    (void)hipStreamDestroy(kv.second);
+  }
+  g_order_streams.clear();
+  if (have_cur) (void)hipSetDevice(cur);
+}
 
 PixelSet all_pixels(int32_t M) {
   PixelSet ps;
@@ -315,11 +425,13 @@ JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev
   j.ap_q = s.ap_q;
   j.ill_a = (float)illumination_exponent(s.pitch_mm, s.waist_mm);
   j.iterations = s.iterations;
-  j.compressed = (s.compression > 0.0 && s.iterations >= 2) ? 1 : 0;
+  j.compressed = job_compressed(s) ? 1 : 0;
   // the random order runs over the pupil's P pixels
   j.m = j.compressed ? (int32_t)std::ceil(s.compression * (double)j.P) : j.P;
   j.h = j.compressed ? half_bits(j.P) : 0;
   j.seed = s.seed;
+  j.order_key = s.order_key;
+  j.order_shared = (j.compressed && s.shared_perm) ? 1 : 0;
   j.pitch_mm = s.pitch_mm;
   j.lambda_mm = s.lambda_mm;
   j.focal_mm = s.focal_mm;
@@ -386,9 +498,10 @@ JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev
   L.off_sp = take(sizeof(SpotRec) * (size_t)s.N);
   L.off_sp_alt = take(sizeof(SpotRec) * (size_t)s.N);
   L.off_coef = take(sizeof(float2) * (size_t)s.N);
-  L.off_tab = j.compressed ? take(sizeof(uint32_t) * ((size_t)kFeistelRoundsHost << j.h)) : 0;
-  L.off_perm = j.compressed ? take(sizeof(int32_t) * (size_t)j.P) : 0;
-  L.off_rows = (j.compressed && j.ap_q >= 0) ? take(sizeof(int32_t) * (2 * (size_t)j.H + 1)) : 0;
+  const bool own_order = j.compressed && !j.order_shared;
+  L.off_tab = own_order ? take(sizeof(uint32_t) * ((size_t)kFeistelRoundsHost << j.h)) : 0;
+  L.off_perm = own_order ? take(sizeof(int32_t) * (size_t)j.P) : 0;
+  L.off_rows = (own_order && j.ap_q >= 0) ? take(sizeof(int32_t) * (2 * (size_t)j.H + 1)) : 0;
   if (j.mixed) {
     const size_t ops = (size_t)j.mx_steps * 64;  // operand groups per 16-row/column block
     L.off_mxFc = take(16 * ops * j.mx_cblocks);
@@ -432,9 +545,15 @@ JobDev bind_job(const JobLayout& L, const JobSpec& s, char* base, const double* 
   // round, whose kernel applies deferred updates
   j.defer_ok = pass_units_per_wave(s.N) == 1 ? 1 : 0;
   j.coef = reinterpret_cast<float2*>(base + L.off_coef);
-  j.tab = j.compressed ? reinterpret_cast<uint32_t*>(base + L.off_tab) : nullptr;
-  j.perm = j.compressed ? reinterpret_cast<int32_t*>(base + L.off_perm) : nullptr;
-  j.rows = (j.compressed && j.ap_q >= 0) ? reinterpret_cast<int32_t*>(base + L.off_rows) : nullptr;
+  if (j.order_shared) {
+    j.tab = s.shared_tab;
+    j.perm = s.shared_perm;
+    j.rows = s.shared_rows;
+  } else {
+    j.tab = j.compressed ? reinterpret_cast<uint32_t*>(base + L.off_tab) : nullptr;
+    j.perm = j.compressed ? reinterpret_cast<int32_t*>(base + L.off_perm) : nullptr;
+    j.rows = (j.compressed && j.ap_q >= 0) ? reinterpret_cast<int32_t*>(base + L.off_rows) : nullptr;
+  }
   j.partial = j.mixed ? reinterpret_cast<float2*>(base + L.off_partial) : nullptr;
   j.gpart = j.mixed ? reinterpret_cast<double2*>(base + L.off_gpart) : nullptr;
   j.acc = (!j.mixed || j.compressed) ? reinterpret_cast<unsigned long long*>(base + L.off_acc)
@@ -711,7 +830,7 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
     bytes += layouts_[i].bytes;
     max_rounds = std::max(max_rounds, specs[i].iterations);
     const JobDev& j = layouts_[i].dev;
-    if (j.compressed) {
+    if (j.compressed && !j.order_shared) {
       max_h_ = std::max(max_h_, j.h);
       if (j.h > 11) perm_lds_ = false;
     }
@@ -736,7 +855,7 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
   for (int i = 0; i < count; ++i) {
     const JobDev& j = jobs_[i];
     if (j.phi) final_.add_final(j, layouts_[i], i);
-    if (j.compressed) {
+    if (j.compressed && !j.order_shared) {
       perm_.push_back(JobSlice{perm_blocks_, i});
       perm_blocks_ += perm_blocks(j.P);
     }

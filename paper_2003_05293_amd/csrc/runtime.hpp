@@ -100,7 +100,13 @@ struct JobSpec {
   bool spots_on_device = false;
   int32_t iterations = 0;
   double compression = -1.0;  // <= 0: plain WGS (no random order)
-  uint64_t seed = 0;
+  uint64_t seed = 0;                  // theta^0
+  uint64_t order_key = HG_ORDER_KEY;  // the random order (compressed jobs)
+  // the random order shared by every hologram of this grid and pupil on
+  // the device (attach_shared_order); null: the job builds its own
+  int32_t* shared_perm = nullptr;
+  uint32_t* shared_tab = nullptr;
+  int32_t* shared_rows = nullptr;
   uint32_t precision = HG_PREC_FP32;
   bool full_direct = false;   // full-grid passes with the per-pixel kernels
   bool hook = false;          // single-pass entry point (any pixel set up to W*H)
@@ -112,6 +118,13 @@ struct JobSpec {
   int32_t gray_bits = 0;
   void* gray = nullptr;
 };
+
+// The random pixel order of a compressed job's grid, pupil and order key,
+// shared by every hologram that has them on the current device: built on
+// first use (the call blocks until it is complete) and kept until
+// release_shared_orders.  Leaves jobs without a random order unchanged.
+hg_status attach_shared_order(JobSpec* s);
+void release_shared_orders();
 
 // Launch-geometry parameters (chosen per shape by the autotuner).
 struct TuneParams {

@@ -8,10 +8,11 @@ Two checks per run:
   (eqs. 1 and 3); the GPU's V^{j+1} must agree to 1e-5 of the mean spot
   magnitude (FP32 form; mixed: 1e-3, or 8 2^-11 sqrt(N / m) for a pass over
   m pixels when larger), the bar of one pass with the state held fixed.
-  The FP32 bar is that of the 1152^2, N = 100 pass (m = 82944), scaled by
-  sqrt(N / m) where that ratio is larger: V_n is a mean of m terms whose
-  FP32 phase rounding is independent from term to term, so its absolute
-  error falls as m^-1/2, while the mean spot magnitude falls as N^-1/2.
+  The FP32 bar is 1e-5, or 4 2 pi 2^-24 t_max sqrt(N / m) where larger
+  (t_max: the largest |phase| in turns of a term): V_n is a mean of m terms
+  whose FP32 phases carry independent roundings of a few 2^-24 |t| turns,
+  so its absolute error falls as m^-1/2, while the mean spot magnitude
+  falls as N^-1/2.
   The absolute error of a field does not depend on its magnitude, so it is
   taken against the mean, not spot by spot (the weakest of 200 spots can
   be a tenth of the mean).  A wrong update, a stale state or a wrong pixel
@@ -79,9 +80,20 @@ def rel_mag_spot(Vg, Vo):
     return np.abs(np.abs(Vg) - np.abs(Vo)) / np.abs(Vo)
 
 
-def step_bar(precision, N, m):
+def t_max(g, s):
+    """Largest |phase| in turns of any (pixel, spot) term, bounded term by
+    term at the grid's outermost pixel centres."""
+    xm = (g.W - 1) / 2 * g.pitch_mm
+    ym = (g.H - 1) / 2 * g.pitch_mm
+    lf = OPTICS.lambda_mm * OPTICS.focal_mm
+    t = (np.abs(s.x_mm) * xm + np.abs(s.y_mm) * ym) / lf \
+        + np.abs(s.z_mm) * (xm * xm + ym * ym) / (lf * OPTICS.focal_mm)
+    return float(t.max())
+
+
+def step_bar(precision, N, m, tmax):
     if precision == "fp32":
-        return BARS["fp32"][0] * max(1.0, math.sqrt((N / m) / (100 / 82944)))
+        return max(BARS["fp32"][0], 4 * 2 * math.pi * 2.0 ** -24 * tmax * math.sqrt(N / m))
     return max(BARS["mixed"][0], 8 * 2.0 ** -11 * math.sqrt(N / m))
 
 
@@ -93,7 +105,7 @@ def pixel_set(g, I, c, seed, j):
     """Pixels of the forward sum of iteration j (no pupil; c None is WGS,
     whose every iteration sums over all pixels)."""
     if c is not None and j < I:
-        return oracle.subset(g.M, seed, j, c)
+        return oracle.subset(g.M, oracle.ORDER_KEY, j, c)
     return np.arange(g.M, dtype=np.int64)
 
 
@@ -148,8 +160,9 @@ def test_every_iteration(W, H, N, I, c, seed, zh, precision):
     assert V.shape == (I, N)
     errs, sizes = one_step_errors(g, s, I, c, seed, V, range(1, I))
     print("one-step |V| err by iteration", {k: f"{v:.2e}" for k, v in sorted(errs.items())})
+    tm = t_max(g, s)
     for j, e in errs.items():
-        assert e <= step_bar(precision, N, sizes[j]), j
+        assert e <= step_bar(precision, N, sizes[j], tm), j
     tr = oracle.Trace()
     if c is None:
         oracle.wgs(g, OPTICS, s, I, seed, tr)

@@ -186,13 +186,14 @@ def pin_subsets_in_aperture():
         assert np.isin(sub, inside).all()
         seen.append(sub)
     assert np.array_equal(np.sort(np.concatenate(seen)), inside)
-    # the schedule's forward sums use exactly these sets
+    # the schedule's forward sums use exactly the windows of the SLM's one
+    # order (key ORDER_KEY), whatever the hologram's seed
     s = spot_cloud(2, 5, g)
     tr = oracle.Trace()
     oracle.cswgs(g, o, s, 3, c, 3, tr)
     w = np.ones(s.n)
     th = oracle.theta0(3, s.n)
-    p1 = inside[S.subset(K, 3, 1, c)]
+    p1 = inside[S.subset(K, S.ORDER_KEY, 1, c)]
     V1 = H.forward(g, o, s, H.backward(g, o, s, w, th, p1), p1)
     assert np.array_equal(V1, tr.V[0])
 
