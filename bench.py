@@ -65,8 +65,8 @@ ISSUE_T_PER_S = 256 * 2.4e9 * 128 / 1e12
 SLOTS_PER_PAIR = 12 + 2 + 4 * 4
 PEAK_ISSUE_TFLOPS = round(ISSUE_T_PER_S / SLOTS_PER_PAIR * (FLOPS_BACK + FLOPS_FWD), 1)
 # Launch tags of the library's kernel timing (hg_timing_read).
-KERNELS = ("k_setup", "k_perm", "k_sep_tables", "k_sep_pass", "k_sep_final", "k_pass_subset",
-           "k_pass_full", "k_pass_mixed", "k_backprop_phi", "k_mx_tables", "k_mxp_subset",
+KERNELS = ("k_prologue", "k_perm", "k_sep_pass", "k_sep_final", "k_pass_subset",
+           "k_pass_full", "k_pass_mixed", "k_backprop_phi", "k_mxp_subset",
            "k_mx_full", "k_mx_final")
 
 

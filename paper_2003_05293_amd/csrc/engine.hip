@@ -241,31 +241,27 @@ hg_status hg_engine_step(hg_engine* e, void* stream, int32_t* pending_out) {
     fresh.push_back(free_slot);
   }
 
-  // step payload: [slot table][new jobs][perm slices][mx table slices][sep table slices]
+  // step payload: [slot table][new jobs][perm slices][prologue slices]
   // [iteration][final][spots]
   std::vector<hg::JobDev> table(e->max_slots, hg::JobDev{});
   for (int si = 0; si < e->max_slots; ++si)
     if (e->slots[si].used) table[si] = e->slots[si].dev;
   std::vector<hg::JobDev> newjobs;
-  std::vector<hg::JobSlice> perm, mxtab, septab;
-  int perm_blocks = 0, mxtab_blocks = 0, septab_blocks = 0, max_h = 0;
+  std::vector<hg::JobSlice> perm;
+  std::vector<hg::PrologueSlice> pro;
+  int perm_blocks = 0, pro_blocks = 0;
   bool perm_lds = true;
   for (int si : fresh) {
     const hg::JobDev& j = e->slots[si].dev;
     if (j.compressed && !j.order_shared) {
       perm.push_back(hg::JobSlice{perm_blocks, (int32_t)newjobs.size()});
       perm_blocks += hg::perm_blocks(j.P);
-      max_h = std::max(max_h, j.h);
       if (j.h > 11) perm_lds = false;
     }
-    if (j.mixed) {
-      mxtab.push_back(hg::JobSlice{mxtab_blocks, (int32_t)newjobs.size()});
-      mxtab_blocks += hg::mx_table_blocks(j);
-    }
-    if (e->slots[si].layout.separable) {
-      septab.push_back(hg::JobSlice{septab_blocks, (int32_t)newjobs.size()});
-      septab_blocks += hg::sep_table_blocks(j);
-    }
+    const hg::PrologueSlice ps{pro_blocks, (int32_t)newjobs.size(), hg::prologue_setup_blocks(j),
+                               hg::prologue_table_blocks(j)};
+    pro.push_back(ps);
+    pro_blocks += ps.setup_blocks + ps.table_blocks;
     newjobs.push_back(j);
   }
   hg::LaunchSet iter, fin;
@@ -292,10 +288,8 @@ hg_status hg_engine_step(hg_engine* e, void* stream, int32_t* pending_out) {
   o = align(o + sizeof(hg::JobDev) * newjobs.size());
   const size_t o_perm = o;
   o = align(o + sizeof(hg::JobSlice) * perm.size());
-  const size_t o_mxtab = o;
-  o = align(o + sizeof(hg::JobSlice) * mxtab.size());
-  const size_t o_septab = o;
-  o = align(o + sizeof(hg::JobSlice) * septab.size());
+  const size_t o_pro = o;
+  o = align(o + sizeof(hg::PrologueSlice) * pro.size());
   const size_t o_iter = o;
   o += iter.bytes();
   const size_t o_fin = o;
@@ -311,9 +305,7 @@ hg_status hg_engine_step(hg_engine* e, void* stream, int32_t* pending_out) {
   std::memcpy(st + o_table, table.data(), sizeof(hg::JobDev) * table.size());
   if (!newjobs.empty()) std::memcpy(st + o_new, newjobs.data(), sizeof(hg::JobDev) * newjobs.size());
   if (!perm.empty()) std::memcpy(st + o_perm, perm.data(), sizeof(hg::JobSlice) * perm.size());
-  if (!mxtab.empty()) std::memcpy(st + o_mxtab, mxtab.data(), sizeof(hg::JobSlice) * mxtab.size());
-  if (!septab.empty())
-    std::memcpy(st + o_septab, septab.data(), sizeof(hg::JobSlice) * septab.size());
+  if (!pro.empty()) std::memcpy(st + o_pro, pro.data(), sizeof(hg::PrologueSlice) * pro.size());
   iter.stage(st + o_iter, e->step_buf.p + o_iter);
   fin.stage(st + o_fin, e->step_buf.p + o_fin);
   HG_HIP(hipMemcpyAsync(e->step_buf.p, st, table_bytes, hipMemcpyHostToDevice, s));
@@ -331,22 +323,14 @@ hg_status hg_engine_step(hg_engine* e, void* stream, int32_t* pending_out) {
   const hg::JobDev* slots_dev = reinterpret_cast<const hg::JobDev*>(e->step_buf.p + o_table);
   if (!newjobs.empty()) {
     const hg::JobDev* new_dev = reinterpret_cast<const hg::JobDev*>(e->step_buf.p + o_new);
-    hg::timed(s, "k_setup", [&] { hg::launch_setup_batch(new_dev, (int)newjobs.size(), max_h, s); });
+    hg::timed(s, "k_prologue", [&] {
+      hg::launch_prologue(new_dev, reinterpret_cast<const hg::PrologueSlice*>(e->step_buf.p + o_pro),
+                          (int)pro.size(), pro_blocks, s);
+    });
     if (perm_blocks)
       hg::timed(s, "k_perm", [&] {
         hg::launch_perm_batch(new_dev, reinterpret_cast<const hg::JobSlice*>(e->step_buf.p + o_perm),
                               (int)perm.size(), perm_blocks, perm_lds, s);
-      });
-    if (mxtab_blocks)
-      hg::timed(s, "k_mx_tables", [&] {
-        hg::launch_mx_tables(new_dev, reinterpret_cast<const hg::JobSlice*>(e->step_buf.p + o_mxtab),
-                             (int)mxtab.size(), mxtab_blocks, s);
-      });
-    if (septab_blocks)
-      hg::timed(s, "k_sep_tables", [&] {
-        hg::launch_sep_tables(new_dev,
-                              reinterpret_cast<const hg::JobSlice*>(e->step_buf.p + o_septab),
-                              (int)septab.size(), septab_blocks, s);
       });
   }
   iter.launch(slots_dev, s, false);

@@ -13,6 +13,7 @@
 #include "device_common.hpp"
 #include "device_math.hpp"
 #include "kernels.hpp"
+#include "operand_layout.hpp"
 #include "pass_tail.hpp"
 
 namespace hg {
@@ -237,13 +238,12 @@ __device__ __forceinline__ int32_t pupil_pixel(const JobDev& jb, uint32_t r) {
 // Spot coefficients in FP64, rounded once to FP32; theta^0 from Philox;
 // w = 1; pass counters cleared.  Spot values that are not finite, or
 // amplitudes that are not positive, raise the argument status flag
-// (device-resident inputs cannot be checked on the host).  Blocks with
-// blockIdx.y > 0 fill the Feistel round tables of compressed jobs whose
-// order is their own (a job of N = 0 builds a shared order's tables and
-// pupil rows).
-__global__ __launch_bounds__(kSetupThreads) void k_setup_batch(const JobDev* __restrict__ jobs) {
-  const JobDev& jb = jobs[blockIdx.x];
-  if (blockIdx.y == 0) {
+// (device-resident inputs cannot be checked on the host).  The job's
+// setup blocks after the first fill the Feistel round tables of a
+// compressed job whose order is its own (a job of N = 0 builds a shared
+// order's tables and pupil rows); all of them clear the exact sums.
+__device__ void setup_part(const JobDev& jb, int lb, int nb) {
+  if (lb == 0) {
     const double lf = jb.lambda_mm * jb.focal_mm;
     const double lf2 = lf * jb.focal_mm;
     for (int n = threadIdx.x; n < jb.N; n += blockDim.x) {
@@ -268,17 +268,140 @@ __global__ __launch_bounds__(kSetupThreads) void k_setup_batch(const JobDev* __r
     if (jb.rows && !jb.order_shared) pupil_rows(jb);
   }
   // the exact sums start at zero (every block of the job takes a share)
-  for (int64_t k = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; k < jb.acc_len;
-       k += (int64_t)gridDim.y * blockDim.x)
+  for (int64_t k = (int64_t)lb * blockDim.x + threadIdx.x; k < jb.acc_len;
+       k += (int64_t)nb * blockDim.x)
     jb.acc[k] = 0ull;
-  if (blockIdx.y == 0) {
-  } else if (jb.compressed && !jb.order_shared) {
+  if (lb > 0 && jb.compressed && !jb.order_shared) {
     const int total = kFeistelRounds << jb.h;
-    const int stride = (gridDim.y - 1) * blockDim.x;
-    for (int k = (blockIdx.y - 1) * blockDim.x + threadIdx.x; k < total; k += stride)
+    const int stride = (nb - 1) * blockDim.x;
+    for (int k = (lb - 1) * blockDim.x + threadIdx.x; k < total; k += stride)
       jb.tab[k] = feistel_table_entry(jb.order_key, k >> jb.h, (uint32_t)k & ((1u << jb.h) - 1u),
                                       jb.h);
   }
+}
+
+// ------------------------------------------------- factor tables ---
+
+// Factor tables from FP64 phases (zero outside the grid and beyond N):
+//   Fc  back-propagation B operand: part of F_n(col), col 16 cb + l%16,
+//       spot n = 2 s + g/2 of K-step s;
+//   Ga  G_n(row) for row 16 rb + l%16, spot 2 s + g/2 (forms the A operand);
+//   Fn  forward B operand: part of F_n(col), spot 16 sb + l%16, column
+//       2 cp + g/2 of column pair cp;
+//   Gv  G_n(row) for spot 16 sb + l%16 and rows 16 rb + 4 g + r (V sums).
+__device__ void sep_tables_part(const JobDev& jb, int lb, int nb) {
+  const int W = jb.W, H = jb.H, N = jb.N;
+  const int S16 = jb.mx_steps, Np = 16 * S16, KS = Np / 2;
+  const int CB = jb.mx_cblocks, RB = jb.mx_rblocks, CP = 8 * CB;
+  const int64_t nF = (int64_t)(16 * CB) * Np, total = nF + (int64_t)(16 * RB) * Np;
+  const double lf = jb.lambda_mm * jb.focal_mm;
+  const double lf2 = lf * jb.focal_mm;
+  const double kxy = jb.pitch_mm / (2.0 * lf), kz = jb.pitch_mm * jb.pitch_mm / (4.0 * lf2);
+  for (int64_t k = (int64_t)lb * kSetupThreads + threadIdx.x; k < total; k += (int64_t)nb * kSetupThreads) {
+    if (k < nF) {
+      const int col = (int)(k / Np), n = (int)(k % Np);
+      float fr = 0.f, fi = 0.f;
+      if (col < W && n < N) {
+        const double L = (double)(2 * col - (W - 1));
+        double t = jb.in.x[n] * kxy * L + jb.in.z[n] * kz * L * L;
+        t -= rint(t);
+        double s, c;
+        sincospi(2.0 * t, &s, &c);
+        fr = (float)c;
+        fi = (float)s;
+      }
+      const int lgc = (n & 1) << 1, lgn = (col & 1) << 1;
+      for (int p = 0; p < 2; ++p) {
+        const float v = p ? fi : fr;
+        jb.sepFc[op_index(col >> 4, n >> 1, KS, (col & 15) + 16 * (lgc + p))] = v;
+        jb.sepFn[op_index(n >> 4, col >> 1, CP, (n & 15) + 16 * (lgn + p))] = v;
+      }
+    } else {
+      const int64_t kk = k - nF;
+      const int row = (int)(kk / Np), n = (int)(kk % Np);
+      float2 g = make_float2(0.f, 0.f);
+      if (row < H && n < N) {
+        const double L = (double)(2 * row - (H - 1));
+        double t = jb.in.y[n] * kxy * L + jb.in.z[n] * kz * L * L;
+        t -= rint(t);
+        double s, c;
+        sincospi(2.0 * t, &s, &c);
+        g = make_float2((float)c, (float)s);
+      }
+      const int lga = (n & 1) << 1;
+      for (int p = 0; p < 2; ++p)
+        jb.sepGa[op_index(row >> 4, n >> 1, KS, (row & 15) + 16 * (lga + p))] = g;
+      float2* Gv = reinterpret_cast<float2*>(jb.sepGv);
+      Gv[op_index(row >> 4, n >> 4, S16, (n & 15) + 16 * ((row & 15) >> 2)) * 4 + (row & 3)] = g;
+    }
+  }
+}
+
+// Factor tables from FP64 phases:
+//   Fc: back-propagation B operand, column 16 cb + l % 16, spots of step s;
+//   Fn: forward B operand, spot 16 sb + l % 16, columns 16 cb + 4 (l / 16) + q;
+//   Ga: G_n(j) for row 16 rb + l % 16, spots of step s (forms the A operand);
+//   Gv: G_n(j) for spot 16 sb + l % 16, rows 16 rb + 4 (l / 16) + r (V sums).
+// Entries outside the grid or beyond N are zero.
+__device__ void mx_tables_part(const JobDev& jb, int lb, int nb) {
+  const int W = jb.W, H = jb.H, N = jb.N;
+  const int S16 = jb.mx_steps, Np = 16 * S16, CB = jb.mx_cblocks, RB = jb.mx_rblocks;
+  const int64_t nF = (int64_t)(16 * CB) * Np, total = nF + (int64_t)(16 * RB) * Np;
+  const double lf = jb.lambda_mm * jb.focal_mm;
+  const double lf2 = lf * jb.focal_mm;
+  const double kxy = jb.pitch_mm / (2.0 * lf), kz = jb.pitch_mm * jb.pitch_mm / (4.0 * lf2);
+  uint32_t* Fc = reinterpret_cast<uint32_t*>(jb.mxFc);
+  uint32_t* Fn = reinterpret_cast<uint32_t*>(jb.mxFn);
+  float2* Ga = reinterpret_cast<float2*>(jb.mxGa);
+  float2* Gv = reinterpret_cast<float2*>(jb.mxGv);
+  for (int64_t k = (int64_t)lb * kSetupThreads + threadIdx.x; k < total; k += (int64_t)nb * kSetupThreads) {
+    if (k < nF) {
+      const int col = (int)(k / Np), n = (int)(k % Np);
+      uint32_t v = 0u;
+      if (col < W && n < N) {
+        const double L = (double)(2 * col - (W - 1));
+        double t = jb.in.x[n] * kxy * L + jb.in.z[n] * kz * L * L;
+        t -= rint(t);
+        double s, c;
+        sincospi(2.0 * t, &s, &c);
+        v = h2_bits((float)c, (float)s);
+      }
+      const int cb = col >> 4, cl = col & 15, s = n >> 4, nl = n & 15;
+      Fc[fc_index(cb, s, S16, cl + 16 * (nl >> 2)) * 4 + (nl & 3)] = v;
+      Fn[fn_index(s, cb, CB, nl + 16 * (cl >> 2)) * 4 + (cl & 3)] = v;
+    } else {
+      const int64_t kk = k - nF;
+      const int row = (int)(kk / Np), n = (int)(kk % Np);
+      float2 g = make_float2(0.f, 0.f);
+      if (row < H && n < N) {
+        const double L = (double)(2 * row - (H - 1));
+        double t = jb.in.y[n] * kxy * L + jb.in.z[n] * kz * L * L;
+        t -= rint(t);
+        double s, c;
+        sincospi(2.0 * t, &s, &c);
+        g = make_float2((float)c, (float)s);
+      }
+      const int rb = row >> 4, rl = row & 15, s = n >> 4, nl = n & 15;
+      Ga[g_index(rb, s, S16, rl + 16 * (nl >> 2)) * 4 + (nl & 3)] = g;
+      Gv[g_index(rb, s, S16, nl + 16 * (rl >> 2)) * 4 + (rl & 3)] = g;
+    }
+  }
+}
+
+// The prologue of every job of a launch (PrologueSlice): its setup blocks,
+// then the blocks that build the factor tables of its full-grid passes
+// (separable FP32 or mixed precision).  The tables depend on the spot
+// inputs alone, so both run in one launch.
+__global__ __launch_bounds__(kSetupThreads) void k_prologue(const JobDev* __restrict__ jobs,
+                                                           const PrologueSlice* __restrict__ slices,
+                                                           int nslices) {
+  const int si = find_desc(slices, nslices, blockIdx.x);
+  const PrologueSlice& sl = slices[si];
+  const JobDev& jb = jobs[sl.job];
+  const int lb = blockIdx.x - sl.block_begin;
+  if (lb < sl.setup_blocks) setup_part(jb, lb, sl.setup_blocks);
+  else if (jb.mixed) mx_tables_part(jb, lb - sl.setup_blocks, sl.table_blocks);
+  else sep_tables_part(jb, lb - sl.setup_blocks, sl.table_blocks);
 }
 
 // pi(k) for every k < P of each compressed job.  With an
@@ -1171,17 +1294,24 @@ PassPlan plan_pass(int32_t count, int32_t block_cap) {
   return p;
 }
 
-int setup_table_blocks(int max_h) {
-  if (max_h <= 0) return 0;
-  const int total = kFeistelRounds << max_h;
-  int b = ceil_div(total, 256 * 4);
-  return b > 64 ? 64 : b;
+int prologue_setup_blocks(const JobDev& j) {
+  if (!j.compressed || j.order_shared) return 1;
+  const int total = kFeistelRounds << j.h;
+  const int b = ceil_div(total, 256 * 4);
+  return 1 + (b > 64 ? 64 : b);
 }
 
-void launch_setup_batch(const JobDev* jobs, int njobs, int max_h, hipStream_t s) {
-  if (njobs <= 0) return;
-  hipLaunchKernelGGL(k_setup_batch, dim3(njobs, 1 + setup_table_blocks(max_h)), dim3(kSetupThreads), 0, s,
-                     jobs);
+int prologue_table_blocks(const JobDev& j) {
+  if (!j.sepFc && !j.mxFc) return 0;  // no matrix-core passes
+  const int64_t total = (int64_t)16 * (j.mx_cblocks + j.mx_rblocks) * 16 * j.mx_steps;
+  return ceil_div(total, kSetupThreads);
+}
+
+void launch_prologue(const JobDev* jobs, const PrologueSlice* slices, int nslices,
+                     int total_blocks, hipStream_t s) {
+  if (nslices <= 0 || total_blocks <= 0) return;
+  hipLaunchKernelGGL(k_prologue, dim3(total_blocks), dim3(kSetupThreads), 0, s, jobs, slices,
+                     nslices);
 }
 
 int perm_blocks(int32_t M) { return ceil_div(M, (int64_t)kPermThreads * kPermPerThread); }

@@ -228,17 +228,28 @@ struct BackDesc {
   float* out;
 };
 
-// One job's share of a batched setup / permutation launch.
+// One job's share of a batched permutation launch.
 struct JobSlice {
   int32_t block_begin;
   int32_t job;
 };
 
-// ---- setup (FP64) ----
-// Spot records, theta^0, state and pass counters of every job, plus the
-// Feistel tables of the compressed jobs; grid = njobs x (1 + table blocks).
-int setup_table_blocks(int max_h);
-void launch_setup_batch(const JobDev* jobs, int njobs, int max_h, hipStream_t s);
+// ---- prologue (FP64) ----
+// One job's share of a prologue launch: blocks [block_begin, block_begin +
+// setup_blocks) set up its spot records, theta^0, state, counters and exact
+// sums (and the Feistel tables of a random order of its own); the next
+// table_blocks build the factor tables of its full-grid passes (separable
+// FP32 or mixed precision), which depend on the spot inputs alone.
+struct PrologueSlice {
+  int32_t block_begin;
+  int32_t job;
+  int32_t setup_blocks;
+  int32_t table_blocks;
+};
+int prologue_setup_blocks(const JobDev& j);
+int prologue_table_blocks(const JobDev& j);  // 0 without matrix-core passes
+void launch_prologue(const JobDev* jobs, const PrologueSlice* slices, int nslices,
+                     int total_blocks, hipStream_t s);
 // Random pixel order of the compressed jobs; slices[] maps blocks to jobs.
 int perm_blocks(int32_t M);
 void launch_perm_batch(const JobDev* jobs, const JobSlice* slices, int nslices, int total_blocks,
@@ -301,11 +312,9 @@ struct SepDesc {
   double2* V;
   float* out;           // final-phase variant: Phi output
 };
-// Factor tables of each listed job from its spot inputs (FP64 phases; they
-// do not change during the iterations).
-int sep_table_blocks(const JobDev& j);
-void launch_sep_tables(const JobDev* jobs, const JobSlice* slices, int nslices, int total_blocks,
-                       hipStream_t s);
+// (The factor tables are built by the prologue from FP64 phases: the spots
+// do not move during the iterations.)
+
 PassPlan plan_sep(int W, int H);
 // Fused full-grid pass (back-propagation S = B F and forward T = U conj(F)^T
 // on the FP32 matrix cores, exact sums, update) or, with final != 0, the
@@ -336,11 +345,8 @@ struct MxDesc {
   float* out;           // final hologram (kMxFinal)
 };
 PassPlan plan_mx(int W, int H);
-// FP16 / FP32 tables from FP64 phases (spot inputs only: they do not change
-// during the iterations).
-int mx_table_blocks(const JobDev& j);
-void launch_mx_tables(const JobDev* jobs, const JobSlice* slices, int nslices, int total_blocks,
-                      hipStream_t s);
+// (FP16 / FP32 tables built by the prologue from FP64 phases.)
+
 // mode: MxMode; max_steps: largest Np / 16 among the descriptors.
 void launch_mx_pass(const JobDev* jobs, const MxDesc* descs, int ndesc, int total_blocks,
                     int mode, int max_steps, hipStream_t s);

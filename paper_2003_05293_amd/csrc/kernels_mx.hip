@@ -20,6 +20,7 @@
 #include "device_common.hpp"
 #include "device_math.hpp"
 #include "kernels.hpp"
+#include "operand_layout.hpp"
 
 namespace hg {
 
@@ -31,10 +32,7 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
 
 // (lo, hi) rounded to nearest FP16, packed into one dword.
-__device__ __forceinline__ uint32_t pack_h2(float lo, float hi) {
-  const h2_t v = {(_Float16)lo, (_Float16)hi};
-  return __builtin_bit_cast(uint32_t, v);
-}
+__device__ __forceinline__ uint32_t pack_h2(float lo, float hi) { return h2_bits(lo, hi); }
 
 __device__ __forceinline__ f4_t mfma16(const u4_t& a, const u4_t& b, const f4_t& c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8_t, a),
@@ -46,81 +44,6 @@ __device__ __forceinline__ uint32_t times_minus_i(uint32_t v) {
   return ((v >> 16) | (v << 16)) ^ 0x80000000u;
 }
 
-// Operand layouts of v_mfma_f32_16x16x32_f16 (lane l, e < 8, r < 4):
-//   A[l % 16][8 (l / 16) + e],  B[8 (l / 16) + e][l % 16],  D[4 (l / 16) + r][l % 16].
-// With K = 2 Np interleaved (k = 2 n + part), lane l of K-step s covers
-// spots 16 s + 4 (l / 16) + q, q < 4, as four (re, im) half pairs.  The
-// tables below hold, for each 16-row (or 16-column) block and K-step, the 64
-// lanes' operands contiguously, so every operand load is one coalesced
-// 16-byte (FP16) or 32-byte (FP32) access per lane.
-
-// Entries in table units (64-lane operand groups) of a job.
-__device__ __forceinline__ int64_t fc_index(int cb, int s, int S16, int lane) {
-  return ((int64_t)cb * S16 + s) * 64 + lane;
-}
-__device__ __forceinline__ int64_t fn_index(int sb, int cb, int CB, int lane) {
-  return ((int64_t)sb * CB + cb) * 64 + lane;
-}
-__device__ __forceinline__ int64_t g_index(int rb, int s, int S16, int lane) {
-  return ((int64_t)rb * S16 + s) * 64 + lane;
-}
-
-// Factor tables from FP64 phases:
-//   Fc: back-propagation B operand, column 16 cb + l % 16, spots of step s;
-//   Fn: forward B operand, spot 16 sb + l % 16, columns 16 cb + 4 (l / 16) + q;
-//   Ga: G_n(j) for row 16 rb + l % 16, spots of step s (forms the A operand);
-//   Gv: G_n(j) for spot 16 sb + l % 16, rows 16 rb + 4 (l / 16) + r (V sums).
-// Entries outside the grid or beyond N are zero.
-__global__ __launch_bounds__(256) void k_mx_tables(const JobDev* __restrict__ jobs,
-                                                   const JobSlice* __restrict__ slices,
-                                                   int nslices) {
-  const int si = find_desc(slices, nslices, blockIdx.x);
-  const JobDev& jb = jobs[slices[si].job];
-  const int lb = blockIdx.x - slices[si].block_begin;
-  const int W = jb.W, H = jb.H, N = jb.N;
-  const int S16 = jb.mx_steps, Np = 16 * S16, CB = jb.mx_cblocks, RB = jb.mx_rblocks;
-  const int64_t nF = (int64_t)(16 * CB) * Np, total = nF + (int64_t)(16 * RB) * Np;
-  const int nb = ceil_div(total, 256);
-  const double lf = jb.lambda_mm * jb.focal_mm;
-  const double lf2 = lf * jb.focal_mm;
-  const double kxy = jb.pitch_mm / (2.0 * lf), kz = jb.pitch_mm * jb.pitch_mm / (4.0 * lf2);
-  uint32_t* Fc = reinterpret_cast<uint32_t*>(jb.mxFc);
-  uint32_t* Fn = reinterpret_cast<uint32_t*>(jb.mxFn);
-  float2* Ga = reinterpret_cast<float2*>(jb.mxGa);
-  float2* Gv = reinterpret_cast<float2*>(jb.mxGv);
-  for (int64_t k = (int64_t)lb * 256 + threadIdx.x; k < total; k += (int64_t)nb * 256) {
-    if (k < nF) {
-      const int col = (int)(k / Np), n = (int)(k % Np);
-      uint32_t v = 0u;
-      if (col < W && n < N) {
-        const double L = (double)(2 * col - (W - 1));
-        double t = jb.in.x[n] * kxy * L + jb.in.z[n] * kz * L * L;
-        t -= rint(t);
-        double s, c;
-        sincospi(2.0 * t, &s, &c);
-        v = pack_h2((float)c, (float)s);
-      }
-      const int cb = col >> 4, cl = col & 15, s = n >> 4, nl = n & 15;
-      Fc[fc_index(cb, s, S16, cl + 16 * (nl >> 2)) * 4 + (nl & 3)] = v;
-      Fn[fn_index(s, cb, CB, nl + 16 * (cl >> 2)) * 4 + (cl & 3)] = v;
-    } else {
-      const int64_t kk = k - nF;
-      const int row = (int)(kk / Np), n = (int)(kk % Np);
-      float2 g = make_float2(0.f, 0.f);
-      if (row < H && n < N) {
-        const double L = (double)(2 * row - (H - 1));
-        double t = jb.in.y[n] * kxy * L + jb.in.z[n] * kz * L * L;
-        t -= rint(t);
-        double s, c;
-        sincospi(2.0 * t, &s, &c);
-        g = make_float2((float)c, (float)s);
-      }
-      const int rb = row >> 4, rl = row & 15, s = n >> 4, nl = n & 15;
-      Ga[g_index(rb, s, S16, rl + 16 * (nl >> 2)) * 4 + (nl & 3)] = g;
-      Gv[g_index(rb, s, S16, nl + 16 * (rl >> 2)) * 4 + (rl & 3)] = g;
-    }
-  }
-}
 
 // Compensated (Neumaier) FP32 accumulation: the sum is s + c.
 __device__ __forceinline__ void ksum(float& s, float& c, float x) {
@@ -508,17 +431,6 @@ PassPlan plan_mx(int W, int H) {
   p.group_size = gs;
   p.ngroups = ceil_div(p.blocks, gs);
   return p;
-}
-
-int mx_table_blocks(const JobDev& j) {
-  const int64_t total = (int64_t)16 * (j.mx_cblocks + j.mx_rblocks) * 16 * j.mx_steps;
-  return ceil_div(total, 256);
-}
-
-void launch_mx_tables(const JobDev* jobs, const JobSlice* slices, int nslices, int total_blocks,
-                      hipStream_t s) {
-  if (nslices <= 0 || total_blocks <= 0) return;
-  hipLaunchKernelGGL(k_mx_tables, dim3(total_blocks), dim3(256), 0, s, jobs, slices, nslices);
 }
 
 void launch_mx_pass(const JobDev* jobs, const MxDesc* descs, int ndesc, int total_blocks,

@@ -15,6 +15,7 @@
 
 #include "device_common.hpp"
 #include "kernels.hpp"
+#include "operand_layout.hpp"
 #include "pass_tail.hpp"
 
 namespace hg {
@@ -23,80 +24,11 @@ namespace {
 
 typedef float f4_t __attribute__((ext_vector_type(4)));
 
-// Operand layouts of v_mfma_f32_16x16x4_f32 (lane l, r < 4):
-//   A[l % 16][l / 16],  B[l / 16][l % 16],  D[4 (l / 16) + r][l % 16].
-// K-step s of a spot contraction covers spots 2s and 2s + 1; lane group
-// g = l / 16 holds part g % 2 (0 real, 1 imaginary) of spot 2 s + g / 2.
-// The tables hold, per 16-column (or 16-row) block and K-step, the 64
-// lanes' operands contiguously: one coalesced load per operand.
 __device__ __forceinline__ f4_t mfma4(float a, float b, const f4_t& c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ int64_t op_index(int blk, int step, int steps, int lane) {
-  return ((int64_t)blk * steps + step) * 64 + lane;
-}
 
-// Factor tables from FP64 phases (zero outside the grid and beyond N):
-//   Fc  back-propagation B operand: part of F_n(col), col 16 cb + l%16,
-//       spot n = 2 s + g/2 of K-step s;
-//   Ga  G_n(row) for row 16 rb + l%16, spot 2 s + g/2 (forms the A operand);
-//   Fn  forward B operand: part of F_n(col), spot 16 sb + l%16, column
-//       2 cp + g/2 of column pair cp;
-//   Gv  G_n(row) for spot 16 sb + l%16 and rows 16 rb + 4 g + r (V sums).
-__global__ __launch_bounds__(256) void k_sep_tables(const JobDev* __restrict__ jobs,
-                                                    const JobSlice* __restrict__ slices,
-                                                    int nslices) {
-  const int si = find_desc(slices, nslices, blockIdx.x);
-  const JobDev& jb = jobs[slices[si].job];
-  const int lb = blockIdx.x - slices[si].block_begin;
-  const int W = jb.W, H = jb.H, N = jb.N;
-  const int S16 = jb.mx_steps, Np = 16 * S16, KS = Np / 2;
-  const int CB = jb.mx_cblocks, RB = jb.mx_rblocks, CP = 8 * CB;
-  const int64_t nF = (int64_t)(16 * CB) * Np, total = nF + (int64_t)(16 * RB) * Np;
-  const int nb = ceil_div(total, 256);
-  const double lf = jb.lambda_mm * jb.focal_mm;
-  const double lf2 = lf * jb.focal_mm;
-  const double kxy = jb.pitch_mm / (2.0 * lf), kz = jb.pitch_mm * jb.pitch_mm / (4.0 * lf2);
-  for (int64_t k = (int64_t)lb * 256 + threadIdx.x; k < total; k += (int64_t)nb * 256) {
-    if (k < nF) {
-      const int col = (int)(k / Np), n = (int)(k % Np);
-      float fr = 0.f, fi = 0.f;
-      if (col < W && n < N) {
-        const double L = (double)(2 * col - (W - 1));
-        double t = jb.in.x[n] * kxy * L + jb.in.z[n] * kz * L * L;
-        t -= rint(t);
-        double s, c;
-        sincospi(2.0 * t, &s, &c);
-        fr = (float)c;
-        fi = (float)s;
-      }
-      const int lgc = (n & 1) << 1, lgn = (col & 1) << 1;
-      for (int p = 0; p < 2; ++p) {
-        const float v = p ? fi : fr;
-        jb.sepFc[op_index(col >> 4, n >> 1, KS, (col & 15) + 16 * (lgc + p))] = v;
-        jb.sepFn[op_index(n >> 4, col >> 1, CP, (n & 15) + 16 * (lgn + p))] = v;
-      }
-    } else {
-      const int64_t kk = k - nF;
-      const int row = (int)(kk / Np), n = (int)(kk % Np);
-      float2 g = make_float2(0.f, 0.f);
-      if (row < H && n < N) {
-        const double L = (double)(2 * row - (H - 1));
-        double t = jb.in.y[n] * kxy * L + jb.in.z[n] * kz * L * L;
-        t -= rint(t);
-        double s, c;
-        sincospi(2.0 * t, &s, &c);
-        g = make_float2((float)c, (float)s);
-      }
-      const int lga = (n & 1) << 1;
-      for (int p = 0; p < 2; ++p)
-        jb.sepGa[op_index(row >> 4, n >> 1, KS, (row & 15) + 16 * (lga + p))] = g;
-      float2* Gv = reinterpret_cast<float2*>(jb.sepGv);
-      Gv[op_index(row >> 4, n >> 4, S16, (n & 15) + 16 * ((row & 15) >> 2)) * 4 + (row & 3)] = g;
-    }
-  }
-}
 
 constexpr int kSepSteps = 8;  // K-steps of the back-propagation product per load group
 constexpr int kSepCols = 8;   // column pairs of the forward product per load group
@@ -357,17 +289,6 @@ __global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ 
 }
 
 }  // namespace
-
-int sep_table_blocks(const JobDev& j) {
-  const int64_t total = (int64_t)16 * (j.mx_cblocks + j.mx_rblocks) * 16 * j.mx_steps;
-  return ceil_div(total, 256);
-}
-
-void launch_sep_tables(const JobDev* jobs, const JobSlice* slices, int nslices, int total_blocks,
-                       hipStream_t s) {
-  if (nslices <= 0 || total_blocks <= 0) return;
-  hipLaunchKernelGGL(k_sep_tables, dim3(total_blocks), dim3(256), 0, s, jobs, slices, nslices);
-}
 
 PassPlan plan_sep(int W, int H) {
   PassPlan p;

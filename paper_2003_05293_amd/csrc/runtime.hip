@@ -307,7 +307,7 @@ struct OrderId {
     return std::tie(dev, W, H, ap_q, key) < std::tie(o.dev, o.W, o.H, o.ap_q, o.key);
   }
 };
-// Device memory of one order: [JobDev][JobSlice][tables][perm][rows].
+// Device memory of one order: [JobDev][JobSlice][PrologueSlice][tables][perm][rows].
 struct OrderEntry {
   int dev = 0;
   DevBuf<char> mem;
@@ -333,7 +333,8 @@ hg_status build_order(OrderEntry& e, const JobSpec& s, int dev) {
   od.h = half_bits(od.P);
   od.order_key = s.order_key;
   const size_t o_slice = align_up(sizeof(JobDev), 256);
-  const size_t o_tab = align_up(o_slice + sizeof(JobSlice), 256);
+  const size_t o_pro = align_up(o_slice + sizeof(JobSlice), 256);
+  const size_t o_tab = align_up(o_pro + sizeof(PrologueSlice), 256);
   const size_t o_perm = align_up(o_tab + sizeof(uint32_t) * ((size_t)kFeistelRoundsHost << od.h), 256);
   const size_t o_rows = align_up(o_perm + sizeof(int32_t) * (size_t)od.P, 256);
   const size_t total = o_rows + (s.ap_q >= 0 ? sizeof(int32_t) * (2 * (size_t)s.H + 1) : 0);
@@ -346,12 +347,15 @@ hg_status build_order(OrderEntry& e, const JobSpec& s, int dev) {
   od.perm = e.perm;
   od.rows = e.rows;
   const JobSlice slice{0, 0};
+  const PrologueSlice pro{0, 0, prologue_setup_blocks(od), 0};
   HG_HIP(hipMemcpy(e.mem.p, &od, sizeof(JobDev), hipMemcpyHostToDevice));
   HG_HIP(hipMemcpy(e.mem.p + o_slice, &slice, sizeof(JobSlice), hipMemcpyHostToDevice));
+  HG_HIP(hipMemcpy(e.mem.p + o_pro, &pro, sizeof(PrologueSlice), hipMemcpyHostToDevice));
   hipStream_t& st = g_order_streams[dev];
   if (!st) HG_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
   const JobDev* jd = reinterpret_cast<const JobDev*>(e.mem.p);
-  launch_setup_batch(jd, 1, od.h, st);
+  launch_prologue(jd, reinterpret_cast<const PrologueSlice*>(e.mem.p + o_pro), 1,
+                  pro.setup_blocks, st);
   launch_perm_batch(jd, reinterpret_cast<const JobSlice*>(e.mem.p + o_slice), 1, perm_blocks(od.P),
                     od.h <= 11, st);
   const hipError_t le = hipGetLastError();
@@ -822,7 +826,6 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
     }
   size_t bytes = align_up(host_spot_bytes_, 256);
   int max_rounds = 0;
-  max_h_ = 0;
   perm_lds_ = true;
   for (int i = 0; i < count; ++i) {
     layouts_[i] = layout_job(specs[i], tp, status_dev, false);
@@ -831,7 +834,6 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
     max_rounds = std::max(max_rounds, specs[i].iterations);
     const JobDev& j = layouts_[i].dev;
     if (j.compressed && !j.order_shared) {
-      max_h_ = std::max(max_h_, j.h);
       if (j.h > 11) perm_lds_ = false;
     }
   }
@@ -848,10 +850,8 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
   final_ = LaunchSet{};
   perm_.clear();
   perm_blocks_ = 0;
-  mxtab_.clear();
-  mxtab_blocks_ = 0;
-  septab_.clear();
-  septab_blocks_ = 0;
+  pro_.clear();
+  pro_blocks_ = 0;
   for (int i = 0; i < count; ++i) {
     const JobDev& j = jobs_[i];
     if (j.phi) final_.add_final(j, layouts_[i], i);
@@ -859,14 +859,9 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
       perm_.push_back(JobSlice{perm_blocks_, i});
       perm_blocks_ += perm_blocks(j.P);
     }
-    if (j.mixed) {
-      mxtab_.push_back(JobSlice{mxtab_blocks_, i});
-      mxtab_blocks_ += mx_table_blocks(j);
-    }
-    if (layouts_[i].separable) {
-      septab_.push_back(JobSlice{septab_blocks_, i});
-      septab_blocks_ += sep_table_blocks(j);
-    }
+    const PrologueSlice ps{pro_blocks_, i, prologue_setup_blocks(j), prologue_table_blocks(j)};
+    pro_.push_back(ps);
+    pro_blocks_ += ps.setup_blocks + ps.table_blocks;
   }
   // chained launch of a single FP32 job's compressed passes
   chain_descs_.clear();
@@ -892,15 +887,13 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
       chain_units_ = units;
     }
   }
-  // descriptor tables: [JobDev][JobSlice perm][JobSlice mx tables]
-  // [JobSlice sep tables][chain passes][rounds...][final]
+  // descriptor tables: [JobDev][JobSlice perm][PrologueSlice][chain passes]
+  // [rounds...][final]
   size_t tb = align_up(sizeof(JobDev) * count, 256);
   const size_t t_perm = tb;
   tb = align_up(tb + sizeof(JobSlice) * perm_.size(), 256);
-  const size_t t_mxtab = tb;
-  tb = align_up(tb + sizeof(JobSlice) * mxtab_.size(), 256);
-  const size_t t_septab = tb;
-  tb = align_up(tb + sizeof(JobSlice) * septab_.size(), 256);
+  const size_t t_pro = tb;
+  tb = align_up(tb + sizeof(PrologueSlice) * pro_.size(), 256);
   const size_t t_chain = tb;
   tb = align_up(tb + sizeof(PassDesc) * chain_descs_.size(), 256);
   const size_t t_sets = tb;
@@ -914,15 +907,11 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
   perm_dev_ = reinterpret_cast<JobSlice*>(table_.p + t_perm);
   std::memcpy(staging_.p, jobs_.data(), sizeof(JobDev) * count);
   if (!perm_.empty()) std::memcpy(staging_.p + t_perm, perm_.data(), sizeof(JobSlice) * perm_.size());
-  mxtab_dev_ = reinterpret_cast<JobSlice*>(table_.p + t_mxtab);
-  if (!mxtab_.empty())
-    std::memcpy(staging_.p + t_mxtab, mxtab_.data(), sizeof(JobSlice) * mxtab_.size());
+  pro_dev_ = reinterpret_cast<PrologueSlice*>(table_.p + t_pro);
+  std::memcpy(staging_.p + t_pro, pro_.data(), sizeof(PrologueSlice) * pro_.size());
   chain_dev_ = reinterpret_cast<PassDesc*>(table_.p + t_chain);
   if (!chain_descs_.empty())
     std::memcpy(staging_.p + t_chain, chain_descs_.data(), sizeof(PassDesc) * chain_descs_.size());
-  septab_dev_ = reinterpret_cast<JobSlice*>(table_.p + t_septab);
-  if (!septab_.empty())
-    std::memcpy(staging_.p + t_septab, septab_.data(), sizeof(JobSlice) * septab_.size());
   size_t o = t_sets;
   for (LaunchSet& ls : rounds_) o += ls.stage(staging_.p + o, table_.p + o);
   o += final_.stage(staging_.p + o, table_.p + o);
@@ -949,18 +938,11 @@ hg_status Batch::enqueue_prologue(hipStream_t s, bool capture) {
     if (quiet) launch();
     else timed(s, name, launch);
   };
-  run("k_setup", [&] { launch_setup_batch(jobs_dev_, count(), max_h_, s); });
+  run("k_prologue",
+      [&] { launch_prologue(jobs_dev_, pro_dev_, (int)pro_.size(), pro_blocks_, s); });
   if (perm_blocks_ > 0)
     run("k_perm", [&] {
       launch_perm_batch(jobs_dev_, perm_dev_, (int)perm_.size(), perm_blocks_, perm_lds_, s);
-    });
-  if (mxtab_blocks_ > 0)
-    run("k_mx_tables", [&] {
-      launch_mx_tables(jobs_dev_, mxtab_dev_, (int)mxtab_.size(), mxtab_blocks_, s);
-    });
-  if (septab_blocks_ > 0)
-    run("k_sep_tables", [&] {
-      launch_sep_tables(jobs_dev_, septab_dev_, (int)septab_.size(), septab_blocks_, s);
     });
   return HG_OK;
 }
@@ -1054,8 +1036,7 @@ void Batch::release() {
   custom_.release();
   jobs_dev_ = nullptr;
   perm_dev_ = nullptr;
-  mxtab_dev_ = nullptr;
-  septab_dev_ = nullptr;
+  pro_dev_ = nullptr;
   chain_dev_ = nullptr;
 }
 

@@ -299,19 +299,15 @@ class Batch {
   LaunchSet final_;                      // final phases
   std::vector<JobSlice> perm_;
   int perm_blocks_ = 0;
-  std::vector<JobSlice> mxtab_;          // factor tables of the mixed-precision jobs
-  int mxtab_blocks_ = 0;
-  JobSlice* mxtab_dev_ = nullptr;
-  std::vector<JobSlice> septab_;         // factor tables of the separable FP32 jobs
-  int septab_blocks_ = 0;
-  JobSlice* septab_dev_ = nullptr;
+  std::vector<PrologueSlice> pro_;       // setup and factor tables, one launch
+  int pro_blocks_ = 0;
+  PrologueSlice* pro_dev_ = nullptr;
   // chained launch of the compressed passes (single job): iterations
   // 1..chain_rounds_ run in one k_pass_chain launch instead of rounds_
   std::vector<PassDesc> chain_descs_;
   PassDesc* chain_dev_ = nullptr;
   int chain_rounds_ = 0, chain_blocks_ = 0, chain_units_ = 1;
   bool perm_lds_ = true;
-  int max_h_ = 0;
   size_t host_spot_bytes_ = 0;
   size_t raw_base_ = 0;
   DevBuf<char> arena_;
