@@ -146,6 +146,11 @@ __device__ __forceinline__ bool update_rec(SpotRec& r, float2 v, float mag, floa
 // vs: LDS room for N float2 (the spot fields in FP32, kept for the update:
 // values other threads stored to memory are not read back, since a block
 // of a chained launch may hold stale copies of them in its L1 cache).
+// In a chained launch the passes' updates run in blocks on any XCD, and the
+// XCDs' L2 caches write back independently: a plain store of C_n or V_n
+// could leave an older pass's value dirty in one L2 and written back after
+// the newer one, so there every state word goes out with device-scope
+// stores (not left dirty in any L2).
 __device__ void tail_final(const PassCtx& a, float2* vs) {
   const int N = a.N;
   const double inv = ldexp(1.0, -a.plan.shift) * a.inv_count;
@@ -155,7 +160,8 @@ __device__ void tail_final(const PassCtx& a, float2* vs) {
     const long long re = (long long)take_dev(tot + (int64_t)n * kAccSpotWords);
     const long long im = (long long)take_dev(tot + (int64_t)n * kAccSpotWords + 1);
     const double2 t = make_double2((double)re * inv, (double)im * inv);
-    a.V[n] = t;
+    if (a.chain) store_dev(a.V + n, t);
+    else a.V[n] = t;
     const float2 v = field32(t);
     vs[n] = v;
     msum += mag32(v);
@@ -191,7 +197,8 @@ __device__ void tail_final(const PassCtx& a, float2* vs) {
     else a.sp[n] = r;
     // C_n = A_n e^{i theta_n} = A_n V_n / |V_n|
     const float Am = r.A / mag;
-    a.coef[n] = make_float2(Am * v.x, Am * v.y);
+    if (a.chain) store_dev(a.coef + n, make_float2(Am * v.x, Am * v.y));
+    else a.coef[n] = make_float2(Am * v.x, Am * v.y);
   }
 }
 

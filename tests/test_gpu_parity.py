@@ -454,3 +454,21 @@ def test_chained_passes_bit_identical(W, H, N, I, c, seed):
     torch.cuda.synchronize()
     assert torch.equal(a, b)
     assert np.array_equal(Va, Vb)
+
+
+def test_chained_state_after_launch_repeatable():
+    """The spot state a chained launch leaves for the full-grid pass after it
+    is the last pass's: every update in the launch may run on another XCD,
+    whose L2 holds its own copy of the state words, so the state goes out
+    with device-scope stores.  Repeated chained runs of one hologram, each
+    against one launch per pass, bit for bit (hologram and every field)."""
+    import torch
+    g = Grid(1152, 1152)
+    s = spot_cloud(0, 100, g, z_half_mm=0.1)
+    say("chained launch repeated", 1152, 1152, 100, 30)
+    a, Va = hg.cswgs(g, OPTICS, s, 30, 1 / 16, 0, trace=True)
+    for rep in range(4):
+        b, Vb = hg.cswgs(g, OPTICS, s, 30, 1 / 16, 0, trace=True, tune=CHAINED)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), rep
+        assert np.array_equal(Va, Vb), rep
