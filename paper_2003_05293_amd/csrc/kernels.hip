@@ -313,8 +313,8 @@ __device__ void sep_tables_part(const JobDev& jb, int lb, int nb) {
       const int lgc = (n & 1) << 1, lgn = (col & 1) << 1;
       for (int p = 0; p < 2; ++p) {
         const float v = p ? fi : fr;
-        jb.sepFc[op_index(col >> 4, n >> 1, KS, (col & 15) + 16 * (lgc + p))] = v;
-        jb.sepFn[op_index(n >> 4, col >> 1, CP, (n & 15) + 16 * (lgn + p))] = v;
+        jb.sepFc[op_index4(col >> 4, n >> 1, KS, (col & 15) + 16 * (lgc + p))] = v;
+        jb.sepFn[op_index4(n >> 4, col >> 1, CP, (n & 15) + 16 * (lgn + p))] = v;
       }
     } else {
       const int64_t kk = k - nF;
@@ -330,7 +330,7 @@ __device__ void sep_tables_part(const JobDev& jb, int lb, int nb) {
       }
       const int lga = (n & 1) << 1;
       for (int p = 0; p < 2; ++p)
-        jb.sepGa[op_index(row >> 4, n >> 1, KS, (row & 15) + 16 * (lga + p))] = g;
+        jb.sepGa[op_index4(row >> 4, n >> 1, KS, (row & 15) + 16 * (lga + p))] = g;
       float2* Gv = reinterpret_cast<float2*>(jb.sepGv);
       Gv[op_index(row >> 4, n >> 4, S16, (n & 15) + 16 * ((row & 15) >> 2)) * 4 + (row & 3)] = g;
     }

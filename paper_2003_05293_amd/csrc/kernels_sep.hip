@@ -43,14 +43,27 @@ struct BpOps {
 };
 __device__ __forceinline__ void bp_load(BpOps& o, const JobDev& jb, int rb, int tx, int s0, int KS,
                                         int lane) {
+  static_assert(kSepSteps % 4 == 0, "groups of whole step quads");
 #pragma unroll
-  for (int q = 0; q < kSepSteps; ++q) {
-    const HG_GLOBAL float* gp =
-        as_global(reinterpret_cast<const float*>(jb.sepGa + op_index(rb, s0 + q, KS, lane)));
-    o.ga[q] = make_float2(gp[0], gp[1]);
+  for (int h = 0; h < kSepSteps; h += 4) {
+    // four steps of G (float2 each) in two 16-byte loads, four of each F
+    // operand in one
+    const HG_GLOBAL f4_t* gp =
+        as_global(reinterpret_cast<const f4_t*>(jb.sepGa + op_index4(rb, s0 + h, KS, lane)));
+    const f4_t g01 = gp[0], g23 = gp[1];
+    o.ga[h] = make_float2(g01[0], g01[1]);
+    o.ga[h + 1] = make_float2(g01[2], g01[3]);
+    o.ga[h + 2] = make_float2(g23[0], g23[1]);
+    o.ga[h + 3] = make_float2(g23[2], g23[3]);
 #pragma unroll
-    for (int t = 0; t < kSepCB; ++t)
-      o.fc[q][t] = as_global(jb.sepFc)[op_index(kSepCB * tx + t, s0 + q, KS, lane)];
+    for (int t = 0; t < kSepCB; ++t) {
+      const f4_t f = as_global(reinterpret_cast<const f4_t*>(
+          jb.sepFc + op_index4(kSepCB * tx + t, s0 + h, KS, lane)))[0];
+      o.fc[h][t] = f[0];
+      o.fc[h + 1][t] = f[1];
+      o.fc[h + 2][t] = f[2];
+      o.fc[h + 3][t] = f[3];
+    }
   }
 }
 // A operand: part of B (real output: (Br, -Bi)) or of i B (imaginary
@@ -83,12 +96,19 @@ __device__ void sep_forward(const JobDev& jb, const float2 (*us)[kSepTileW + 1],
 #pragma unroll
   for (int k = 0; k < R; ++k) tr[k] = ti[k] = f4_t{0.f, 0.f, 0.f, 0.f};
   float fa[kSepCols][R], fb[kSepCols][R];
-  auto load = [&](float (*fn)[R], int c0) {
+  static_assert(kSepCols % 4 == 0, "load groups of whole column-pair quads");
+  auto load = [&](float (*fn)[R], int c0) {  // four column pairs per 16-byte load
 #pragma unroll
-    for (int q = 0; q < kSepCols; ++q)
+    for (int q = 0; q < kSepCols; q += 4)
 #pragma unroll
-      for (int k = 0; k < R; ++k)
-        fn[q][k] = as_global(jb.sepFn)[op_index(sb0 + k, col0 / 2 + c0 + q, CP, lane)];
+      for (int k = 0; k < R; ++k) {
+        const f4_t f = as_global(reinterpret_cast<const f4_t*>(
+            jb.sepFn + op_index4(sb0 + k, col0 / 2 + c0 + q, CP, lane)))[0];
+        fn[q][k] = f[0];
+        fn[q + 1][k] = f[1];
+        fn[q + 2][k] = f[2];
+        fn[q + 3][k] = f[3];
+      }
   };
   auto mma = [&](const float (*fn)[R], int c0) {
 #pragma unroll

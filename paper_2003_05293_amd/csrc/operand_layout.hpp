@@ -16,6 +16,12 @@ namespace hg {
 __device__ __forceinline__ int64_t op_index(int blk, int step, int steps, int lane) {
   return ((int64_t)blk * steps + step) * 64 + lane;
 }
+// The same operands with each lane's four consecutive steps next to each
+// other (steps a multiple of 4): one 16-byte load per lane covers four
+// K-steps of a 4-byte operand, two cover four steps of an 8-byte one.
+__device__ __forceinline__ int64_t op_index4(int blk, int step, int steps, int lane) {
+  return (((int64_t)blk * (steps >> 2) + (step >> 2)) * 64 + lane) * 4 + (step & 3);
+}
 
 // Mixed-precision passes, v_mfma_f32_16x16x32_f16 (lane l, e < 8, r < 4):
 //   A[l % 16][8 (l / 16) + e],  B[8 (l / 16) + e][l % 16],  D[4 (l / 16) + r][l % 16].
