@@ -766,7 +766,11 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab, bool has_pre = fals
           acc.x += v.x;
           acc.y += v.y;
         }
-      acc_add(a.acc, N, a.plan.shift, kAccTotalRows + tile / a.plan.group_size, n, acc);
+      // a deferring pass adds into a row of its total set, others into
+      // their tile's group
+      const int row = a.defer ? a.tot_row * kAccReplicas + tile % kAccReplicas
+                              : kAccGroupRow0 + tile / a.plan.group_size;
+      acc_add(a.acc, N, a.plan.shift, row, n, acc);
     }
     if (threadIdx.x == 0) {
       done[ndone++] = tile;
@@ -775,18 +779,17 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab, bool has_pre = fals
     __syncthreads();
     tile = next_tile;
     if (ndone == kDoneList) {
-      count_tiles(a, done, ndone, owned, &nowned);
+      if (!a.defer) count_tiles(a, done, ndone, owned, &nowned);
       if (threadIdx.x == 0) ndone = 0;
       __syncthreads();
     }
   }
-  count_tiles(a, done, ndone, owned, &nowned);
-  if constexpr (!CHAIN && MAXU == 1) {  // (deferring passes have one unit per wave)
-    if (a.defer) {
-      for (int i = 0; i < nowned; ++i) tail_group_deferred(a, owned[i]);
-      return;
-    }
+  // a deferring pass is complete when this launch ends: its tiles' sums are
+  // not counted (deferring passes have one unit per wave and no chain)
+  if constexpr (!CHAIN && MAXU == 1) {
+    if (a.defer) return;
   }
+  count_tiles(a, done, ndone, owned, &nowned);
   // the pass completes at most once, with this block's last group (the
   // update after the loop keeps the loop's registers free)
   bool last = false;
@@ -922,7 +925,7 @@ __device__ void pass_block_e(const PassCtx& a, unsigned* grab) {
     }
     // the tile's partials: spot n_lo + lane of each wave
     if (lane < cnt)
-      acc_add(a.acc, N, a.plan.shift, kAccTotalRows + tile / a.plan.group_size, n_lo + lane,
+      acc_add(a.acc, N, a.plan.shift, kAccGroupRow0 + tile / a.plan.group_size, n_lo + lane,
               rede[wave][lane]);
     if (threadIdx.x == 0) {
       done[ndone++] = tile;

@@ -55,11 +55,17 @@ constexpr int32_t kMaxTiles = 8192;
 // Words per spot in the rows of exact sums: the atomic additions of
 // different spots go to different cache lines.
 constexpr int kAccSpotWords = 2;
-// Rows of pass totals in the exact sums.  A compressed pass followed by
-// another compressed pass of the same job leaves its total in row
-// it mod 3 (it = iteration); the next pass applies that update, and the
-// pass after it clears the row.  Other passes use row 0.
+// Pass totals in the exact sums: kAccTotalRows sets of kAccReplicas rows.
+// A compressed pass followed by another compressed pass of the same job
+// (a deferring pass) adds each tile's sums straight into row
+// tile mod kAccReplicas of set it mod 3 (it = iteration), with no counting:
+// the next pass reads the set after this launch has ended and adds its rows
+// (integer sums, so the total is the same whatever the split), and the pass
+// after that clears it.  Other passes hand their sums over through group
+// rows into the first row of their set (set 0 unless pending).
 constexpr int kAccTotalRows = 3;
+constexpr int kAccReplicas = 10;
+constexpr int kAccGroupRow0 = kAccTotalRows * kAccReplicas;  // row of group 0
 // Fixed-point scale of the exact sums of a pass over `pixels` pixels: every
 // term has magnitude <= 1, so |sum| * 2^shift <= 2^62.
 int sum_shift(int64_t pixels);
@@ -138,12 +144,12 @@ struct JobDev {
   float* phi;          // [H][W] output hologram (or input of a forward test pass)
   float2* partial;     // [max pass tiles][N] (mixed-precision passes)
   double2* gpart;      // [max pass groups][N] (mixed-precision passes)
-  // exact fixed-point sums of the FP32 passes: rows 0..kAccTotalRows-1 pass
-  // totals, row kAccTotalRows + g group g; per spot a (re, im) two's-
+  // exact fixed-point sums of the FP32 passes: rows 0..kAccGroupRow0-1 the
+  // sets of pass totals, row kAccGroupRow0 + g group g; per spot a (re, im) two's-
   // complement pair at the start of an entry of kAccSpotWords words; zero
   // between passes, except a total that a deferred update leaves for the
   // next pass
-  unsigned long long* acc;  // [max pass groups + kAccTotalRows][N][kAccSpotWords]
+  unsigned long long* acc;  // [kAccGroupRow0 + max pass groups][N][kAccSpotWords]
   int64_t acc_len;
   unsigned* counters;  // [max pass groups + 1] group and pass counters, kCounterStride apart
   unsigned* grab;      // [iterations + 2] tile counters of the passes (PassDesc::grab_slot)
@@ -200,19 +206,19 @@ struct PassDesc {
   double inv_count;
   double2* V;           // spot fields of this pass, [N]
   // Deferred updates between consecutive compressed passes of a job
-  // (N <= kPendMaxSpots).  A deferring pass stops once its groups have
-  // added into total row tot_row: the pass counter, the read of the total
-  // and the update leave its critical path.  The next pass is pending:
+  // (N <= kPendMaxSpots).  A deferring pass stops once its tiles have
+  // added into the rows of total set tot_row: the counts, the hand-off, the
+  // read of the total and the update leave its critical path.  The next pass is pending:
   // every block applies that update to the state st_in at its start (the
   // same FP32 operations in the same order, so the same bits) and keeps the
   // result in LDS; its block 0 stores it to st_out when the pass defers in
-  // turn, and clears total row clear_row.  A pending pass that does not
-  // defer updates from its LDS state as usual and clears prev_row at the end.
+  // turn, and clears total set clear_row.  A pending pass that does not
+  // defer updates from its LDS state as usual and clears set prev_row at the end.
   int32_t defer = 0;
   int32_t pending = 0;
-  int32_t tot_row = 0;     // total row of this pass's sums
-  int32_t prev_row = 0;    // total row of the previous pass (pending)
-  int32_t clear_row = -1;  // total row block 0 clears at its start (pending)
+  int32_t tot_row = 0;     // total set of this pass's sums
+  int32_t prev_row = 0;    // total set of the previous pass (pending)
+  int32_t clear_row = -1;  // total set block 0 clears at its start (pending)
   double prev_inv = 0.0;   // 2^-shift / count of the previous pass (pending)
   const SpotRec* st_in = nullptr;  // state before the previous pass's update
   SpotRec* st_out = nullptr;       // updated state, for the next pass (pending and defer)

@@ -156,7 +156,7 @@ __device__ void sep_forward(const JobDev& jb, const float2 (*us)[kSepTileW + 1],
         v.x += red[w][threadIdx.x].x;
         v.y += red[w][threadIdx.x].y;
       }
-      acc_add(jb.acc, jb.N, shift, kAccTotalRows + g, n, v);
+      acc_add(jb.acc, jb.N, shift, kAccGroupRow0 + g, n, v);
     }
   }
   __syncthreads();

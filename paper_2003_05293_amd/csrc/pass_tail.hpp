@@ -70,8 +70,9 @@ __device__ __forceinline__ void load_recs_dev(const SpotRec* sp, int N, SpotRec*
 // fixed-point integer (scale 2^shift, |sum over the pass| <= pixels, so no
 // sum overflows) and added with device-scope integer atomics: integer
 // addition is associative, so the sums do not depend on the order in which
-// tiles, groups or blocks arrive.  Rows: 0..kAccTotalRows-1 = pass totals,
-// kAccTotalRows + g = group g.
+// tiles, groups or blocks arrive.  Rows: the sets of pass totals (rows
+// 0..kAccGroupRow0-1, kAccReplicas per set), then row kAccGroupRow0 + g =
+// group g.
 __device__ __forceinline__ void acc_add(unsigned long long* acc, int N, int shift, int row, int n,
                                         float2 v) {
   const double scale = ldexp(1.0, shift);
@@ -92,23 +93,10 @@ __device__ __forceinline__ unsigned long long take_dev(unsigned long long* p) {
 __device__ bool tail_group(const PassCtx& a, int g, int* flag) {
   for (int k = threadIdx.x; k < 2 * a.N; k += kBlock) {
     const int64_t e = (int64_t)(k >> 1) * kAccSpotWords + (k & 1);  // spot k / 2, part k % 2
-    const unsigned long long v = take_dev(a.acc + (int64_t)(kAccTotalRows + g) * a.N * kAccSpotWords + e);
-    atomicAdd(a.acc + (int64_t)a.tot_row * a.N * kAccSpotWords + e, v);
+    const unsigned long long v = take_dev(a.acc + (int64_t)(kAccGroupRow0 + g) * a.N * kAccSpotWords + e);
+    atomicAdd(a.acc + (int64_t)a.tot_row * kAccReplicas * a.N * kAccSpotWords + e, v);
   }
   return arrive_last(&a.counters[a.plan.ngroups * kCounterStride], (unsigned)a.plan.ngroups, flag);
-}
-
-// Group g of a deferring pass is complete: its sums go into the pass total,
-// which the next pass reads after this launch has ended, and the group's
-// counter is ready for the next pass (every count of this pass has arrived).
-__device__ void tail_group_deferred(const PassCtx& a, int g) {
-  for (int k = threadIdx.x; k < 2 * a.N; k += kBlock) {
-    const int64_t e = (int64_t)(k >> 1) * kAccSpotWords + (k & 1);
-    const unsigned long long v = take_dev(a.acc + (int64_t)(kAccTotalRows + g) * a.N * kAccSpotWords + e);
-    atomicAdd(a.acc + (int64_t)a.tot_row * a.N * kAccSpotWords + e, v);
-  }
-  if (threadIdx.x == 0)
-    __hip_atomic_store(a.counters + g * kCounterStride, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // The weight update of eqs. (4)-(6) in FP32: the one place that does this
@@ -154,7 +142,7 @@ __device__ __forceinline__ bool update_rec(SpotRec& r, float2 v, float mag, floa
 __device__ void tail_final(const PassCtx& a, float2* vs) {
   const int N = a.N;
   const double inv = ldexp(1.0, -a.plan.shift) * a.inv_count;
-  unsigned long long* tot = a.acc + (int64_t)a.tot_row * N * kAccSpotWords;
+  unsigned long long* tot = a.acc + (int64_t)a.tot_row * kAccReplicas * N * kAccSpotWords;
   float msum = 0.f;
   for (int n = threadIdx.x; n < N; n += kBlock) {
     const long long re = (long long)take_dev(tot + (int64_t)n * kAccSpotWords);
@@ -166,12 +154,12 @@ __device__ void tail_final(const PassCtx& a, float2* vs) {
     vs[n] = v;
     msum += mag32(v);
   }
-  // the previous pass's total, which every block of this pass has read
+  // the previous pass's total set, which every block of this pass has read
   // before counting its tiles, is cleared
   if (a.pend_row >= 0) {
     HG_GLOBAL unsigned long long* q =
-        as_global_mut(a.acc + (int64_t)a.pend_row * N * kAccSpotWords);
-    for (int k = threadIdx.x; k < N * kAccSpotWords; k += kBlock)
+        as_global_mut(a.acc + (int64_t)a.pend_row * kAccReplicas * N * kAccSpotWords);
+    for (int k = threadIdx.x; k < kAccReplicas * N * kAccSpotWords; k += kBlock)
       __hip_atomic_store(q + k, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   // the counters are ready for the next pass (kernel end orders these
@@ -202,10 +190,11 @@ __device__ void tail_final(const PassCtx& a, float2* vs) {
   }
 }
 
-// Pending pass: every block applies the previous pass's update to the state
-// before it (d.st_in) and keeps the result in recs (LDS), with the
-// arithmetic and the mean of tail_final (one spot per thread).  Block 0 (lead)
-// also clears the total row two passes back, stores the state for the next
+// Pending pass: every block adds the rows of the previous pass's total set
+// (integer sums: the total that a hand-off would have formed), applies that
+// pass's update to the state before it (d.st_in) and keeps the result in
+// recs (LDS), with the arithmetic and the mean of tail_final (one spot per
+// thread).  Block 0 (lead) also clears the total set two passes back, stores the state for the next
 // pass when this pass defers in turn, the previous V when traced, and the
 // status.  N <= kPendMaxSpots <= kBlock.
 __device__ void apply_pending(const JobDev& jb, const PassDesc& d, bool lead, SpotRec* recs,
@@ -214,8 +203,8 @@ __device__ void apply_pending(const JobDev& jb, const PassDesc& d, bool lead, Sp
   const int n = threadIdx.x;
   if (lead && d.clear_row >= 0) {
     HG_GLOBAL unsigned long long* q =
-        as_global_mut(jb.acc + (int64_t)d.clear_row * N * kAccSpotWords);
-    for (int k = threadIdx.x; k < N * kAccSpotWords; k += kBlock)
+        as_global_mut(jb.acc + (int64_t)d.clear_row * kAccReplicas * N * kAccSpotWords);
+    for (int k = threadIdx.x; k < kAccReplicas * N * kAccSpotWords; k += kBlock)
       __hip_atomic_store(q + k, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
   double2 t = make_double2(0.0, 0.0);
@@ -227,9 +216,15 @@ __device__ void apply_pending(const JobDev& jb, const PassDesc& d, bool lead, Sp
   for (int k = 0; k < kWords; ++k) f[k] = 0.f;
   if (n < N) {
     const HG_GLOBAL unsigned long long* tot =
-        as_global(jb.acc + ((int64_t)d.prev_row * N + n) * kAccSpotWords);
-    const long long re = (long long)__hip_atomic_load(tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const long long im = (long long)__hip_atomic_load(tot + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        as_global(jb.acc + ((int64_t)d.prev_row * kAccReplicas * N + n) * kAccSpotWords);
+    unsigned long long sre = 0ull, sim = 0ull;  // modulo 2^64: the exact total fits
+#pragma unroll
+    for (int r = 0; r < kAccReplicas; ++r) {
+      const HG_GLOBAL unsigned long long* t = tot + (int64_t)r * N * kAccSpotWords;
+      sre += __hip_atomic_load(t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      sim += __hip_atomic_load(t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const long long re = (long long)sre, im = (long long)sim;
     t = make_double2((double)re * d.prev_inv, (double)im * d.prev_inv);
     const HG_GLOBAL float* src = as_global(reinterpret_cast<const float*>(d.st_in + n));
 #pragma unroll

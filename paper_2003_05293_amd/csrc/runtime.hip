@@ -518,7 +518,7 @@ JobLayout layout_job(const JobSpec& s, const TuneParams& tp, int32_t* status_dev
     L.off_gpart = take(sizeof(double2) * (size_t)max_groups * s.N);
   }
   if (!j.mixed || j.compressed) {  // exact fixed-point sums of the per-pixel passes
-    j.acc_len = (int64_t)(acc_groups + kAccTotalRows) * s.N * kAccSpotWords;
+    j.acc_len = (int64_t)(kAccGroupRow0 + acc_groups) * s.N * kAccSpotWords;
     L.off_acc = take(sizeof(unsigned long long) * (size_t)j.acc_len);
   }
   L.off_counters = take(sizeof(unsigned) * (size_t)j.counters_len);
