@@ -317,6 +317,19 @@ struct SepDesc {
   double inv_count;
   double2* V;
   float* out;           // final-phase variant: Phi output
+  // Deferred updates, as in PassDesc: a pending pass (or final hologram)
+  // applies the previous pass's update at its start, into LDS (records and
+  // C_n); a deferring pass adds its tiles' sums into total set tot_row and
+  // stops.
+  int32_t defer = 0;
+  int32_t pending = 0;
+  int32_t tot_row = 0;
+  int32_t prev_row = 0;
+  int32_t clear_row = -1;
+  double prev_inv = 0.0;
+  const SpotRec* st_in = nullptr;
+  SpotRec* st_out = nullptr;
+  double2* prev_V = nullptr;
 };
 // (The factor tables are built by the prologue from FP64 phases: the spots
 // do not move during the iterations.)

@@ -85,12 +85,12 @@ __device__ __forceinline__ void bp_mma(const BpOps& o, const float2* cs, int s0,
 
 // T = U conj(F)^T for R 16-spot blocks starting at sb0 and the wave's 16
 // rows, then the tile's partial V_n = sum_j conj(G_n(j)) T[j][n] of those
-// spots, added into the exact sums of group g.  Every thread of the block
+// spots, added into row `row` of the exact sums.  Every thread of the block
 // calls this with the same sb0 and R.
 template <int R>
 __device__ void sep_forward(const JobDev& jb, const float2 (*us)[kSepTileW + 1],
                             float2 (*red)[64], int sb0, int rb, int col0, int S16, int CP, int lane,
-                            int wave, int shift, int g) {
+                            int wave, int shift, int row) {
   const int lr = lane & 15, lg = lane >> 4, part = lg & 1;
   f4_t tr[R], ti[R];
 #pragma unroll
@@ -125,13 +125,19 @@ __device__ void sep_forward(const JobDev& jb, const float2 (*us)[kSepTileW + 1],
   static_assert(kSepTileW / 2 == 2 * kSepCols, "two column groups per tile");
   load(fa, 0);
   load(fb, kSepCols);
+  // G of the V sums, requested with F (it does not depend on the products)
+  f4_t gva[R], gvb[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) {
+    const int64_t gv = op_index(rb, sb0 + k, S16, lane) * 2;
+    gva[k] = as_global(reinterpret_cast<const f4_t*>(jb.sepGv))[gv];
+    gvb[k] = as_global(reinterpret_cast<const f4_t*>(jb.sepGv))[gv + 1];
+  }
   mma(fa, 0);
   mma(fb, kSepCols);
 #pragma unroll
   for (int k = 0; k < R; ++k) {
-    const int64_t gv = op_index(rb, sb0 + k, S16, lane) * 2;
-    const f4_t g01 = as_global(reinterpret_cast<const f4_t*>(jb.sepGv))[gv];
-    const f4_t g23 = as_global(reinterpret_cast<const f4_t*>(jb.sepGv))[gv + 1];
+    const f4_t g01 = gva[k], g23 = gvb[k];
     const float gr[4] = {g01[0], g01[2], g23[0], g23[2]};
     const float gi[4] = {g01[1], g01[3], g23[1], g23[3]};
     float vr = 0.f, vi = 0.f;
@@ -156,7 +162,7 @@ __device__ void sep_forward(const JobDev& jb, const float2 (*us)[kSepTileW + 1],
         v.x += red[w][threadIdx.x].x;
         v.y += red[w][threadIdx.x].y;
       }
-      acc_add(jb.acc, jb.N, shift, kAccGroupRow0 + g, n, v);
+      acc_add(jb.acc, jb.N, shift, row, n, v);
     }
   }
   __syncthreads();
@@ -168,6 +174,7 @@ __global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ 
                                                      int ndesc) {
   extern __shared__ float2 cs[];                      // [Np] C_n = A_n e^{i theta_n}
   __shared__ float2 us[kWaves][16][kSepTileW + 1];    // u of each wave's rows
+  __shared__ SpotRec recs[kPendMaxSpots];             // pending: the updated records
   __shared__ float2 red[kWaves][64];
   __shared__ int flag;
   const int di = find_desc(descs, ndesc, blockIdx.x);
@@ -182,16 +189,6 @@ __global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ 
   const int rb = 4 * ty + wave;
   const int row0 = 16 * rb, col0 = kSepTileW * tx;
 
-  for (int n = threadIdx.x; n < 16 * S16; n += kBlock) {
-    float2 c = make_float2(0.f, 0.f);
-    if (n < N) {
-      const HG_GLOBAL float* f = as_global(reinterpret_cast<const float*>(jb.coef + n));
-      c = make_float2(f[0], f[1]);
-    }
-    cs[n] = c;
-  }
-  __syncthreads();
-
   // S = B F, K = 2 Np in groups of kSepSteps steps (KS = 8 S16 is a
   // multiple of kSepSteps), the next group's operands loaded ahead.
   f4_t sr[kSepCB], si[kSepCB];
@@ -200,10 +197,27 @@ __global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ 
   {
     static_assert(kSepSteps == 8, "K-step groups of 8: KS = 8 S16");
     const int G = KS / kSepSteps;
-    // three operand buffers: the loads run two groups ahead of the products
+    // three operand buffers: the loads run two groups ahead of the products;
+    // the first two are requested before C_n is staged, so that the two
+    // reads overlap
     BpOps P, Q, R;
     bp_load(P, jb, rb, tx, 0, KS, lane);
     if (G > 1) bp_load(Q, jb, rb, tx, kSepSteps, KS, lane);
+    if (d.pending) {
+      // the previous pass's deferred update, C_n formed as its tail would
+      apply_pending(jb, d, lb == 0, recs, nullptr, cs);
+      for (int n = N + threadIdx.x; n < 16 * S16; n += kBlock) cs[n] = make_float2(0.f, 0.f);
+    } else {
+      for (int n = threadIdx.x; n < 16 * S16; n += kBlock) {
+        float2 c = make_float2(0.f, 0.f);
+        if (n < N) {
+          const HG_GLOBAL float* f = as_global(reinterpret_cast<const float*>(jb.coef + n));
+          c = make_float2(f[0], f[1]);
+        }
+        cs[n] = c;
+      }
+    }
+    __syncthreads();
     for (int gi = 0; gi < G; gi += 3) {
       if (gi + 2 < G) bp_load(R, jb, rb, tx, (gi + 2) * kSepSteps, KS, lane);
       bp_mma(P, cs, gi * kSepSteps, lg, part, sr, si);
@@ -264,24 +278,29 @@ __global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ 
     }
   __syncthreads();
 
-  // T and the partial V in groups of four 16-spot blocks, then the rest.
+  // T and the partial V in groups of four 16-spot blocks, then the rest,
+  // into the tile's group row, or, when the pass defers its update, into a
+  // row of its total set (no counting: the next launch reads the set)
   const int g = lb / d.plan.group_size;
+  const int row =
+      d.defer ? d.tot_row * kAccReplicas + lb % kAccReplicas : kAccGroupRow0 + g;
   int sb0 = 0;
   for (; sb0 + 4 <= S16; sb0 += 4)
-    sep_forward<4>(jb, us[wave], red, sb0, rb, col0, S16, CP, lane, wave, d.plan.shift, g);
+    sep_forward<4>(jb, us[wave], red, sb0, rb, col0, S16, CP, lane, wave, d.plan.shift, row);
   switch (S16 - sb0) {
     case 3:
-      sep_forward<3>(jb, us[wave], red, sb0, rb, col0, S16, CP, lane, wave, d.plan.shift, g);
+      sep_forward<3>(jb, us[wave], red, sb0, rb, col0, S16, CP, lane, wave, d.plan.shift, row);
       break;
     case 2:
-      sep_forward<2>(jb, us[wave], red, sb0, rb, col0, S16, CP, lane, wave, d.plan.shift, g);
+      sep_forward<2>(jb, us[wave], red, sb0, rb, col0, S16, CP, lane, wave, d.plan.shift, row);
       break;
     case 1:
-      sep_forward<1>(jb, us[wave], red, sb0, rb, col0, S16, CP, lane, wave, d.plan.shift, g);
+      sep_forward<1>(jb, us[wave], red, sb0, rb, col0, S16, CP, lane, wave, d.plan.shift, row);
       break;
     default:
       break;
   }
+  if (d.defer) return;
 
   PassCtx a;
   a.sp = jb.sp;
@@ -302,6 +321,11 @@ __global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ 
   a.status = jb.status;
   a.update = d.update;
   a.from_phi = 0;
+  a.tot_row = d.tot_row;
+  if (d.pending) {  // the update starts from the records in LDS
+    a.recs = recs;
+    a.pend_row = d.prev_row;
+  }
   const int size = min(d.plan.group_size, d.plan.tiles - g * d.plan.group_size);
   if (arrive_last(&jb.counters[g * kCounterStride], (unsigned)size, &flag) &&
       tail_group(a, g, &flag))

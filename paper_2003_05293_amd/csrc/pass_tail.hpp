@@ -194,11 +194,15 @@ __device__ void tail_final(const PassCtx& a, float2* vs) {
 // (integer sums: the total that a hand-off would have formed), applies that
 // pass's update to the state before it (d.st_in) and keeps the result in
 // recs (LDS), with the arithmetic and the mean of tail_final (one spot per
-// thread).  Block 0 (lead) also clears the total set two passes back, stores the state for the next
-// pass when this pass defers in turn, the previous V when traced, and the
-// status.  N <= kPendMaxSpots <= kBlock.
-__device__ void apply_pending(const JobDev& jb, const PassDesc& d, bool lead, SpotRec* recs,
-                              uint2* cpl) {
+// thread); with cl or cpl, also C_n = A_n e^{i theta_n} in FP32 or as FP16
+// pairs (LDS), formed as tail_final forms it.  Block 0 (lead) also clears
+// the total set two passes back, stores the state for the next pass when
+// this pass defers in turn (the final state, in the final hologram), the
+// previous V when traced, and the status.  N <= kPendMaxSpots <= kBlock.
+// D: PassDesc or SepDesc.
+template <typename D>
+__device__ void apply_pending(const JobDev& jb, const D& d, bool lead, SpotRec* recs, uint2* cpl,
+                              float2* cl = nullptr) {
   const int N = jb.N;
   const int n = threadIdx.x;
   if (lead && d.clear_row >= 0) {
@@ -243,7 +247,7 @@ __device__ void apply_pending(const JobDev& jb, const PassDesc& d, bool lead, Sp
     const float mag = mag32(v);
     const bool ok = update_rec(r, v, mag, mean);
     if (!ok && lead) jb.status[0] = 4;  // HG_ENUMERIC
-    if (cpl) {  // mixed precision: C_n = A_n e^{i theta_n} as FP16 pairs
+    if (cpl || cl) {  // C_n = A_n e^{i theta_n}
       float2 C;
       if (ok) {
         const float Am = r.A / mag;  // as tail_final forms it
@@ -253,7 +257,8 @@ __device__ void apply_pending(const JobDev& jb, const PassDesc& d, bool lead, Sp
         sincos_turns(r.th, sn, cs);
         C = make_float2(r.A * cs, r.A * sn);
       }
-      cpl[n] = coef_pairs(C);
+      if (cpl) cpl[n] = coef_pairs(C);  // mixed precision: FP16 pairs
+      if (cl) cl[n] = C;
     }
     __builtin_memcpy(f, &r, sizeof(r));
     float* dst = reinterpret_cast<float*>(recs + n);

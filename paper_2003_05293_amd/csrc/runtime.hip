@@ -581,6 +581,63 @@ JobDev bind_job(const JobLayout& L, const JobSpec& s, char* base, const double* 
   return j;
 }
 
+namespace {
+// Deferred updates.  Pass it of job j (1..I; I + 1 is the final hologram)
+// can apply the previous pass's update at its start, and so let that pass
+// stop after its sums: the per-pixel compressed passes of one spot unit per
+// wave (FP32 or mixed), and the FP32 separable full-grid passes and final
+// hologram, for N <= kPendMaxSpots.
+bool pend_capable(const JobDev& j, const JobLayout& L, int it) {
+  if (j.N > kPendMaxSpots || !j.sp_alt) return false;
+  if (j.compressed && it < j.iterations) return j.defer_ok && !j.shared_e;
+  if (j.mixed || !L.separable) return false;
+  return it <= j.iterations || j.phi != nullptr;
+}
+bool defers(const JobDev& j, const JobLayout& L, int it) {
+  return it <= j.iterations && pend_capable(j, L, it) && pend_capable(j, L, it + 1);
+}
+// 2^-shift / count of pass it's sums, as its tail would scale them
+double pass_inv(const JobDev& j, const JobLayout& L, int it) {
+  const bool sub = j.compressed && it < j.iterations;
+  return sub ? std::ldexp(1.0, -L.plan_sub.shift) * (1.0 / (double)j.m)
+             : std::ldexp(1.0, -L.plan_sep.shift) * (1.0 / (double)j.P);
+}
+// A pending pass it reads the state X_{it-2} that the previous pass used
+// and, when it defers in turn (or is the final hologram), stores X_{it-1},
+// which it formed, for the next.  In a run of pending passes s, s+1, ...
+// (pass s-1 defers without being pending, so X_{s-2} is in the spot records
+// sp, where the setup or a pass's own update left it) pass it reads buffer
+// (it - s) mod 2 and writes the other (0: sp, 1: sp_alt).
+template <typename D>
+void plan_deferral(D& d, const JobDev& j, const JobLayout& L, int it) {
+  const bool df = defers(j, L, it), pd = it >= 2 && defers(j, L, it - 1);
+  if (!df && !pd) return;
+  SpotRec* const buf[2] = {j.sp, j.sp_alt};
+  d.tot_row = it % kAccTotalRows;
+  d.defer = df ? 1 : 0;
+  if (pd) {
+    int s = it;  // the first pending pass of this run
+    while (s - 1 >= 2 && defers(j, L, s - 2)) --s;
+    d.pending = 1;
+    d.prev_row = (it - 1) % kAccTotalRows;
+    d.clear_row = (it + 1) % kAccTotalRows;
+    d.prev_inv = pass_inv(j, L, it - 1);
+    d.st_in = buf[(it - s) % 2];
+    d.st_out = (df || it > j.iterations) ? buf[(it - s + 1) % 2] : nullptr;
+    d.prev_V = j.trace ? j.V + (size_t)(it - 2) * j.N : nullptr;
+  }
+}
+template <typename D>
+void clear_deferral(D& d) {
+  d.defer = d.pending = d.tot_row = d.prev_row = 0;
+  d.clear_row = -1;
+  d.prev_inv = 0.0;
+  d.st_in = nullptr;
+  d.st_out = nullptr;
+  d.prev_V = nullptr;
+}
+}  // namespace
+
 PassDesc iteration_desc(const JobDev& j, const JobLayout& L, int it, int index, int block_begin) {
   const bool sub = j.compressed && it < j.iterations;
   PassDesc d;
@@ -599,24 +656,9 @@ PassDesc iteration_desc(const JobDev& j, const JobLayout& L, int it, int index, 
   d.grab_slot = it;
   d.inv_count = 1.0 / (double)(sub ? j.m : j.P);  // eq. (3): the mean over the set
   d.V = j.V + (j.trace ? (size_t)(it - 1) * j.N : 0);
-  // Deferred updates: compressed passes 1..I-1 in the per-pixel FP32 form
-  // follow one another; each but the last leaves its update to the next.
-  // State X_k (after k updates) lives in buffer k mod 2 (0: sp, 1: sp_alt):
-  // pass it reads X_{it-2} and, when it defers, stores X_{it-1}.
-  if (sub && j.defer_ok && !j.shared_e && j.N <= kPendMaxSpots && j.sp_alt) {
-    SpotRec* const buf[2] = {j.sp, j.sp_alt};
-    d.tot_row = it % kAccTotalRows;
-    d.defer = it + 1 < j.iterations ? 1 : 0;
-    if (it >= 2) {
-      d.pending = 1;
-      d.prev_row = (it - 1) % kAccTotalRows;
-      d.clear_row = (it + 1) % kAccTotalRows;
-      d.prev_inv = std::ldexp(1.0, -L.plan_sub.shift) * (1.0 / (double)j.m);  // as the tail forms it
-      d.st_in = buf[(it - 2) % 2];
-      d.st_out = d.defer ? buf[(it - 1) % 2] : nullptr;
-      d.prev_V = j.trace ? j.V + (size_t)(it - 2) * j.N : nullptr;
-    }
-  }
+  // Deferred updates: consecutive compressed passes, and the last of them
+  // with the separable full-grid pass and the final hologram after it
+  if (sub) plan_deferral(d, j, L, it);
   return d;
 }
 
@@ -690,6 +732,7 @@ void LaunchSet::add_iteration(const JobDev& j, const JobLayout& L, int it, int i
     SepDesc d = sep_desc(j, L, index, sep_blocks);
     d.update = 1;
     d.V = j.V + (j.trace ? (size_t)(it - 1) * j.N : 0);
+    plan_deferral(d, j, L, it);
     sep.push_back(d);
     sep_blocks += d.plan.blocks;
     sep_steps = std::max(sep_steps, j.mx_steps);
@@ -722,6 +765,7 @@ void LaunchSet::add_final(const JobDev& j, const JobLayout& L, int index) {
   if (L.separable) {
     SepDesc d = sep_desc(j, L, index, sep_blocks);
     d.out = j.phi;
+    plan_deferral(d, j, L, j.iterations + 1);
     sep.push_back(d);
     sep_blocks += d.plan.blocks;
     sep_steps = std::max(sep_steps, j.mx_steps);
@@ -875,12 +919,19 @@ hg_status Batch::build(const JobSpec* specs, int count, const TuneParams& tp,
       for (int r = 0; r < passes; ++r) {
         // a chained launch hands the state over inside the launch
         PassDesc d = rounds_[r].pass.at(0);
-        d.defer = d.pending = d.tot_row = d.prev_row = 0;
-        d.clear_row = -1;
-        d.st_in = nullptr;
-        d.st_out = nullptr;
-        d.prev_V = nullptr;
+        clear_deferral(d);
         chain_descs_.push_back(d);
+      }
+      // and the passes after it update in their own tails (the chain's
+      // last pass leaves the state in the spot records); so does the last
+      // compressed pass of the one-launch-per-pass form that stands in when
+      // the cooperative launch is refused
+      if ((size_t)passes < rounds_.size())
+        for (SepDesc& d : rounds_[passes].sep) clear_deferral(d);
+      for (SepDesc& d : final_.sep) clear_deferral(d);
+      for (PassDesc& d : rounds_[passes - 1].pass) {
+        d.defer = 0;
+        d.st_out = nullptr;
       }
       chain_rounds_ = passes;
       chain_blocks_ = layouts_[0].plan_sub.blocks;
