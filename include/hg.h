@@ -120,10 +120,12 @@ typedef struct hg_spots {
 /* Arithmetic of the iteration kernels (low bits of hg_params.flags and of
  * the flags argument of the single-step calls). */
 #define HG_PREC_FP32 0u   /* FP32 phases, sincos and sums                  */
-#define HG_PREC_MIXED 1u  /* back-propagation as FP16 complex products
+#define HG_PREC_MIXED 1u  /* back-propagation as FP16 products
                              accumulated in FP32 (compressed passes: per
-                             pixel, exact sums; full-grid passes: FP16
-                             matrix cores, compensated FP32 sums)          */
+                             pixel, the cosines, sines and amplitudes of
+                             two spots per FP16 dot product, exact sums;
+                             full-grid passes: FP16 matrix cores,
+                             compensated FP32 sums)                        */
 #define HG_PREC_MASK 0xffu
 /* hg_params.flags: the four hg_spots arrays are device pointers (already
  * in HBM) instead of host pointers.  Their values are then checked on the

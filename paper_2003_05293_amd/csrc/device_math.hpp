@@ -97,11 +97,6 @@ __device__ __forceinline__ h2v_t to_h2(float lo, float hi) {
 __device__ __forceinline__ uint32_t h2_bits(float lo, float hi) {
   return __builtin_bit_cast(uint32_t, to_h2(lo, hi));
 }
-// The two FP16 pairs of a complex coefficient C for the products C E as
-// dot products with E = (Er, Ei): (Cr, -Ci) gives Re, (Ci, Cr) gives Im.
-__device__ __forceinline__ uint2 coef_pairs(float2 C) {
-  return make_uint2(h2_bits(C.x, -C.y), h2_bits(C.y, C.x));
-}
 
 __device__ __forceinline__ void sincos_turns(float t, float& s, float& c) {
   const float r = __builtin_amdgcn_fractf(t);

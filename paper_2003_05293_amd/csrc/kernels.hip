@@ -124,64 +124,74 @@ __device__ __forceinline__ float2 backprop_field_lds(const SpotRec* recs, int n0
   return make_float2(sr, si);
 }
 
-// Mixed-precision back-propagation (eq. 1): the phase in FP32 turns and
-// its exponential E_n(p) from v_sin/v_cos, both rounded to FP16 and packed
-// with the complex coefficient C_n = A_n e^{i theta_n} (FP16); each complex
-// product C_n E_n(p) is two FP16 dot products accumulated in FP32
-// (v_dot2_f32_f16): re = (Cr, -Ci).(Er, Ei), im = (Ci, Cr).(Er, Ei).
-__device__ __forceinline__ void mx_term(float t, uint2 cp, float& sr, float& si) {
-  float sn, cs;
-  sincos_turns(t, sn, cs);
-  const h2v_t e = to_h2(cs, sn);
-  sr = __builtin_amdgcn_fdot2(e, __builtin_bit_cast(h2v_t, cp.x), sr, false);
-  si = __builtin_amdgcn_fdot2(e, __builtin_bit_cast(h2v_t, cp.y), si, false);
+// Mixed-precision back-propagation (eq. 1): the phase of each spot in FP32
+// turns with theta folded in, t_n = phi_n(p) / 2 pi + theta_n, its cosine
+// and sine from v_sin/v_cos; the two spots of a pair have their cosines,
+// their sines and their amplitudes A_n rounded to FP16 and packed, and one
+// FP16 dot product accumulated in FP32 (v_dot2_f32_f16) adds each part of
+// the pair's terms A_n e^{i 2 pi t_n}: re += (cos_1, cos_2).(A_1, A_2),
+// im += (sin_1, sin_2).(A_1, A_2).  A spot left without a partner is paired
+// with a zero amplitude.
+__device__ __forceinline__ void mx_pair(float t1, float a1, float t2, float a2, float& sr,
+                                        float& si) {
+  float sn1, cs1, sn2, cs2;
+  sincos_turns(t1, sn1, cs1);
+  sincos_turns(t2, sn2, cs2);
+  const h2v_t a = to_h2(a1, a2);
+  sr = __builtin_amdgcn_fdot2(to_h2(cs1, cs2), a, sr, false);
+  si = __builtin_amdgcn_fdot2(to_h2(sn1, sn2), a, si, false);
 }
-// Records and coefficients by scalar loads, four spots per wait.
-__device__ __forceinline__ float2 backprop_field_mx(const SpotRec* spg, const float2* cfg, int n0,
-                                                    int n1, const PixCoord& c) {
+__device__ __forceinline__ float turns_of(float cx, float cy, float cz, float th,
+                                          const PixCoord& c) {
+  return fmaf(cx, c.Lx, fmaf(cy, c.Ly, fmaf(cz, c.Q, th)));
+}
+// Records by scalar loads, four spots per wait.
+__device__ __forceinline__ float2 backprop_field_mx(const SpotRec* spg, int n0, int n1,
+                                                    const PixCoord& c) {
   const HG_CONST SpotRec* sp = as_const(spg);
-  const HG_CONST float* cf = as_const(reinterpret_cast<const float*>(cfg));  // (re, im) pairs
   float sr = 0.f, si = 0.f;
   int n = n0;
   for (; n + 3 < n1; n += 4) {
-    float scx[4], scy[4], scz[4], scr[4], sci[4];
+    float t[4], A[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      scx[k] = sp[n + k].cx;
-      scy[k] = sp[n + k].cy;
-      scz[k] = sp[n + k].cz;
-      scr[k] = cf[2 * (n + k)];
-      sci[k] = cf[2 * (n + k) + 1];
+      t[k] = turns_of(sp[n + k].cx, sp[n + k].cy, sp[n + k].cz, sp[n + k].th, c);
+      A[k] = sp[n + k].A;
     }
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      mx_term(fmaf(scx[k], c.Lx, fmaf(scy[k], c.Ly, scz[k] * c.Q)),
-              coef_pairs(make_float2(scr[k], sci[k])), sr, si);
+    mx_pair(t[0], A[0], t[1], A[1], sr, si);
+    mx_pair(t[2], A[2], t[3], A[3], sr, si);
   }
-  for (; n < n1; ++n)
-    mx_term(fmaf(sp[n].cx, c.Lx, fmaf(sp[n].cy, c.Ly, sp[n].cz * c.Q)),
-            coef_pairs(make_float2(cf[2 * n], cf[2 * n + 1])), sr, si);
+  for (; n + 1 < n1; n += 2)
+    mx_pair(turns_of(sp[n].cx, sp[n].cy, sp[n].cz, sp[n].th, c), sp[n].A,
+            turns_of(sp[n + 1].cx, sp[n + 1].cy, sp[n + 1].cz, sp[n + 1].th, c), sp[n + 1].A,
+            sr, si);
+  if (n < n1)
+    mx_pair(turns_of(sp[n].cx, sp[n].cy, sp[n].cz, sp[n].th, c), sp[n].A, 0.f, 0.f, sr, si);
   return make_float2(sr, si);
 }
-// Records and coefficient pairs from LDS (a pending pass's updated state).
-__device__ __forceinline__ float2 backprop_field_mx_lds(const SpotRec* recs, const uint2* cpl,
-                                                        int n0, int n1, const PixCoord& c) {
+// Records from LDS (a pending pass's updated state).
+__device__ __forceinline__ float2 backprop_field_mx_lds(const SpotRec* recs, int n0, int n1,
+                                                        const PixCoord& c) {
   float sr = 0.f, si = 0.f;
   int n = n0;
   for (; n + 3 < n1; n += 4) {
-    float4 q[4];
-    uint2 cp[4];
+    float t[4], A[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      q[k] = *reinterpret_cast<const float4*>(&recs[n + k].cx);
-      cp[k] = cpl[n + k];
+      const float4 q = *reinterpret_cast<const float4*>(&recs[n + k].cx);
+      t[k] = turns_of(q.x, q.y, q.z, q.w, c);
+      A[k] = recs[n + k].A;
     }
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      mx_term(fmaf(q[k].x, c.Lx, fmaf(q[k].y, c.Ly, q[k].z * c.Q)), cp[k], sr, si);
+    mx_pair(t[0], A[0], t[1], A[1], sr, si);
+    mx_pair(t[2], A[2], t[3], A[3], sr, si);
   }
-  for (; n < n1; ++n)
-    mx_term(fmaf(recs[n].cx, c.Lx, fmaf(recs[n].cy, c.Ly, recs[n].cz * c.Q)), cpl[n], sr, si);
+  for (; n + 1 < n1; n += 2)
+    mx_pair(turns_of(recs[n].cx, recs[n].cy, recs[n].cz, recs[n].th, c), recs[n].A,
+            turns_of(recs[n + 1].cx, recs[n + 1].cy, recs[n + 1].cz, recs[n + 1].th, c),
+            recs[n + 1].A, sr, si);
+  if (n < n1)
+    mx_pair(turns_of(recs[n].cx, recs[n].cy, recs[n].cz, recs[n].th, c), recs[n].A, 0.f, 0.f,
+            sr, si);
   return make_float2(sr, si);
 }
 
@@ -665,8 +675,8 @@ __device__ void pass_block(const PassCtx& a, unsigned* grab, bool has_pre = fals
         PixCoord c{0.f, 0.f, 0.f, 0};
         if (valid) c = pixel_coord(p, a.W, a.H);
         if constexpr (MX)
-          sw[wave][lane] = PEND ? backprop_field_mx_lds(a.recs, a.cpl, n_lo, n_hi, c)
-                                : backprop_field_mx(sp, a.coef, n_lo, n_hi, c);
+          sw[wave][lane] = PEND ? backprop_field_mx_lds(a.recs, n_lo, n_hi, c)
+                                : backprop_field_mx(sp, n_lo, n_hi, c);
         else
           sw[wave][lane] = lds_recs ? backprop_field_lds(a.recs, n_lo, n_hi, c)
                                     : backprop_field(sp, n_lo, n_hi, c);
@@ -982,7 +992,6 @@ __device__ __forceinline__ void pass_ctx(PassCtx& a, const JobDev& jb, const Pas
 template <bool MX>
 __device__ __forceinline__ void pending_pass(PassCtx& a, const JobDev& jb, const PassDesc& d) {
   __shared__ SpotRec recs[kPendMaxSpots];
-  __shared__ uint2 cpl[MX ? kPendMaxSpots : 1];
   bool has_pre = false;
   int32_t pre_p = 0;
   if (!d.from_phi && a.lb < a.plan.tiles) {
@@ -990,9 +999,8 @@ __device__ __forceinline__ void pending_pass(PassCtx& a, const JobDev& jb, const
     pre_p = q < a.ps.count ? pixel_of(a.ps, q) : 0;
     has_pre = true;
   }
-  apply_pending(jb, d, a.lb == 0, recs, MX ? cpl : nullptr);
+  apply_pending(jb, d, a.lb == 0, recs);
   a.recs = recs;
-  a.cpl = cpl;
   if (!d.defer) a.pend_row = d.prev_row;
   pass_block<1, false, true, MX>(a, jb.grab + d.grab_slot, has_pre, pre_p);
 }
@@ -1032,9 +1040,9 @@ __global__ __launch_bounds__(kBlock, MAXU > 4 ? 2 : (MAXE > 16 ? 6 : 8)) void k_
 }
 
 // Compressed passes of mixed-precision jobs: the per-pixel pass with the
-// back-propagation in FP16 complex products accumulated in FP32
-// (backprop_field_mx); forward terms, sums, hand-off and update as in the
-// FP32 form.
+// back-propagation terms as FP16 products accumulated in FP32, two spots per
+// dot product (backprop_field_mx); forward terms, sums, hand-off and update
+// as in the FP32 form.
 template <int MAXU>
 __global__ __launch_bounds__(kBlock, MAXU > 4 ? 2 : 8) void k_pass_mx(const JobDev* __restrict__ jobs,
                                                                     const PassDesc* __restrict__ descs,

@@ -276,8 +276,8 @@ __host__ __device__ int pass_e_width(int N);
 void launch_pass_batch(const JobDev* jobs, const PassDesc* descs, int ndesc, int total_blocks,
                        int max_units, int e_width, hipStream_t s);
 // Compressed passes of mixed-precision jobs (the per-pixel pass with FP16
-// complex back-propagation products accumulated in FP32); descs and units
-// as for launch_pass_batch.
+// back-propagation products accumulated in FP32); descs and units as for
+// launch_pass_batch.
 void launch_pass_mx(const JobDev* jobs, const PassDesc* descs, int ndesc, int total_blocks,
                     int max_units, hipStream_t s);
 void launch_backprop_batch(const JobDev* jobs, const BackDesc* descs, int ndesc,
@@ -362,6 +362,18 @@ struct MxDesc {
   float inv_count;
   double2* V;           // [N] spot fields of the pass (FP32 values widened)
   float* out;           // final hologram (kMxFinal)
+  // Deferred updates, as in PassDesc: a pending pass applies the previous
+  // (compressed) pass's update at its start, into LDS (records and C_n).
+  // These passes do not defer their own.
+  int32_t defer = 0;
+  int32_t pending = 0;
+  int32_t tot_row = 0;
+  int32_t prev_row = 0;
+  int32_t clear_row = -1;
+  double prev_inv = 0.0;
+  const SpotRec* st_in = nullptr;
+  SpotRec* st_out = nullptr;
+  double2* prev_V = nullptr;
 };
 PassPlan plan_mx(int W, int H);
 // (FP16 / FP32 tables built by the prologue from FP64 phases.)

@@ -21,6 +21,7 @@
 #include "device_math.hpp"
 #include "kernels.hpp"
 #include "operand_layout.hpp"
+#include "pass_tail.hpp"
 
 namespace hg {
 
@@ -100,8 +101,9 @@ __device__ __forceinline__ float4 combine_slices(const float4* part, int Npad, i
 // last group adds those (group order, compensated), scales by 1 / |Omega|
 // and, when asked, applies eqs. (4)-(6) in FP32.  The same last-arriver
 // hand-off as the FP32 passes; thread (c, s) takes spot lane c of Npad and
-// slice s of S.
-__device__ void mx_tail(const JobDev& jb, const MxDesc& d, int lb) {
+// slice s of S.  recs: the state the pass used, when it applied a pending
+// update into LDS (else the spot records).
+__device__ void mx_tail(const JobDev& jb, const MxDesc& d, int lb, const SpotRec* recs) {
   __shared__ int last;
   __shared__ float wsum[kWaves];
   __shared__ float4 part[kBlock];
@@ -135,9 +137,15 @@ __device__ void mx_tail(const JobDev& jb, const MxDesc& d, int lb) {
 #pragma unroll
   for (int k = 0; k < kRecWords; ++k) pre[k] = 0.f;
   if (d.update && s == 0 && c < N) {
-    const HG_GLOBAL float* q = as_global(reinterpret_cast<const float*>(jb.sp + c));
+    if (recs) {
+      const float* q = reinterpret_cast<const float*>(recs + c);
 #pragma unroll
-    for (int k = 0; k < kRecWords; ++k) pre[k] = q[k];
+      for (int k = 0; k < kRecWords; ++k) pre[k] = q[k];
+    } else {
+      const HG_GLOBAL float* q = as_global(reinterpret_cast<const float*>(jb.sp + c));
+#pragma unroll
+      for (int k = 0; k < kRecWords; ++k) pre[k] = q[k];
+    }
   }
   const ColumnSrc gsrc = column_src(gsum, d.plan.ngroups, N);
   float msum = 0.f;
@@ -156,6 +164,13 @@ __device__ void mx_tail(const JobDev& jb, const MxDesc& d, int lb) {
   }
   // the counters are ready for the next pass (kernel end orders these writes)
   for (int k = threadIdx.x; k <= d.plan.ngroups; k += kBlock) jb.counters[k * kCounterStride] = 0u;
+  // the previous pass's total set, which every block has read, is cleared
+  if (d.pending) {
+    HG_GLOBAL unsigned long long* q =
+        as_global_mut(jb.acc + (int64_t)d.prev_row * kAccReplicas * N * kAccSpotWords);
+    for (int k = threadIdx.x; k < kAccReplicas * N * kAccSpotWords; k += kBlock)
+      __hip_atomic_store(q + k, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   if (!d.update) return;
   for (int off = 32; off > 0; off >>= 1) msum += __shfl_xor(msum, off);
   if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = msum;
@@ -173,6 +188,10 @@ __device__ void mx_tail(const JobDev& jb, const MxDesc& d, int lb) {
     if (n == c) {
 #pragma unroll
       for (int k = 0; k < kRecWords; ++k) f[k] = pre[k];
+    } else if (recs) {
+      const float* q = reinterpret_cast<const float*>(recs + n);
+#pragma unroll
+      for (int k = 0; k < kRecWords; ++k) f[k] = q[k];
     } else {
       const HG_GLOBAL float* q = as_global(reinterpret_cast<const float*>(jb.sp + n));
 #pragma unroll
@@ -183,6 +202,7 @@ __device__ void mx_tail(const JobDev& jb, const MxDesc& d, int lb) {
     const float w = r.w * (mean / mag);
     if (!(mag > 0.f) || !isfinite(w)) {
       jb.status[0] = 4;  // HG_ENUMERIC
+      if (recs) jb.sp[n] = r;  // the state this pass used
       continue;
     }
     r.w = w;
@@ -247,6 +267,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_mx_pass(const JobDev* __restrict_
                                                     const MxDesc* __restrict__ descs, int ndesc) {
   extern __shared__ float2 cs[];                     // [Np] C_n = A_n e^{i theta_n}
   __shared__ uint32_t us[kWaves][16][kMxTileW + 4];  // u of each wave's rows (half pairs)
+  __shared__ SpotRec recs[kPendMaxSpots];            // pending: the updated records
   __shared__ float2 red[kWaves][64];
   const int di = find_desc(descs, ndesc, blockIdx.x);
   const MxDesc& d = descs[di];
@@ -264,13 +285,19 @@ __global__ __launch_bounds__(kBlock, 3) void k_mx_pass(const JobDev* __restrict_
   for (int t = 0; t < kMxCB; ++t) sr[t] = si[t] = f4_t{0.f, 0.f, 0.f, 0.f};
 
   if (MODE != kMxFromPhi) {
-    for (int n = threadIdx.x; n < 16 * S16; n += kBlock) {
-      float2 c = make_float2(0.f, 0.f);
-      if (n < N) {
-        const HG_GLOBAL float* f = as_global(reinterpret_cast<const float*>(jb.coef + n));
-        c = make_float2(f[0], f[1]);
+    if (d.pending) {
+      // the previous pass's deferred update, C_n formed as its tail would
+      apply_pending(jb, d, lb == 0, recs, cs);
+      for (int n = N + threadIdx.x; n < 16 * S16; n += kBlock) cs[n] = make_float2(0.f, 0.f);
+    } else {
+      for (int n = threadIdx.x; n < 16 * S16; n += kBlock) {
+        float2 c = make_float2(0.f, 0.f);
+        if (n < N) {
+          const HG_GLOBAL float* f = as_global(reinterpret_cast<const float*>(jb.coef + n));
+          c = make_float2(f[0], f[1]);
+        }
+        cs[n] = c;
       }
-      cs[n] = c;
     }
     __syncthreads();
     // S = B F in groups of kMxSteps K-steps, the next group's operands
@@ -415,7 +442,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_mx_pass(const JobDev* __restrict_
     }
     __syncthreads();
   }
-  mx_tail(jb, d, lb);
+  mx_tail(jb, d, lb, d.pending ? recs : nullptr);
 }
 
 }  // namespace

@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void k_sep_pass(const JobDev* __restrict__ 
     if (G > 1) bp_load(Q, jb, rb, tx, kSepSteps, KS, lane);
     if (d.pending) {
       // the previous pass's deferred update, C_n formed as its tail would
-      apply_pending(jb, d, lb == 0, recs, nullptr, cs);
+      apply_pending(jb, d, lb == 0, recs, cs);
       for (int n = N + threadIdx.x; n < 16 * S16; n += kBlock) cs[n] = make_float2(0.f, 0.f);
     } else {
       for (int n = threadIdx.x; n < 16 * S16; n += kBlock) {

@@ -45,7 +45,6 @@ struct PassCtx {
   // chained launches: the generation word to publish after the update
   int chain = 0;
   const SpotRec* recs = nullptr;
-  const uint2* cpl = nullptr;  // mixed pending passes: FP16 pairs of C_n (LDS)
   unsigned* gen = nullptr;
   unsigned gen_next = 0;
 };
@@ -194,14 +193,14 @@ __device__ void tail_final(const PassCtx& a, float2* vs) {
 // (integer sums: the total that a hand-off would have formed), applies that
 // pass's update to the state before it (d.st_in) and keeps the result in
 // recs (LDS), with the arithmetic and the mean of tail_final (one spot per
-// thread); with cl or cpl, also C_n = A_n e^{i theta_n} in FP32 or as FP16
-// pairs (LDS), formed as tail_final forms it.  Block 0 (lead) also clears
+// thread); with cl, also C_n = A_n e^{i theta_n} in FP32 (LDS), formed as
+// tail_final forms it.  Block 0 (lead) also clears
 // the total set two passes back, stores the state for the next pass when
 // this pass defers in turn (the final state, in the final hologram), the
 // previous V when traced, and the status.  N <= kPendMaxSpots <= kBlock.
 // D: PassDesc or SepDesc.
 template <typename D>
-__device__ void apply_pending(const JobDev& jb, const D& d, bool lead, SpotRec* recs, uint2* cpl,
+__device__ void apply_pending(const JobDev& jb, const D& d, bool lead, SpotRec* recs,
                               float2* cl = nullptr) {
   const int N = jb.N;
   const int n = threadIdx.x;
@@ -247,7 +246,7 @@ __device__ void apply_pending(const JobDev& jb, const D& d, bool lead, SpotRec* 
     const float mag = mag32(v);
     const bool ok = update_rec(r, v, mag, mean);
     if (!ok && lead) jb.status[0] = 4;  // HG_ENUMERIC
-    if (cpl || cl) {  // C_n = A_n e^{i theta_n}
+    if (cl) {  // C_n = A_n e^{i theta_n}
       float2 C;
       if (ok) {
         const float Am = r.A / mag;  // as tail_final forms it
@@ -257,8 +256,7 @@ __device__ void apply_pending(const JobDev& jb, const D& d, bool lead, SpotRec* 
         sincos_turns(r.th, sn, cs);
         C = make_float2(r.A * cs, r.A * sn);
       }
-      if (cpl) cpl[n] = coef_pairs(C);  // mixed precision: FP16 pairs
-      if (cl) cl[n] = C;
+      cl[n] = C;
     }
     __builtin_memcpy(f, &r, sizeof(r));
     float* dst = reinterpret_cast<float*>(recs + n);

@@ -590,11 +590,16 @@ namespace {
 bool pend_capable(const JobDev& j, const JobLayout& L, int it) {
   if (j.N > kPendMaxSpots || !j.sp_alt) return false;
   if (j.compressed && it < j.iterations) return j.defer_ok && !j.shared_e;
-  if (j.mixed || !L.separable) return false;
+  // the mixed full-grid pass takes a pending update but updates in its own
+  // tail (its sums are compensated FP32, not the exact sets)
+  if (j.mixed) return it == j.iterations;
+  if (!L.separable) return false;
   return it <= j.iterations || j.phi != nullptr;
 }
+bool defer_capable(const JobDev& j, int it) { return !(j.mixed && it >= j.iterations); }
 bool defers(const JobDev& j, const JobLayout& L, int it) {
-  return it <= j.iterations && pend_capable(j, L, it) && pend_capable(j, L, it + 1);
+  return it <= j.iterations && defer_capable(j, it) && pend_capable(j, L, it) &&
+         pend_capable(j, L, it + 1);
 }
 // 2^-shift / count of pass it's sums, as its tail would scale them
 double pass_inv(const JobDev& j, const JobLayout& L, int it) {
@@ -723,6 +728,7 @@ void LaunchSet::add_iteration(const JobDev& j, const JobLayout& L, int it, int i
     mx_full += 1;
     d.update = 1;
     d.V = j.V + (j.trace ? (size_t)(it - 1) * j.N : 0);
+    plan_deferral(d, j, L, it);
     mx.push_back(d);
     mx_blocks += d.plan.blocks;
     mx_steps = std::max(mx_steps, j.mx_steps);
