@@ -590,8 +590,8 @@ __host__ __device__ inline LaneMap lane_map(int N) {
 // and the block that completes the pass publishes the generation word after
 // the update.  PEND: the records come from LDS too (a.recs: the state after
 // the previous pass's deferred update), and the first pixel index may come
-// prefetched as in CHAIN.  With a.defer the pass ends after
-// its groups have added into its total row.
+// prefetched as in CHAIN.  With a.defer the tiles add into the rows of the
+// pass's total set and the pass ends there (no counting).
 template <int MAXU, bool CHAIN = false, bool PEND = false, bool MX = false>
 __device__ void pass_block(const PassCtx& a, unsigned* grab, bool has_pre = false,
                            int32_t pre_p = 0) {
