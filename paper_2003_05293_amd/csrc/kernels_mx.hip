@@ -14,7 +14,8 @@
 // Precision: F and B are rounded to FP16 (relative error <= 2^-11 per
 // operand), products and sums are FP32, partials are added across tiles with
 // compensated (Neumaier) FP32 sums, and the weight update is FP32.  FP64 is
-// used only for the factor tables (setup).
+// used only for the factor tables (setup).  The full-grid pass after the
+// compressed passes applies the last one's deferred update at its start.
 #include <math.h>
 
 #include "device_common.hpp"

@@ -10,7 +10,9 @@
 // complex product is a real one with K = 2 Np, the real and imaginary parts
 // of each spot (or pixel column) interleaved along K.  The factor tables are
 // evaluated once per hologram in FP64 (the spots do not move), so the
-// phases are exact to FP32 rounding; C_n comes from the state.
+// phases are exact to FP32 rounding; C_n comes from the state, or from the
+// previous pass's deferred update, which a pending pass (and the final
+// hologram) applies at its start.
 #include <math.h>
 
 #include "device_common.hpp"
