@@ -15,7 +15,9 @@
 // operand), products and sums are FP32, partials are added across tiles with
 // compensated (Neumaier) FP32 sums, and the weight update is FP32.  FP64 is
 // used only for the factor tables (setup).  The full-grid pass after the
-// compressed passes applies the last one's deferred update at its start.
+// compressed passes applies the last one's deferred update at its start and
+// defers its own to the final hologram, adding its sums exactly (64-bit
+// fixed point) into its total set.
 #include <math.h>
 
 #include "device_common.hpp"
@@ -438,11 +440,17 @@ __global__ __launch_bounds__(kBlock, 3) void k_mx_pass(const JobDev* __restrict_
           v.x += red[w][threadIdx.x].x;
           v.y += red[w][threadIdx.x].y;
         }
-        store_dev(jb.partial + (int64_t)lb * N + n, v);
+        if (d.defer)
+          acc_add(jb.acc, N, d.plan.shift, d.tot_row * kAccReplicas + lb % kAccReplicas, n, v);
+        else
+          store_dev(jb.partial + (int64_t)lb * N + n, v);
       }
     }
     __syncthreads();
   }
+  // a deferring pass is complete when this launch ends (the final hologram
+  // applies its update)
+  if (d.defer) return;
   mx_tail(jb, d, lb, d.pending ? recs : nullptr);
 }
 
@@ -452,7 +460,9 @@ PassPlan plan_mx(int W, int H) {
   PassPlan p;
   p.tiles = ceil_div(W, kMxTileW) * ceil_div(H, kMxTile);
   p.sub = 1;
-  p.shift = 0;  // the mixed passes use compensated FP32 sums
+  // compensated FP32 sums, except in a pass that defers its update: exact
+  // fixed-point sums into its total set (every term has magnitude <= 1)
+  p.shift = sum_shift((int64_t)W * H);
   p.blocks = p.tiles;
   int gs = 1;
   while (gs * gs < p.blocks) ++gs;

@@ -590,13 +590,13 @@ namespace {
 bool pend_capable(const JobDev& j, const JobLayout& L, int it) {
   if (j.N > kPendMaxSpots || !j.sp_alt) return false;
   if (j.compressed && it < j.iterations) return j.defer_ok && !j.shared_e;
-  // the mixed full-grid pass takes a pending update but updates in its own
-  // tail (its sums are compensated FP32, not the exact sets)
-  if (j.mixed) return it == j.iterations;
+  // mixed CS-WGS: the full-grid pass and the final hologram (the exact sums
+  // of a mixed job are kept only with compressed passes)
+  if (j.mixed) return j.compressed && (it == j.iterations || (it > j.iterations && j.phi));
   if (!L.separable) return false;
   return it <= j.iterations || j.phi != nullptr;
 }
-bool defer_capable(const JobDev& j, int it) { return !(j.mixed && it >= j.iterations); }
+bool defer_capable(const JobDev& j, int it) { return !(j.mixed && it > j.iterations); }
 bool defers(const JobDev& j, const JobLayout& L, int it) {
   return it <= j.iterations && defer_capable(j, it) && pend_capable(j, L, it) &&
          pend_capable(j, L, it + 1);
@@ -604,8 +604,8 @@ bool defers(const JobDev& j, const JobLayout& L, int it) {
 // 2^-shift / count of pass it's sums, as its tail would scale them
 double pass_inv(const JobDev& j, const JobLayout& L, int it) {
   const bool sub = j.compressed && it < j.iterations;
-  return sub ? std::ldexp(1.0, -L.plan_sub.shift) * (1.0 / (double)j.m)
-             : std::ldexp(1.0, -L.plan_sep.shift) * (1.0 / (double)j.P);
+  const int shift = sub ? L.plan_sub.shift : j.mixed ? L.plan_mx.shift : L.plan_sep.shift;
+  return std::ldexp(1.0, -shift) * (1.0 / (double)(sub ? j.m : j.P));
 }
 // A pending pass it reads the state X_{it-2} that the previous pass used
 // and, when it defers in turn (or is the final hologram), stores X_{it-1},
@@ -762,6 +762,7 @@ void LaunchSet::add_final(const JobDev& j, const JobLayout& L, int index) {
   if (j.mixed) {
     MxDesc d = mx_desc(j, L, index, mx_blocks);
     d.out = j.phi;
+    plan_deferral(d, j, L, j.iterations + 1);
     mx.push_back(d);
     mx_blocks += d.plan.blocks;
     mx_steps = std::max(mx_steps, j.mx_steps);
