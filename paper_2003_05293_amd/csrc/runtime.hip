@@ -585,8 +585,9 @@ namespace {
 // Deferred updates.  Pass it of job j (1..I; I + 1 is the final hologram)
 // can apply the previous pass's update at its start, and so let that pass
 // stop after its sums: the per-pixel compressed passes of one spot unit per
-// wave (FP32 or mixed), and the FP32 separable full-grid passes and final
-// hologram, for N <= kPendMaxSpots.
+// wave (FP32 or mixed), the FP32 separable full-grid passes and final
+// hologram, and the mixed full-grid pass and final hologram of a CS-WGS
+// job, for N <= kPendMaxSpots.
 bool pend_capable(const JobDev& j, const JobLayout& L, int it) {
   if (j.N > kPendMaxSpots || !j.sp_alt) return false;
   if (j.compressed && it < j.iterations) return j.defer_ok && !j.shared_e;
@@ -596,10 +597,8 @@ bool pend_capable(const JobDev& j, const JobLayout& L, int it) {
   if (!L.separable) return false;
   return it <= j.iterations || j.phi != nullptr;
 }
-bool defer_capable(const JobDev& j, int it) { return !(j.mixed && it > j.iterations); }
 bool defers(const JobDev& j, const JobLayout& L, int it) {
-  return it <= j.iterations && defer_capable(j, it) && pend_capable(j, L, it) &&
-         pend_capable(j, L, it + 1);
+  return it <= j.iterations && pend_capable(j, L, it) && pend_capable(j, L, it + 1);
 }
 // 2^-shift / count of pass it's sums, as its tail would scale them
 double pass_inv(const JobDev& j, const JobLayout& L, int it) {
